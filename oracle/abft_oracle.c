@@ -1,0 +1,686 @@
+/*
+ * CPU oracle for ABFT-protected stencil sweeps
+ * (Cavelan & Ciorba, "Algorithm-Based Fault Tolerance for Parallel Stencil Computations").
+ *
+ * TEST INFRASTRUCTURE ONLY: the reference the GPU library is checked against.  Only the tests,
+ * the smoke check and the benchmark's CPU-baseline leg may load it.  It shares no code with
+ * the GPU library.  Plain loops, no blocking or fusion; each function follows one step of the
+ * paper and says which.  Floating point is double (fp64) throughout; grid values are stored in
+ * the problem's storage type (float or double) exactly as the method stores them.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math: the compensated sums
+ * rely on IEEE rounding).
+ *
+ * Parity pins: every function here is pinned by the CPU tests (library correlate for the sweep,
+ * exactly rounded sums for the checksums, exact rational arithmetic for Theorem 1, closed forms
+ * for whole runs, the paper's detectable-bit result for detection, rollback equality for the
+ * offline mode).  No function is "parity unpinned".
+ */
+#include "abft_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------------------------
+ * Storage access.  Values are read into double and written back rounded to the storage type.
+ * ------------------------------------------------------------------------------------------ */
+static double ld(int dtype, const void* u, int64_t i)
+{
+    return dtype == ORC_F32 ? (double)((const float*)u)[i] : ((const double*)u)[i];
+}
+
+static void st(int dtype, void* u, int64_t i, double v)
+{
+    if (dtype == ORC_F32)
+        ((float*)u)[i] = (float)v;
+    else
+        ((double*)u)[i] = v;
+}
+
+static double round_to(int dtype, double v)
+{
+    return dtype == ORC_F32 ? (double)(float)v : v;
+}
+
+static size_t elem_size(int dtype) { return dtype == ORC_F32 ? 4 : 8; }
+
+static int64_t idx(const orc_problem* p, int64_t x, int64_t y, int64_t z)
+{
+    return x + (int64_t)p->nx * (y + (int64_t)p->ny * z);
+}
+
+/* Boundary rules (Section 3.3, "Dealing with Boundary Conditions"): map one coordinate onto
+ * [0, n).  Clamp repeats the edge point (the sweep listing of Section 3.2 uses the centre for
+ * a missing neighbour), periodic wraps, and constant returns -1: the point is a ghost whose
+ * value is the constant (zero gives the "empty" boundary). */
+static int64_t map_coord(int bc, int64_t c, int64_t n)
+{
+    if (c >= 0 && c < n) return c;
+    if (bc == ORC_BC_CLAMP) return c < 0 ? 0 : n - 1;
+    if (bc == ORC_BC_PERIODIC) {
+        int64_t m = c % n;
+        return m < 0 ? m + n : m;
+    }
+    return -1;
+}
+
+/* G(u, x, y, z): the ghost-extended grid. */
+static double ghost(const orc_problem* p, const void* u, int64_t x, int64_t y, int64_t z)
+{
+    int64_t mx = map_coord(p->bc, x, p->nx);
+    int64_t my = map_coord(p->bc, y, p->ny);
+    int64_t mz = map_coord(p->bc, z, p->nz);
+    if (mx < 0 || my < 0 || mz < 0) return round_to(p->dtype, p->bc_value);
+    return ld(p->dtype, u, idx(p, mx, my, mz));
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Compensated summation (Neumaier's improvement of Kahan summation).  Used for every checksum
+ * so that the oracle's sums are the exact sums to within a few units of double rounding.
+ * Non-finite partial sums fall back to the plain sum so that Inf stays Inf.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct { double s, c; } csum;
+
+static void cs_add(csum* a, double v)
+{
+    double t = a->s + v;
+    if (isfinite(t)) {
+        if (fabs(a->s) >= fabs(v))
+            a->c += (a->s - t) + v;
+        else
+            a->c += (v - t) + a->s;
+    }
+    a->s = t;
+}
+
+static double cs_val(csum a) { return isfinite(a.s) ? a.s + a.c : a.s; }
+
+/* ------------------------------------------------------------------------------------------ */
+int orc_validate(const orc_problem* p)
+{
+    if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
+    if (p->dtype != ORC_F32 && p->dtype != ORC_F64) return -1;
+    if (p->bc < ORC_BC_CLAMP || p->bc > ORC_BC_CONSTANT) return -1;
+    if (p->ntaps < 0 || (p->ntaps > 0 && !p->taps)) return -1;
+    for (int k = 0; k < p->ntaps; k++) {
+        /* Theorem 1's boundary terms need the shift to stay within one line length. */
+        if (abs(p->taps[k].dx) > p->nx || abs(p->taps[k].dy) > p->ny ||
+            abs(p->taps[k].dz) > p->nz)
+            return -2;
+    }
+    return 0;
+}
+
+static double* rounded_weights(const orc_problem* p)
+{
+    double* w = (double*)malloc(sizeof(double) * (size_t)(p->ntaps > 0 ? p->ntaps : 1));
+    for (int k = 0; k < p->ntaps; k++) w[k] = round_to(p->dtype, p->taps[k].w);
+    return w;
+}
+
+/* Eq.(1), Section 3.1: out-of-place sweep. */
+void orc_sweep(const orc_problem* p, const void* C, const void* uin, void* uout)
+{
+    double* w = rounded_weights(p);
+    const double cs = round_to(p->dtype, p->c_scalar);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < p->nz; z++)
+        for (int64_t y = 0; y < p->ny; y++)
+            for (int64_t x = 0; x < p->nx; x++) {
+                const int64_t i = idx(p, x, y, z);
+                double acc = C ? ld(p->dtype, C, i) : cs;
+                for (int k = 0; k < p->ntaps; k++)
+                    acc += w[k] * ghost(p, uin, x + p->taps[k].dx, y + p->taps[k].dy,
+                                        z + p->taps[k].dz);
+                st(p->dtype, uout, i, acc);
+            }
+    free(w);
+}
+
+/* Eq.(3) per layer: B[z][y] = sum over x. */
+void orc_row_checksums(const orc_problem* p, const void* u, double* B)
+{
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < p->nz; z++)
+        for (int64_t y = 0; y < p->ny; y++) {
+            csum s = {0.0, 0.0};
+            for (int64_t x = 0; x < p->nx; x++) cs_add(&s, ld(p->dtype, u, idx(p, x, y, z)));
+            B[z * p->ny + y] = cs_val(s);
+        }
+}
+
+/* Eq.(2) per layer: A[z][x] = sum over y. */
+void orc_col_checksums(const orc_problem* p, const void* u, double* A)
+{
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < p->nz; z++)
+        for (int64_t x = 0; x < p->nx; x++) {
+            csum s = {0.0, 0.0};
+            for (int64_t y = 0; y < p->ny; y++) cs_add(&s, ld(p->dtype, u, idx(p, x, y, z)));
+            A[z * p->nx + x] = cs_val(s);
+        }
+}
+
+/* c_y and c_x of Theorem 1: the checksums of the constant term, computed once. */
+void orc_const_row_checksums(const orc_problem* p, const void* C, double* cB)
+{
+    const double cs = round_to(p->dtype, p->c_scalar);
+    for (int64_t z = 0; z < p->nz; z++)
+        for (int64_t y = 0; y < p->ny; y++) {
+            csum s = {0.0, 0.0};
+            for (int64_t x = 0; x < p->nx; x++)
+                cs_add(&s, C ? ld(p->dtype, C, idx(p, x, y, z)) : cs);
+            cB[z * p->ny + y] = cs_val(s);
+        }
+}
+
+void orc_const_col_checksums(const orc_problem* p, const void* C, double* cA)
+{
+    const double cs = round_to(p->dtype, p->c_scalar);
+    for (int64_t z = 0; z < p->nz; z++)
+        for (int64_t x = 0; x < p->nx; x++) {
+            csum s = {0.0, 0.0};
+            for (int64_t y = 0; y < p->ny; y++)
+                cs_add(&s, C ? ld(p->dtype, C, idx(p, x, y, z)) : cs);
+            cA[z * p->nx + x] = cs_val(s);
+        }
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Boundary strips.  Theorem 1's boundary terms only involve the first and last |shift| points
+ * of a line, so the strips hold the first r and last r values of every line.
+ * ------------------------------------------------------------------------------------------ */
+int orc_strip_width(const orc_problem* p, int axis)
+{
+    int r = 0;
+    for (int k = 0; k < p->ntaps; k++) {
+        int d = axis == 0 ? abs(p->taps[k].dx) : abs(p->taps[k].dy);
+        if (d > r) r = d;
+    }
+    return r;
+}
+
+void orc_row_strips(const orc_problem* p, const void* u, double* strips)
+{
+    const int r = orc_strip_width(p, 0);
+    if (r == 0) return;
+    for (int64_t z = 0; z < p->nz; z++)
+        for (int64_t y = 0; y < p->ny; y++) {
+            double* s = strips + (z * p->ny + y) * 2 * r;
+            for (int i = 0; i < r; i++) {
+                s[i] = ld(p->dtype, u, idx(p, i, y, z));
+                s[r + i] = ld(p->dtype, u, idx(p, p->nx - r + i, y, z));
+            }
+        }
+}
+
+void orc_col_strips(const orc_problem* p, const void* u, double* strips)
+{
+    const int r = orc_strip_width(p, 1);
+    if (r == 0) return;
+    for (int64_t z = 0; z < p->nz; z++)
+        for (int64_t x = 0; x < p->nx; x++) {
+            double* s = strips + (z * p->nx + x) * 2 * r;
+            for (int i = 0; i < r; i++) {
+                s[i] = ld(p->dtype, u, idx(p, x, i, z));
+                s[r + i] = ld(p->dtype, u, idx(p, x, p->ny - r + i, z));
+            }
+        }
+}
+
+/* Value at in-line position q (-r <= q < n + r) of one ghost-extended line of length n, read
+ * from its strip s (first r values, then last r values). */
+static double line_at(int bc, double g, const double* s, int r, int64_t n, int64_t q)
+{
+    if (q < 0) {
+        if (bc == ORC_BC_CLAMP) return s[0];
+        if (bc == ORC_BC_CONSTANT) return g;
+        q += n; /* periodic */
+    } else if (q >= n) {
+        if (bc == ORC_BC_CLAMP) return s[2 * r - 1];
+        if (bc == ORC_BC_CONSTANT) return g;
+        q -= n;
+    }
+    if (q < r) return s[q];
+    return s[r + (q - (n - r))];
+}
+
+/* Theorem 1's boundary term (beta for rows, alpha for columns), 0-based with exclusive upper
+ * limits: shifting a line of length n by d changes its sum from sum_{q=0}^{n-1} to
+ * sum_{q=d}^{n-1+d}; the difference is the d ghost points that enter minus the d points that
+ * leave.  d > 0: sum_{q=n}^{n+d-1} G(q) - sum_{q=0}^{d-1} u(q);
+ * d < 0: sum_{q=d}^{-1} G(q) - sum_{q=n+d}^{n-1} u(q). */
+static double boundary_term(int bc, double g, const double* s, int r, int64_t n, int d)
+{
+    double beta = 0.0;
+    if (d > 0) {
+        for (int64_t q = n; q < n + d; q++) beta += line_at(bc, g, s, r, n, q);
+        for (int64_t q = 0; q < d; q++) beta -= line_at(bc, g, s, r, n, q);
+    } else if (d < 0) {
+        for (int64_t q = d; q < 0; q++) beta += line_at(bc, g, s, r, n, q);
+        for (int64_t q = n + d; q < n; q++) beta -= line_at(bc, g, s, r, n, q);
+    }
+    return beta;
+}
+
+/* Theorem 1, Eq.(5), for the per-layer row checksums of a 3D grid: the stencil applied to the
+ * checksum plane, b'_{z,y} = c_{z,y} + sum_S w * (b_{z+dz, y+dy} + beta_{dx}(y+dy, z+dz)).
+ * The summed axis (x) collapses and its shift is absorbed in beta; the other two axes keep
+ * their shifts and their boundary rule.  A row that lies wholly in constant ghosts sums to
+ * nx * g. */
+void orc_predict_rows(const orc_problem* p, const double* cB, const double* Bt,
+                      const double* row_strips, double* Bp)
+{
+    double* w = rounded_weights(p);
+    const double g = round_to(p->dtype, p->bc_value);
+    const int r = orc_strip_width(p, 0);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < p->nz; z++)
+        for (int64_t y = 0; y < p->ny; y++) {
+            double acc = cB[z * p->ny + y];
+            for (int k = 0; k < p->ntaps; k++) {
+                const orc_tap* t = &p->taps[k];
+                int64_t yy = map_coord(p->bc, y + t->dy, p->ny);
+                int64_t zz = map_coord(p->bc, z + t->dz, p->nz);
+                double R;
+                if (yy < 0 || zz < 0) {
+                    R = (double)p->nx * g;
+                } else {
+                    const int64_t line = zz * p->ny + yy;
+                    R = Bt[line];
+                    if (t->dx != 0)
+                        R += boundary_term(p->bc, g, row_strips + line * 2 * r, r, p->nx, t->dx);
+                }
+                acc += w[k] * R;
+            }
+            Bp[z * p->ny + y] = acc;
+        }
+    free(w);
+}
+
+/* Theorem 1, Eq.(4): the same for the column checksums, with x and y exchanged (alpha). */
+void orc_predict_cols(const orc_problem* p, const double* cA, const double* At,
+                      const double* col_strips, double* Ap)
+{
+    double* w = rounded_weights(p);
+    const double g = round_to(p->dtype, p->bc_value);
+    const int r = orc_strip_width(p, 1);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < p->nz; z++)
+        for (int64_t x = 0; x < p->nx; x++) {
+            double acc = cA[z * p->nx + x];
+            for (int k = 0; k < p->ntaps; k++) {
+                const orc_tap* t = &p->taps[k];
+                int64_t xx = map_coord(p->bc, x + t->dx, p->nx);
+                int64_t zz = map_coord(p->bc, z + t->dz, p->nz);
+                double R;
+                if (xx < 0 || zz < 0) {
+                    R = (double)p->ny * g;
+                } else {
+                    const int64_t line = zz * p->nx + xx;
+                    R = At[line];
+                    if (t->dy != 0)
+                        R += boundary_term(p->bc, g, col_strips + line * 2 * r, r, p->ny, t->dy);
+                }
+                acc += w[k] * R;
+            }
+            Ap[z * p->nx + x] = acc;
+        }
+    free(w);
+}
+
+/* Section 3.4: relative mismatch against the predicted checksum.  Written as a negated
+ * "within tolerance" test so that NaN and Inf mismatches are flagged. */
+int64_t orc_detect(int64_t n, const double* direct, const double* pred, double eps,
+                   uint8_t* flags)
+{
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int f = !(fabs(direct[i] - pred[i]) <= eps * fabs(pred[i]));
+        flags[i] = (uint8_t)f;
+        cnt += f;
+    }
+    return cnt;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Whole runs.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+    const orc_problem* p;
+    const void* C;
+    double eps;
+    int auto_correct;
+    const orc_fault* faults;
+    int64_t nfaults;
+    orc_event* ev;
+    int64_t ev_cap;
+    orc_counters* cnt;
+    /* work arrays */
+    double *B, *Bn, *Bp, *cB, *cA, *At, *An, *Ap, *rs, *cs;
+    uint8_t *rflag, *cflag;
+} run_state;
+
+static void emit(run_state* S, int64_t sweep, int kind, int z, int y, int x, double a, double b)
+{
+    if (S->cnt->events_total < S->ev_cap) {
+        orc_event* e = &S->ev[S->cnt->events_total];
+        e->sweep = sweep;
+        e->kind = kind;
+        e->z = z;
+        e->y = y;
+        e->x = x;
+        e->a = a;
+        e->b = b;
+    }
+    S->cnt->events_total++;
+}
+
+/* Section 5.1 fault model: flip one bit of the value the sweep stores, after the update. */
+static void inject(run_state* S, void* uout, int64_t sweep, int attempt)
+{
+    const orc_problem* p = S->p;
+    for (int64_t f = 0; f < S->nfaults; f++) {
+        const orc_fault* F = &S->faults[f];
+        if (F->sweep != sweep || F->attempt != attempt) continue;
+        const int64_t i = idx(p, F->x, F->y, F->z);
+        if (p->dtype == ORC_F32) {
+            uint32_t v;
+            memcpy(&v, (float*)uout + i, 4);
+            v ^= (uint32_t)1u << F->bit;
+            memcpy((float*)uout + i, &v, 4);
+        } else {
+            uint64_t v;
+            memcpy(&v, (double*)uout + i, 8);
+            v ^= (uint64_t)1u << F->bit;
+            memcpy((double*)uout + i, &v, 8);
+        }
+    }
+}
+
+/* Value implied by the row checksum for point (x, y, z): the predicted row sum minus the other
+ * points of the row.  Eq.(10) written with the partial sum taken directly, which is the same
+ * quantity without losing the row sum to a huge corrupted value. */
+static double row_value(run_state* S, const void* u, int z, int y, int x)
+{
+    const orc_problem* p = S->p;
+    csum s = {0.0, 0.0};
+    for (int64_t q = 0; q < p->nx; q++)
+        if (q != x) cs_add(&s, ld(p->dtype, u, idx(p, q, y, z)));
+    return S->Bp[(int64_t)z * p->ny + y] - cs_val(s);
+}
+
+static double col_value(run_state* S, const void* u, int z, int y, int x)
+{
+    const orc_problem* p = S->p;
+    csum s = {0.0, 0.0};
+    for (int64_t q = 0; q < p->ny; q++)
+        if (q != y) cs_add(&s, ld(p->dtype, u, idx(p, x, q, z)));
+    return S->Ap[(int64_t)z * p->nx + x] - cs_val(s);
+}
+
+static void recompute_row(run_state* S, const void* u, int z, int y, double* B)
+{
+    const orc_problem* p = S->p;
+    csum s = {0.0, 0.0};
+    for (int64_t q = 0; q < p->nx; q++) cs_add(&s, ld(p->dtype, u, idx(p, q, y, z)));
+    B[(int64_t)z * p->ny + y] = cs_val(s);
+}
+
+/* Sections 3.4-3.5 for one layer with flagged rows: the column checksums of the layer locate
+ * the corrupted columns, the intersection gives the points, Eq.(10) gives their values. */
+static void locate_correct_layer(run_state* S, int64_t sweep, const void* uin, void* uout, int z)
+{
+    const orc_problem* p = S->p;
+    (void)uin;
+    int R = 0, K = 0;
+    int* ys = (int*)malloc(sizeof(int) * (size_t)p->ny);
+    int* xs = (int*)malloc(sizeof(int) * (size_t)p->nx);
+    for (int y = 0; y < p->ny; y++)
+        if (S->rflag[(int64_t)z * p->ny + y]) ys[R++] = y;
+    for (int x = 0; x < p->nx; x++) {
+        const int64_t l = (int64_t)z * p->nx + x;
+        if (!(fabs(S->An[l] - S->Ap[l]) <= S->eps * fabs(S->Ap[l]))) {
+            xs[K++] = x;
+            S->cnt->cols_flagged++;
+            emit(S, sweep, ORC_EV_COL_FLAG, z, -1, x, S->An[l], S->Ap[l]);
+        }
+    }
+    if (K == 0) {
+        /* Scenario 2 of the correction section: the grid is consistent with the other
+         * direction, so the mismatch is in a checksum.  The stored row checksum is the direct
+         * sum of the data, so nothing in the grid changes. */
+        for (int i = 0; i < R; i++) {
+            S->cnt->checksum_faults++;
+            emit(S, sweep, ORC_EV_CHECKSUM_FAULT, z, ys[i], -1, S->Bn[(int64_t)z * p->ny + ys[i]],
+                 S->Bp[(int64_t)z * p->ny + ys[i]]);
+        }
+    } else if (R >= 2 && K >= 2) {
+        S->cnt->uncorrectable++;
+        emit(S, sweep, ORC_EV_UNCORRECTABLE, z, -1, -1, (double)R, (double)K);
+    } else {
+        for (int i = 0; i < R; i++)
+            for (int j = 0; j < K; j++) {
+                const int y = ys[i], x = xs[j];
+                const int64_t c = idx(p, x, y, z);
+                const double old = ld(p->dtype, uout, c);
+                double v;
+                if (R == 1 && K == 1)
+                    v = 0.5 * (row_value(S, uout, z, y, x) + col_value(S, uout, z, y, x));
+                else if (R == 1)
+                    v = col_value(S, uout, z, y, x); /* one error per flagged column */
+                else
+                    v = row_value(S, uout, z, y, x); /* one error per flagged row */
+                st(p->dtype, uout, c, v);
+                S->cnt->corrected++;
+                emit(S, sweep, ORC_EV_CORRECTED, z, y, x, old, ld(p->dtype, uout, c));
+            }
+        /* checksum update after correction */
+        for (int i = 0; i < R; i++) recompute_row(S, uout, z, ys[i], S->Bn);
+    }
+    free(ys);
+    free(xs);
+}
+
+/* Online ABFT after sweep t (Figure 1 steps 2-3, then Section 3.5). */
+static void online_check(run_state* S, int64_t sweep, const void* uin, void* uout)
+{
+    const orc_problem* p = S->p;
+    const int64_t nrows = (int64_t)p->nz * p->ny;
+    orc_row_checksums(p, uout, S->Bn);
+    orc_row_strips(p, uin, S->rs);
+    orc_predict_rows(p, S->cB, S->B, S->rs, S->Bp);
+    int64_t nf = orc_detect(nrows, S->Bn, S->Bp, S->eps, S->rflag);
+    if (nf == 0) return;
+    for (int64_t l = 0; l < nrows; l++)
+        if (S->rflag[l]) {
+            S->cnt->rows_flagged++;
+            emit(S, sweep, ORC_EV_ROW_FLAG, (int)(l / p->ny), (int)(l % p->ny), -1, S->Bn[l],
+                 S->Bp[l]);
+        }
+    if (!S->auto_correct) return;
+    /* the second checksum direction, only now that a mismatch was seen */
+    orc_col_checksums(p, uin, S->At);
+    orc_col_strips(p, uin, S->cs);
+    orc_predict_cols(p, S->cA, S->At, S->cs, S->Ap);
+    orc_col_checksums(p, uout, S->An);
+    for (int z = 0; z < p->nz; z++) {
+        int any = 0;
+        for (int y = 0; y < p->ny && !any; y++) any = S->rflag[(int64_t)z * p->ny + y];
+        if (any) locate_correct_layer(S, sweep, uin, uout, z);
+    }
+}
+
+int orc_run(const orc_problem* p, const void* C, int mode, int period, double eps,
+            int auto_correct, void* u_a, void* u_b, int64_t nsweeps,
+            const orc_fault* faults, int64_t nfaults,
+            orc_event* events, int64_t max_events, orc_counters* counters)
+{
+    int rc = orc_validate(p);
+    if (rc) return rc;
+    if (!u_a || !u_b || !counters || nsweeps < 0) return -1;
+    if (mode < ORC_MODE_NONE || mode > ORC_MODE_OFFLINE) return -1;
+    if (mode == ORC_MODE_OFFLINE && period < 1) return -1;
+    const int bits = p->dtype == ORC_F32 ? 32 : 64;
+    for (int64_t f = 0; f < nfaults; f++) {
+        const orc_fault* F = &faults[f];
+        if (F->x < 0 || F->x >= p->nx || F->y < 0 || F->y >= p->ny || F->z < 0 ||
+            F->z >= p->nz || F->bit < 0 || F->bit >= bits)
+            return -3;
+    }
+    memset(counters, 0, sizeof(*counters));
+
+    const int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    const int64_t nrows = (int64_t)p->nz * p->ny, ncols = (int64_t)p->nz * p->nx;
+    const size_t bytes = (size_t)n * elem_size(p->dtype);
+    const int rx = orc_strip_width(p, 0), ry = orc_strip_width(p, 1);
+
+    run_state S;
+    memset(&S, 0, sizeof(S));
+    S.p = p;
+    S.C = C;
+    S.eps = eps;
+    S.auto_correct = auto_correct;
+    S.faults = faults;
+    S.nfaults = nfaults;
+    S.ev = events;
+    S.ev_cap = events ? max_events : 0;
+    S.cnt = counters;
+    S.B = (double*)calloc((size_t)nrows, sizeof(double));
+    S.Bn = (double*)calloc((size_t)nrows, sizeof(double));
+    S.Bp = (double*)calloc((size_t)nrows, sizeof(double));
+    S.cB = (double*)calloc((size_t)nrows, sizeof(double));
+    S.cA = (double*)calloc((size_t)ncols, sizeof(double));
+    S.At = (double*)calloc((size_t)ncols, sizeof(double));
+    S.An = (double*)calloc((size_t)ncols, sizeof(double));
+    S.Ap = (double*)calloc((size_t)ncols, sizeof(double));
+    S.rs = (double*)calloc((size_t)nrows * 2 * (rx ? rx : 1), sizeof(double));
+    S.cs = (double*)calloc((size_t)ncols * 2 * (ry ? ry : 1), sizeof(double));
+    S.rflag = (uint8_t*)calloc((size_t)nrows, 1);
+    S.cflag = (uint8_t*)calloc((size_t)ncols, 1);
+    orc_const_row_checksums(p, C, S.cB);
+    orc_const_col_checksums(p, C, S.cA);
+
+    void* uin = u_a;
+    void* uout = u_b;
+
+    if (mode != ORC_MODE_OFFLINE) {
+        if (mode == ORC_MODE_ONLINE) orc_row_checksums(p, uin, S.B);
+        for (int64_t t = 0; t < nsweeps; t++) {
+            orc_sweep(p, C, uin, uout);
+            inject(&S, uout, t, 0);
+            if (mode == ORC_MODE_ONLINE) {
+                online_check(&S, t, uin, uout);
+                double* tmp = S.B;
+                S.B = S.Bn;
+                S.Bn = tmp;
+            }
+            void* tu = uin;
+            uin = uout;
+            uout = tu;
+            counters->sweeps_done = t + 1;
+        }
+        if (uin != u_a) memcpy(u_a, uin, bytes);
+    } else {
+        /* Section 4: offline detection every `period` sweeps with checkpoint / rollback.
+         * The checkpoint is a copy of the grid and of its row checksums. */
+        void* ckpt = malloc(bytes);
+        double* Bck = (double*)malloc(sizeof(double) * (size_t)nrows);
+        double* hist = (double*)malloc(sizeof(double) * (size_t)nrows * 2 * (rx ? rx : 1) *
+                                       (size_t)period);
+        memcpy(ckpt, u_a, bytes);
+        orc_row_checksums(p, u_a, Bck);
+        int64_t t0 = 0;
+        while (t0 < nsweeps) {
+            const int64_t k = (nsweeps - t0 < period) ? nsweeps - t0 : period;
+            int attempt = 0;
+            int halt = 0;
+            for (;;) {
+                uin = u_a;
+                uout = u_b;
+                for (int64_t j = 0; j < k; j++) {
+                    orc_row_strips(p, uin, hist + j * nrows * 2 * rx);
+                    orc_sweep(p, C, uin, uout);
+                    inject(&S, uout, t0 + j, attempt);
+                    void* tu = uin;
+                    uin = uout;
+                    uout = tu;
+                }
+                if (uin != u_a) memcpy(u_a, uin, bytes);
+                /* direct checksums of the window's result */
+                orc_row_checksums(p, u_a, S.Bn);
+                /* the interpolation applied k times from the checkpoint's checksums */
+                memcpy(S.B, Bck, sizeof(double) * (size_t)nrows);
+                for (int64_t j = 0; j < k; j++) {
+                    orc_predict_rows(p, S.cB, S.B, hist + j * nrows * 2 * rx, S.Bp);
+                    memcpy(S.B, S.Bp, sizeof(double) * (size_t)nrows);
+                }
+                counters->windows_checked++;
+                int64_t nf = orc_detect(nrows, S.Bn, S.Bp, eps, S.rflag);
+                if (nf == 0) break;
+                for (int64_t l = 0; l < nrows; l++)
+                    if (S.rflag[l])
+                        emit(&S, t0 + k - 1, ORC_EV_WINDOW_FLAG, (int)(l / p->ny),
+                             (int)(l % p->ny), attempt, S.Bn[l], S.Bp[l]);
+                if (attempt == 0) counters->windows_flagged++;
+                if (!auto_correct) {
+                    halt = 1;
+                    break;
+                }
+                if (attempt == 1) {
+                    counters->persistent++;
+                    emit(&S, t0 + k - 1, ORC_EV_PERSISTENT, -1, -1, -1, (double)nf, 0.0);
+                    break;
+                }
+                counters->rollbacks++;
+                emit(&S, t0, ORC_EV_ROLLBACK, -1, -1, (int)k, 0.0, 0.0);
+                memcpy(u_a, ckpt, bytes);
+                attempt = 1;
+            }
+            counters->sweeps_done = t0 + k;
+            if (halt) break;
+            memcpy(ckpt, u_a, bytes);
+            memcpy(Bck, S.Bn, sizeof(double) * (size_t)nrows);
+            t0 += k;
+        }
+        free(ckpt);
+        free(Bck);
+        free(hist);
+    }
+
+    free(S.B);
+    free(S.Bn);
+    free(S.Bp);
+    free(S.cB);
+    free(S.cA);
+    free(S.At);
+    free(S.An);
+    free(S.Ap);
+    free(S.rs);
+    free(S.cs);
+    free(S.rflag);
+    free(S.cflag);
+    return 0;
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,125 @@
+/*
+ * CPU oracle for ABFT-protected stencil sweeps
+ * (Cavelan & Ciorba, "Algorithm-Based Fault Tolerance for Parallel Stencil Computations").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This header and abft_oracle.c are the plain, slow reference
+ * that the GPU library is checked against.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load it; the library never includes, links or calls it.
+ * It shares no code, header, table or constant with the GPU library.
+ *
+ * Grid layout: u[z][y][x], x fastest (the paper's index c = x + y*nx + z*nx*ny, Section 3.2).
+ * Row checksum  B[z][y] = sum_x u[z][y][x]   (the paper's b_y, Eq.(3), computed every sweep)
+ * Column checksum A[z][x] = sum_y u[z][y][x] (the paper's a_x, Eq.(2), computed on demand)
+ */
+#ifndef ABFT_ORACLE_H
+#define ABFT_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_F32 = 0, ORC_F64 = 1 };
+enum { ORC_BC_CLAMP = 0, ORC_BC_PERIODIC = 1, ORC_BC_CONSTANT = 2 };
+enum { ORC_MODE_NONE = 0, ORC_MODE_ONLINE = 1, ORC_MODE_OFFLINE = 2 };
+
+/* Event kinds written by orc_run. */
+enum {
+    ORC_EV_ROW_FLAG = 1,       /* online row mismatch: sweep, z, y; a = direct, b = predicted */
+    ORC_EV_CORRECTED = 2,      /* point corrected: sweep, z, y, x; a = old value, b = new value */
+    ORC_EV_CHECKSUM_FAULT = 3, /* row flagged but no column flagged: sweep, z, y */
+    ORC_EV_UNCORRECTABLE = 4,  /* >= 2 flagged rows and >= 2 flagged columns: sweep, z */
+    ORC_EV_WINDOW_FLAG = 5,    /* offline row mismatch at window end: sweep, z, y, x = attempt */
+    ORC_EV_ROLLBACK = 6,       /* offline rollback: sweep = window start, x = window length */
+    ORC_EV_PERSISTENT = 7,     /* offline recompute still mismatched: sweep = window end */
+    ORC_EV_COL_FLAG = 8        /* column mismatch during location: sweep, z, x; a, b as above */
+};
+
+typedef struct { int32_t dx, dy, dz, pad; double w; } orc_tap;
+
+typedef struct {
+    int64_t sweep;              /* sweep t whose stored output u^{t+1} is hit */
+    int32_t z, y, x, bit, attempt, pad;
+} orc_fault;
+
+typedef struct {
+    int64_t sweep;
+    int32_t kind, z, y, x;
+    double a, b;
+} orc_event;
+
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t dtype;              /* storage type of u and C: ORC_F32 or ORC_F64 */
+    int32_t ntaps;
+    int32_t bc;                 /* ORC_BC_* */
+    const orc_tap* taps;        /* weights are rounded to the storage type by the oracle */
+    double bc_value;            /* ghost value for ORC_BC_CONSTANT */
+    double c_scalar;            /* constant term when no C array is given */
+} orc_problem;
+
+typedef struct {
+    int64_t sweeps_done;
+    int64_t rows_flagged;       /* online row mismatches */
+    int64_t cols_flagged;
+    int64_t corrected;
+    int64_t checksum_faults;
+    int64_t uncorrectable;
+    int64_t windows_checked;
+    int64_t windows_flagged;
+    int64_t rollbacks;
+    int64_t persistent;
+    int64_t events_total;       /* may exceed the event capacity */
+} orc_counters;
+
+/* Returns 0 when the problem is valid, a negative code otherwise. */
+int orc_validate(const orc_problem* p);
+
+/* Eq.(1): uout = C + sum_S w * G(uin, x+dx, y+dy, z+dz), evaluated in double and rounded once
+ * to the storage type.  C may be NULL (then p->c_scalar). */
+void orc_sweep(const orc_problem* p, const void* C, const void* uin, void* uout);
+
+/* Eq.(3) / Eq.(2), per layer, compensated double sums. */
+void orc_row_checksums(const orc_problem* p, const void* u, double* B);
+void orc_col_checksums(const orc_problem* p, const void* u, double* A);
+
+/* The constant-term checksums c_y and c_x of Theorem 1. */
+void orc_const_row_checksums(const orc_problem* p, const void* C, double* cB);
+void orc_const_col_checksums(const orc_problem* p, const void* C, double* cA);
+
+/* Boundary strips: for every row line (z, y) the first r and the last r values along x,
+ * stored as 2*r doubles; r = orc_strip_width(p, axis).  Column lines likewise along y. */
+int orc_strip_width(const orc_problem* p, int axis /* 0 = x (rows), 1 = y (columns) */);
+void orc_row_strips(const orc_problem* p, const void* u, double* strips);
+void orc_col_strips(const orc_problem* p, const void* u, double* strips);
+
+/* Theorem 1, Eq.(5) (rows) and Eq.(4) (columns): predicted checksums of the next sweep from
+ * the current checksums, the constant-term checksums and the boundary terms beta / alpha. */
+void orc_predict_rows(const orc_problem* p, const double* cB, const double* Bt,
+                      const double* row_strips, double* Bp);
+void orc_predict_cols(const orc_problem* p, const double* cA, const double* At,
+                      const double* col_strips, double* Ap);
+
+/* Section 3.4: flag[i] = !(|direct - pred| <= eps * |pred|).  Returns the number flagged. */
+int64_t orc_detect(int64_t n, const double* direct, const double* pred, double eps,
+                   uint8_t* flags);
+
+/* Whole run: nsweeps sweeps from u_a (u_b is scratch of the same size), protected in the given
+ * mode (ORC_MODE_*), with the fault plan applied to stored values.  The final grid is left in
+ * u_a.  period is the offline window length.  With auto_correct == 0 in offline mode the run
+ * stops after the first flagged window (the checkpoint is still valid) and sweeps_done tells
+ * where.  Events are written up to max_events.  Returns 0 or a negative code. */
+int orc_run(const orc_problem* p, const void* C, int mode, int period, double eps,
+            int auto_correct, void* u_a, void* u_b, int64_t nsweeps,
+            const orc_fault* faults, int64_t nfaults,
+            orc_event* events, int64_t max_events, orc_counters* counters);
+
+/* Thread control for the OpenMP loops (results do not depend on it). */
+void orc_set_threads(int n);
+int orc_get_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
