@@ -1,0 +1,163 @@
+// Internal declarations shared by the host runtime (abft_runtime.cpp) and the gfx950 kernels
+// (abft_kernels.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "abft_stencil.h"
+
+namespace abft {
+
+constexpr int kMaxFlags = 1024;   // flagged rows remembered per sweep for location
+constexpr int kSweepBlock = 256;  // threads per block of the sweep kernel (4 wavefronts)
+constexpr int kFixBlock = 512;    // threads of the single locate/correct block
+constexpr int kCheckBlock = 256;  // threads per block of the offline window check
+constexpr int kMaxPeriod = 32;    // longest offline window handled by one check launch
+
+// Weight slots of the radius-1 star stencil: centre, x-1, x+1, y-1, y+1, z-1, z+1.
+enum { W_C = 0, W_XM, W_XP, W_YM, W_YP, W_ZM, W_ZP, W_COUNT };
+
+struct Stencil {
+    double w[W_COUNT];  // weights rounded to the grid dtype, held as double
+    uint32_t mask;      // bit k set when slot k is a tap of the stencil
+    int32_t bc;         // abft_bc
+    double g;           // constant ghost value (rounded to the grid dtype)
+};
+
+struct RowFlag {
+    int32_t z, y;
+    double direct, pred;
+};
+
+struct FlagSlot {
+    uint32_t count;
+    uint32_t pad;
+    RowFlag rows[kMaxFlags];
+};
+
+// Device counters; 64-bit so they can be updated with atomicAdd.
+struct Counters {
+    unsigned long long rows_flagged, cols_flagged, corrected, checksum_faults, uncorrectable;
+    unsigned long long windows_checked, windows_flagged, rollbacks, persistent;
+    unsigned long long events_total;
+    unsigned long long noise_bits;  // bit pattern of the largest non-negative noise (double)
+    unsigned long long overflow;    // sweeps whose flagged rows exceeded kMaxFlags
+};
+
+// Sweep kernel variants.
+enum { MODE_PLAIN = 0, MODE_CSUM = 1, MODE_PROT = 2 };
+enum { CS_F64 = 0, CS_F32C = 1 };
+
+struct SweepArgs {
+    const void* uin;
+    void* uout;
+    const void* C;          // constant term or null
+    double c_scalar;        // constant term when C is null
+    Stencil st;
+    int32_t nx, ny, nz;
+    int32_t tz;             // planes per block
+    int32_t nyb, ntiles;    // y-blocks and total tiles (= grid size)
+    int32_t attempt;        // fault-plan attempt matched by this sweep
+    const int64_t* t_base;  // device sweep base (graph replays) or null
+    int64_t t_off;          // sweep index = t_off + (*t_base or 0)
+    // checksums
+    const double* Bt;       // row checksums of uin (prediction input)
+    double* Bn;             // row checksums of uout (written)
+    const double* cB;       // constant-term row checksums
+    double eps;
+    FlagSlot* slot;         // flagged rows of this sweep
+    uint32_t* zero_ptr;     // words cleared by block 0 (next sweep's slot / window counts)
+    int32_t zero_n;
+    Counters* cnt;
+    abft_event* ev;
+    int32_t ev_cap;
+    int32_t grid;           // grid index reported in events
+    // fault plan: entries of sweep t are faults[first[t] .. first[t+1])
+    const abft_fault* faults;
+    const int32_t* fault_first;
+    int64_t fault_tmax;     // first[] covers sweeps [0, fault_tmax)
+    // offline
+    double* E;              // boundary terms of this sweep's input rows, or null
+    const uint32_t* guard;  // run only when *guard != 0 (rollback recompute), or null
+};
+
+struct FixArgs {
+    const void* uin;
+    void* uout;
+    double* Bn;
+    const double* cA;
+    Stencil st;
+    int32_t nx, ny, nz;
+    double eps;
+    FlagSlot* slot;
+    Counters* cnt;
+    abft_event* ev;
+    int32_t ev_cap;
+    int32_t grid;
+    const int64_t* t_base;
+    int64_t t_off;
+};
+
+struct CheckArgs {
+    const double* Bck;      // checksums at the checkpoint
+    const double* Bdir;     // direct checksums at the window end
+    const double* cB;
+    const double* E;        // [k][nz][ny] boundary terms, or null
+    Stencil st;
+    int32_t nx, ny, nz;
+    int32_t k;              // window length
+    double eps;
+    int32_t tyi, tzi, nyt, nzt;   // interior tile sizes and tile counts
+    int32_t ry_max, rz_max;       // region extents the LDS was sized for
+    uint32_t* flag_count;   // window flag counter written
+    const uint32_t* guard;  // run only when *guard != 0, or null
+    uint32_t* ticket;       // block-completion counter (reset by the last block)
+    Counters* cnt;
+    abft_event* ev;
+    int32_t ev_cap;
+    int32_t attempt;
+    int32_t auto_correct;
+    int64_t t_first;        // first sweep of the window
+    int64_t t_last;         // last sweep of the window
+};
+
+// Kernel launchers (abft_kernels.hip).  Each returns hipSuccess or the launch error.
+struct SweepShape {
+    int32_t lpr;   // lanes per row: 16 or 64
+    int32_t nch;   // chunks of lpr*vec elements per row: 1, 2, 4 or 8
+    int32_t vec;   // elements per 16-byte access (1 for rows that are not 16-byte multiples)
+    int32_t tz;    // planes per block
+};
+
+bool sweep_shape_supported(int dtype, const SweepShape& s);
+size_t sweep_lds_bytes(int dtype, int nx, const SweepShape& s);
+int sweep_rows_per_block(const SweepShape& s);
+hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, const SweepArgs& a,
+                        hipStream_t st);
+hipError_t launch_fixup(int dtype, const FixArgs& a, hipStream_t st);
+size_t fixup_lds_bytes(int nx);
+hipError_t launch_check(const CheckArgs& a, hipStream_t st);
+size_t check_lds_bytes(int ry, int rz);
+hipError_t launch_row_sums(int dtype, const void* u, double cs, int nx, int64_t nrows,
+                           double* out, hipStream_t st);
+hipError_t launch_col_sums(int dtype, const void* u, double cs, int nx, int ny, int nz,
+                           double* out, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+hipError_t launch_rollback_note(const uint32_t* guard, Counters* cnt, abft_event* ev, int cap,
+                                int64_t t_first, int k, hipStream_t st);
+
+// Per-variant sweep launchers (one translation unit each).
+#define ABFT_DECL_SWEEP(NAME)                                                                 \
+    hipError_t NAME(int csum, const SweepShape& s, const SweepArgs& a, hipStream_t st,         \
+                    size_t lds);
+ABFT_DECL_SWEEP(launch_sweep_f32_plain)
+ABFT_DECL_SWEEP(launch_sweep_f32_csum)
+ABFT_DECL_SWEEP(launch_sweep_f32_prot)
+ABFT_DECL_SWEEP(launch_sweep_f64_plain)
+ABFT_DECL_SWEEP(launch_sweep_f64_csum)
+ABFT_DECL_SWEEP(launch_sweep_f64_prot)
+#undef ABFT_DECL_SWEEP
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st);
+
+}  // namespace abft

@@ -1,0 +1,484 @@
+// gfx950 kernels other than the sweep: locate and correct (Section 3.5), the offline window
+// check (Section 4.1), and the initial checksums.
+#include "abft_device.h"
+
+namespace abft {
+
+constexpr int kFixXPT = 4;  // columns per thread in the locate block: nx <= 4 * kFixBlock
+
+// Deterministic block-wide fp64 sum (fixed combination order).
+__device__ double block_sum(double v, double* red)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// ------------------------------------------------------------------------------------------
+// Locate and correct after a sweep whose row checks flagged something (Sections 3.4-3.5).
+// One block.  For each layer with flagged rows: the column checksums of the layer (Eq.(2)),
+// their prediction from the input grid (Theorem 1, Eq.(4)), the flagged columns, and the
+// correction of the intersections (Eq.(10), with the partial sum over the other points taken
+// directly).  Exits at once when nothing was flagged.
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kFixBlock) fixup_kernel(const FixArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    __shared__ double red[kFixBlock / 64];
+    __shared__ int sh_K;
+
+    FlagSlot* slot = a.slot;
+    const unsigned n_all = slot->count;
+    if (n_all == 0u) return;
+
+    const int nx = a.nx, ny = a.ny, nz = a.nz, bc = a.st.bc;
+    double* At = reinterpret_cast<double*>(smem_raw);
+    double* Ap = At + nx;
+    double* An = Ap + nx;
+    int* cflag = reinterpret_cast<int*>(An + nx);
+    int* xs = cflag + nx;
+
+    const int tid = threadIdx.x;
+    const int64_t t = a.t_off + (a.t_base != nullptr ? *a.t_base : 0);
+    const T* uin = static_cast<const T*>(a.uin);
+    T* uout = static_cast<T*>(a.uout);
+    const size_t ps = (size_t)nx * (size_t)ny;
+    const double gd = (double)(T)a.st.g;
+    const uint32_t mask = a.st.mask;
+
+    if (n_all > (unsigned)kMaxFlags) {
+        // more flagged rows than remembered: nothing can be located reliably
+        if (tid == 0) {
+            atomicAdd(&a.cnt->uncorrectable, 1ull);
+            emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_UNCORRECTABLE, -1, -1, -1,
+                       (double)n_all, 0.0, a.grid);
+            slot->count = 0u;
+        }
+        return;
+    }
+    const int n = (int)n_all;
+    if (tid == 0) {  // order the flagged rows by (z, y)
+        for (int i = 1; i < n; ++i) {
+            const RowFlag key = slot->rows[i];
+            int j = i - 1;
+            while (j >= 0 && (slot->rows[j].z > key.z ||
+                              (slot->rows[j].z == key.z && slot->rows[j].y > key.y))) {
+                slot->rows[j + 1] = slot->rows[j];
+                --j;
+            }
+            slot->rows[j + 1] = key;
+        }
+    }
+    __syncthreads();
+
+    int i = 0;
+    while (i < n) {
+        const int z = slot->rows[i].z;
+        int j = i;
+        while (j < n && slot->rows[j].z == z) ++j;
+        const int R = j - i;
+        const int zm = map_coord(z - 1, nz, bc), zp = map_coord(z + 1, nz, bc);
+
+        // column checksums of the layer (input: z and its z-neighbours; output: z)
+        double s_zm[kFixXPT], s_zp[kFixXPT], u_f[kFixXPT], u_l[kFixXPT];
+#pragma unroll
+        for (int k = 0; k < kFixXPT; ++k) {
+            const int x = tid + k * kFixBlock;
+            s_zm[k] = s_zp[k] = u_f[k] = u_l[k] = 0.0;
+            if (x < nx) {
+                double sz = 0.0, szm = 0.0, szp = 0.0, sn = 0.0;
+#pragma unroll 4
+                for (int yy = 0; yy < ny; ++yy) {
+                    const size_t o = (size_t)yy * nx + x;
+                    sz += (double)uin[(size_t)z * ps + o];
+                    if (zm >= 0) szm += (double)uin[(size_t)zm * ps + o];
+                    if (zp >= 0) szp += (double)uin[(size_t)zp * ps + o];
+                    sn += (double)uout[(size_t)z * ps + o];
+                }
+                At[x] = sz;
+                An[x] = sn;
+                s_zm[k] = zm >= 0 ? szm : (double)ny * gd;
+                s_zp[k] = zp >= 0 ? szp : (double)ny * gd;
+                u_f[k] = (double)uin[(size_t)z * ps + x];
+                u_l[k] = (double)uin[(size_t)z * ps + (size_t)(ny - 1) * nx + x];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kFixXPT; ++k) {
+            const int x = tid + k * kFixBlock;
+            if (x < nx) {
+                const double a0 = At[x];
+                double gt, gb;  // G(y = -1), G(y = ny)
+                if (bc == ABFT_BC_CLAMP) { gt = u_f[k]; gb = u_l[k]; }
+                else if (bc == ABFT_BC_PERIODIC) { gt = u_l[k]; gb = u_f[k]; }
+                else { gt = gd; gb = gd; }
+                auto acol = [&](int xx) -> double {
+                    const int mx = map_coord(xx, nx, bc);
+                    return mx < 0 ? (double)ny * gd : At[mx];
+                };
+                double ap = a.cA[(size_t)z * nx + x];
+                if (mask & 1u) ap += a.st.w[W_C] * a0;
+                if (mask & 2u) ap += a.st.w[W_XM] * acol(x - 1);
+                if (mask & 4u) ap += a.st.w[W_XP] * acol(x + 1);
+                if (mask & 8u) ap += a.st.w[W_YM] * (a0 + (gt - u_l[k]));
+                if (mask & 16u) ap += a.st.w[W_YP] * (a0 + (gb - u_f[k]));
+                if (mask & 32u) ap += a.st.w[W_ZM] * s_zm[k];
+                if (mask & 64u) ap += a.st.w[W_ZP] * s_zp[k];
+                Ap[x] = ap;
+                const double d = fabs(An[x] - ap);
+                cflag[x] = !(d <= a.eps * fabs(ap));
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int K = 0;
+            for (int x = 0; x < nx; ++x)
+                if (cflag[x]) {
+                    xs[K++] = x;
+                    atomicAdd(&a.cnt->cols_flagged, 1ull);
+                    emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_COL_FLAG, z, -1, x, An[x], Ap[x],
+                               a.grid);
+                }
+            sh_K = K;
+        }
+        __syncthreads();
+        const int K = sh_K;
+
+        if (K == 0) {
+            // the layer is consistent column-wise: the mismatch sits in a checksum
+            if (tid == 0)
+                for (int ri = i; ri < j; ++ri) {
+                    atomicAdd(&a.cnt->checksum_faults, 1ull);
+                    emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_CHECKSUM_FAULT, z,
+                               slot->rows[ri].y, -1, slot->rows[ri].direct, slot->rows[ri].pred,
+                               a.grid);
+                }
+        } else if (R >= 2 && K >= 2) {
+            if (tid == 0) {
+                atomicAdd(&a.cnt->uncorrectable, 1ull);
+                emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_UNCORRECTABLE, z, -1, -1, (double)R,
+                           (double)K, a.grid);
+            }
+        } else {
+            for (int ri = i; ri < j; ++ri) {
+                const int y = slot->rows[ri].y;
+                const double bpred = slot->rows[ri].pred;
+                for (int kk = 0; kk < K; ++kk) {
+                    const int x = xs[kk];
+                    T* row = uout + (size_t)z * ps + (size_t)y * nx;
+                    double p = 0.0;
+                    for (int xx = tid; xx < nx; xx += kFixBlock)
+                        if (xx != x) p += (double)row[xx];
+                    const double prow = block_sum(p, red);
+                    p = 0.0;
+                    for (int yy = tid; yy < ny; yy += kFixBlock)
+                        if (yy != y) p += (double)uout[(size_t)z * ps + (size_t)yy * nx + x];
+                    const double pcol = block_sum(p, red);
+                    if (tid == 0) {
+                        const double vrow = bpred - prow, vcol = Ap[x] - pcol;
+                        double v;
+                        if (R == 1 && K == 1) v = 0.5 * (vrow + vcol);
+                        else if (R == 1) v = vcol;  // several points in one row: one per column
+                        else v = vrow;              // several points in one column: one per row
+                        const T old = row[x];
+                        row[x] = (T)v;
+                        atomicAdd(&a.cnt->corrected, 1ull);
+                        emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_CORRECTED, z, y, x,
+                                   (double)old, (double)(T)v, a.grid);
+                    }
+                    __syncthreads();
+                }
+                // checksum update after the correction: the row's direct sum
+                const T* rowc = uout + (size_t)z * ps + (size_t)y * nx;
+                double p = 0.0;
+                for (int xx = tid; xx < nx; xx += kFixBlock) p += (double)rowc[xx];
+                const double S = block_sum(p, red);
+                if (tid == 0) a.Bn[(size_t)z * ny + y] = S;
+            }
+        }
+        __syncthreads();
+        i = j;
+    }
+    if (tid == 0) slot->count = 0u;
+}
+
+// ------------------------------------------------------------------------------------------
+// Offline window check (Section 4.1): the checksum interpolation applied k times from the
+// checkpoint's checksums, then compared with the direct checksums at the window end.  Each
+// block owns a tile of the (z, y) checksum plane and iterates the plane stencil in LDS on the
+// tile plus a halo of k rows / layers (the k-step dependency cone), so one launch does all k
+// steps.
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    if (a.guard != nullptr && *a.guard == 0u) return;
+
+    const int nx = a.nx, ny = a.ny, nz = a.nz, bc = a.st.bc, k = a.k;
+    const bool per = bc == ABFT_BC_PERIODIC;
+    const double gd = a.st.g;
+    const uint32_t mask = a.st.mask;
+    const int tid = threadIdx.x;
+    const int yt = blockIdx.x % a.nyt, zt = blockIdx.x / a.nyt;
+    const int iy0 = yt * a.tyi, iy1 = min(iy0 + a.tyi, ny);
+    const int iz0 = zt * a.tzi, iz1 = min(iz0 + a.tzi, nz);
+    int ry0, ry1, rz0, rz1;
+    if (per) {
+        ry0 = iy0 - k; ry1 = iy1 + k; rz0 = iz0 - k; rz1 = iz1 + k;
+    } else {
+        ry0 = max(0, iy0 - k); ry1 = min(ny, iy1 + k);
+        rz0 = max(0, iz0 - k); rz1 = min(nz, iz1 + k);
+    }
+    const int RY = ry1 - ry0, RZ = rz1 - rz0, NC = RY * RZ;
+    double* cur = reinterpret_cast<double*>(smem_raw);
+    double* nxt = cur + (size_t)a.ry_max * a.rz_max;
+
+    auto wrap = [](int c, int n) { const int m = c % n; return m < 0 ? m + n : m; };
+    for (int i = tid; i < NC; i += kCheckBlock) {
+        const int yy = ry0 + i % RY, zz = rz0 + i / RY;
+        const int gy = per ? wrap(yy, ny) : yy, gz = per ? wrap(zz, nz) : zz;
+        cur[i] = a.Bck[(size_t)gz * ny + gy];
+    }
+    __syncthreads();
+
+    const double wx = ((mask & 1u) ? a.st.w[W_C] : 0.0) + ((mask & 2u) ? a.st.w[W_XM] : 0.0) +
+                      ((mask & 4u) ? a.st.w[W_XP] : 0.0);
+    for (int s = 0; s < k; ++s) {
+        for (int i = tid; i < NC; i += kCheckBlock) {
+            const int iy = i % RY, iz = i / RY;
+            const int yy = ry0 + iy, zz = rz0 + iz;
+            const int gy = per ? wrap(yy, ny) : yy, gz = per ? wrap(zz, nz) : zz;
+            const double b = cur[i];
+            auto nb = [&](int dz, int dy) -> double {
+                int y2 = yy + dy, z2 = zz + dz;
+                if (!per) {
+                    if (y2 < 0 || y2 >= ny || z2 < 0 || z2 >= nz) {
+                        if (bc == ABFT_BC_CONSTANT) return (double)nx * gd;
+                        y2 = min(max(y2, 0), ny - 1);
+                        z2 = min(max(z2, 0), nz - 1);
+                    }
+                }
+                // outside the loaded region: only cells that do not reach the tile use it
+                if (y2 < ry0 || y2 >= ry1 || z2 < rz0 || z2 >= rz1) return b;
+                return cur[(z2 - rz0) * RY + (y2 - ry0)];
+            };
+            const size_t l = (size_t)gz * ny + gy;
+            double v = a.cB[l] + wx * b;
+            if (a.E != nullptr) v += a.E[(size_t)s * nz * ny + l];
+            if (mask & 8u) v += a.st.w[W_YM] * nb(0, -1);
+            if (mask & 16u) v += a.st.w[W_YP] * nb(0, 1);
+            if (mask & 32u) v += a.st.w[W_ZM] * nb(-1, 0);
+            if (mask & 64u) v += a.st.w[W_ZP] * nb(1, 0);
+            nxt[i] = v;
+        }
+        __syncthreads();
+        double* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+
+    double noise = 0.0;
+    for (int i = tid; i < NC; i += kCheckBlock) {
+        const int yy = ry0 + i % RY, zz = rz0 + i / RY;
+        if (yy < iy0 || yy >= iy1 || zz < iz0 || zz >= iz1) continue;
+        const double bp = cur[i];
+        const double S = a.Bdir[(size_t)zz * ny + yy];
+        const double d = fabs(S - bp);
+        if (!(d <= a.eps * fabs(bp))) {
+            atomicAdd(a.flag_count, 1u);
+            emit_event(a.cnt, a.ev, a.ev_cap, a.t_last, ABFT_EV_WINDOW_FLAG, zz, yy, a.attempt, S,
+                       bp, 0);
+        } else if (bp != 0.0) {
+            noise = fmax(noise, d / fabs(bp));
+        }
+    }
+    record_noise(a.cnt, noise);
+    __syncthreads();
+    if (tid == 0) {
+        if (blockIdx.x == 0) atomicAdd(&a.cnt->windows_checked, 1ull);
+        __threadfence();
+        const unsigned tk = atomicAdd(a.ticket, 1u);
+        if (tk == gridDim.x - 1) {  // last block of the check
+            atomicExch(a.ticket, 0u);
+            const unsigned total = atomicAdd(a.flag_count, 0u);
+            if (total > 0u) {
+                if (a.attempt == 0) {
+                    atomicAdd(&a.cnt->windows_flagged, 1ull);
+                } else {
+                    atomicAdd(&a.cnt->persistent, 1ull);
+                    emit_event(a.cnt, a.ev, a.ev_cap, a.t_last, ABFT_EV_PERSISTENT, -1, -1, -1,
+                               (double)total, 0.0, 0);
+                }
+            }
+        }
+    }
+}
+
+// First sweep of a rollback recompute: records the rollback (guarded like the recompute).
+__global__ void rollback_note_kernel(const uint32_t* guard, Counters* cnt, abft_event* ev,
+                                     int cap, int64_t t_first, int k)
+{
+    if (guard != nullptr && *guard == 0u) return;
+    if (threadIdx.x == 0) {
+        atomicAdd(&cnt->rollbacks, 1ull);
+        emit_event(cnt, ev, cap, t_first, ABFT_EV_ROLLBACK, -1, -1, k, 0.0, 0.0, 0);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Initial checksums: row sums (one wavefront per row) and column sums (one thread per column).
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) row_sums_kernel(const T* u, double cs, int nx,
+                                                        int64_t nrows, double* out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= nrows) return;
+    double p = 0.0;
+    for (int x = lane; x < nx; x += 64) p += u != nullptr ? (double)u[row * nx + x] : cs;
+    const double s = wave_sum(p);
+    if (lane == 0) out[row] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) col_sums_kernel(const T* u, double cs, int nx, int ny,
+                                                        int nz, double* out)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)nz * nx) return;
+    const int64_t z = idx / nx, x = idx % nx;
+    double s = 0.0;
+    for (int y = 0; y < ny; ++y)
+        s += u != nullptr ? (double)u[(z * ny + y) * nx + x] : cs;
+    out[idx] = s;
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void set_i64_kernel(int64_t* p, int64_t v)
+{
+    if (threadIdx.x == 0) *p = v;
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers.
+// ------------------------------------------------------------------------------------------
+bool sweep_shape_supported(int dtype, const SweepShape& s)
+{
+    const int vf = dtype == ABFT_F32 ? 4 : 2;
+    if (s.tz < 1) return false;
+    if (s.vec == vf) {
+        if (s.lpr == 16) return s.nch == 1 || s.nch == 2 || s.nch == 4;
+        if (s.lpr == 64) return s.nch == 1 || s.nch == 2 || s.nch == 4 || s.nch == 8;
+        return false;
+    }
+    if (s.vec == 1) return s.lpr == 64 && (s.nch == 4 || s.nch == 16);
+    return false;
+}
+
+int sweep_rows_per_block(const SweepShape& s) { return (kSweepBlock / 64) * (64 / s.lpr); }
+
+size_t sweep_lds_bytes(int dtype, int nx, const SweepShape& s)
+{
+    const size_t es = dtype == ABFT_F32 ? 4 : 8;
+    return 2 * (size_t)(sweep_rows_per_block(s) + 2) * (size_t)(nx + 2 * s.vec) * es;
+}
+
+hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, const SweepArgs& a,
+                        hipStream_t st)
+{
+    if (!sweep_shape_supported(dtype, s)) return hipErrorInvalidValue;
+    const size_t lds = sweep_lds_bytes(dtype, a.nx, s);
+    if (mode == MODE_PLAIN) csum = CS_F64;  // no checksum in the plain variant
+    if (dtype == ABFT_F32) {
+        if (mode == MODE_PLAIN) return launch_sweep_f32_plain(csum, s, a, st, lds);
+        if (mode == MODE_CSUM) return launch_sweep_f32_csum(csum, s, a, st, lds);
+        return launch_sweep_f32_prot(csum, s, a, st, lds);
+    }
+    if (mode == MODE_PLAIN) return launch_sweep_f64_plain(csum, s, a, st, lds);
+    if (mode == MODE_CSUM) return launch_sweep_f64_csum(csum, s, a, st, lds);
+    return launch_sweep_f64_prot(csum, s, a, st, lds);
+}
+
+size_t fixup_lds_bytes(int nx) { return (size_t)nx * (3 * sizeof(double) + 2 * sizeof(int)); }
+
+hipError_t launch_fixup(int dtype, const FixArgs& a, hipStream_t st)
+{
+    const size_t lds = fixup_lds_bytes(a.nx);
+    if (dtype == ABFT_F32)
+        hipLaunchKernelGGL(fixup_kernel<float>, dim3(1), dim3(kFixBlock), lds, st, a);
+    else
+        hipLaunchKernelGGL(fixup_kernel<double>, dim3(1), dim3(kFixBlock), lds, st, a);
+    return hipGetLastError();
+}
+
+size_t check_lds_bytes(int ry, int rz) { return (size_t)2 * ry * rz * sizeof(double); }
+
+hipError_t launch_check(const CheckArgs& a, hipStream_t st)
+{
+    hipLaunchKernelGGL(check_kernel, dim3(a.nyt * a.nzt), dim3(kCheckBlock),
+                       check_lds_bytes(a.ry_max, a.rz_max), st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rollback_note(const uint32_t* guard, Counters* cnt, abft_event* ev, int cap,
+                                int64_t t_first, int k, hipStream_t st)
+{
+    hipLaunchKernelGGL(rollback_note_kernel, dim3(1), dim3(64), 0, st, guard, cnt, ev, cap,
+                       t_first, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_sums(int dtype, const void* u, double cs, int nx, int64_t nrows,
+                           double* out, hipStream_t st)
+{
+    const dim3 grid((unsigned)((nrows + 3) / 4));
+    if (dtype == ABFT_F32)
+        hipLaunchKernelGGL(row_sums_kernel<float>, grid, dim3(256), 0, st,
+                           static_cast<const float*>(u), cs, nx, nrows, out);
+    else
+        hipLaunchKernelGGL(row_sums_kernel<double>, grid, dim3(256), 0, st,
+                           static_cast<const double*>(u), cs, nx, nrows, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_sums(int dtype, const void* u, double cs, int nx, int ny, int nz,
+                           double* out, hipStream_t st)
+{
+    const dim3 grid((unsigned)(((int64_t)nz * nx + 255) / 256));
+    if (dtype == ABFT_F32)
+        hipLaunchKernelGGL(col_sums_kernel<float>, grid, dim3(256), 0, st,
+                           static_cast<const float*>(u), cs, nx, ny, nz, out);
+    else
+        hipLaunchKernelGGL(col_sums_kernel<double>, grid, dim3(256), 0, st,
+                           static_cast<const double*>(u), cs, nx, ny, nz, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p,
+                       v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st)
+{
+    hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(64), 0, st, p, v);
+    return hipGetLastError();
+}
+
+}  // namespace abft

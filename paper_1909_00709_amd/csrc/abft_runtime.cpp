@@ -1,0 +1,996 @@
+// Host runtime of the C interface in abft_stencil.h: validation, workspace, launch shapes,
+// the online / offline / plain step sequences, graph capture, autotuning and reports.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "abft_internal.h"
+
+using namespace abft;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr int kDefaultEvents = 4096;
+constexpr size_t kLdsLimit = 64 * 1024;       // check and locate kernels
+constexpr size_t kSweepLdsLimit = 160 * 1024; // gfx950: 160 KB of LDS per compute unit
+constexpr int kTargetTiles = 1024;
+
+size_t esize(int dtype) { return dtype == ABFT_F32 ? 4 : 8; }
+
+double round_to(int dtype, double v) { return dtype == ABFT_F32 ? (double)(float)v : v; }
+
+struct CheckShape {
+    int tyi = 0, tzi = 0, nyt = 0, nzt = 0, ry = 0, rz = 0;
+};
+
+}  // namespace
+
+struct abft_ctx {
+    // problem
+    int nx = 0, ny = 0, nz = 0, dtype = 0, bc = 0;
+    Stencil st{};
+    const void* C = nullptr;
+    double cs = 0.0;
+    void* u[3] = {nullptr, nullptr, nullptr};
+    bool own_u2 = false;
+    // options
+    int mode = 0, period = 1, csum = CS_F64, auto_correct = 1;
+    double eps = 0.0;
+    std::string cache_path;
+    hipStream_t stream = nullptr;
+    // workspace
+    std::vector<void*> allocs;
+    double* B[2] = {nullptr, nullptr};
+    double* cB = nullptr;
+    double* cA = nullptr;
+    FlagSlot* slot[2] = {nullptr, nullptr};
+    Counters* cnt = nullptr;
+    abft_event* ev = nullptr;
+    int ev_cap = 0;
+    uint32_t* win = nullptr;     // [2 windows][first, recheck]
+    uint32_t* ticket = nullptr;
+    int64_t* tbase = nullptr;
+    double* E = nullptr;         // [period][nz][ny] when the boundary terms do not cancel
+    abft_fault* faults = nullptr;
+    int32_t* fault_first = nullptr;
+    int64_t fault_tmax = 0;
+    int nfaults = 0;
+    // launch shapes
+    SweepShape shape{};
+    int nyb = 0, nzb = 0, ntiles = 0;
+    CheckShape ck;
+    // trajectory state
+    int64_t t = 0;
+    int cur = 0, bcur = 0;
+    // offline state
+    int ckpt = 0, wq = 1, wr = 2, bck = 0;
+    int64_t win_t0 = 0, win_index = 0;
+    int win_j = 0;
+    bool halted = false;
+    int64_t skipped = 0;
+    // graphs
+    std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+    std::string err;
+};
+
+namespace {
+
+abft_status fail(abft_ctx* c, abft_status s, const std::string& msg)
+{
+    if (c) c->err = msg;
+    else g_init_error = msg;
+    return s;
+}
+
+abft_status hip_fail(abft_ctx* c, hipError_t e, const char* what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, ABFT_E_HIP, m);
+}
+
+#define HIPCHK(ctx, expr)                                           \
+    do {                                                            \
+        hipError_t _e = (expr);                                     \
+        if (_e != hipSuccess) return hip_fail((ctx), _e, #expr);    \
+    } while (0)
+
+template <typename P>
+abft_status dalloc(abft_ctx* c, P** p, size_t bytes)
+{
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, ABFT_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    c->allocs.push_back(q);
+    *p = static_cast<P*>(q);
+    return ABFT_OK;
+}
+
+void free_all(abft_ctx* c)
+{
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    for (void* p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+}
+
+// Radius-1 star taps -> weight slots.
+abft_status map_taps(abft_ctx* c, const abft_problem* p)
+{
+    c->st = Stencil{};
+    c->st.bc = p->bc;
+    c->st.g = round_to(p->dtype, p->bc_value);
+    for (int k = 0; k < p->ntaps; ++k) {
+        const abft_tap& t = p->taps[k];
+        const int ad = std::abs(t.dx) + std::abs(t.dy) + std::abs(t.dz);
+        if (ad > 1)
+            return fail(c, ABFT_E_UNSUPPORTED,
+                        "GPU kernels cover the radius-1 star (centre and six face neighbours)");
+        int slot;
+        if (t.dx == -1) slot = W_XM;
+        else if (t.dx == 1) slot = W_XP;
+        else if (t.dy == -1) slot = W_YM;
+        else if (t.dy == 1) slot = W_YP;
+        else if (t.dz == -1) slot = W_ZM;
+        else if (t.dz == 1) slot = W_ZP;
+        else slot = W_C;
+        if (c->st.mask & (1u << slot)) return fail(c, ABFT_E_INVAL, "duplicate tap offset");
+        if (!std::isfinite(t.w)) return fail(c, ABFT_E_INVAL, "non-finite tap weight");
+        c->st.mask |= 1u << slot;
+        c->st.w[slot] = round_to(p->dtype, t.w);
+    }
+    return ABFT_OK;
+}
+
+// Default launch shape: 16-byte accesses when rows are 16-byte multiples, 16 lanes per row for
+// short rows (4 rows per wavefront), 64 lanes for long rows, and enough z-slabs for ~1024
+// blocks.
+bool default_shape(int dtype, int nx, int ny, int nz, SweepShape* s)
+{
+    const int vf = 16 / (int)esize(dtype);
+    SweepShape r{};
+    if (nx % vf == 0) {
+        r.vec = vf;
+        if (nx <= 16 * vf * 4) {
+            r.lpr = 16;
+            const int n = (nx + 16 * vf - 1) / (16 * vf);
+            r.nch = n <= 1 ? 1 : n <= 2 ? 2 : 4;
+        } else {
+            r.lpr = 64;
+            const int n = (nx + 64 * vf - 1) / (64 * vf);
+            if (n > 8) return false;
+            r.nch = n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : 8;
+        }
+    } else {
+        r.vec = 1;
+        r.lpr = 64;
+        if (nx <= 256) r.nch = 4;
+        else if (nx <= 1024) r.nch = 16;
+        else return false;
+    }
+    const int ty = sweep_rows_per_block(r);
+    const int nyb = (ny + ty - 1) / ty;
+    int nzb = std::max(1, std::min(nz, (kTargetTiles + nyb - 1) / nyb));
+    r.tz = (nz + nzb - 1) / nzb;
+    *s = r;
+    return true;
+}
+
+abft_status apply_shape(abft_ctx* c, const SweepShape& s)
+{
+    if (!sweep_shape_supported(c->dtype, s)) return fail(c, ABFT_E_UNSUPPORTED, "launch shape");
+    if ((int64_t)s.lpr * s.nch * s.vec < c->nx) return fail(c, ABFT_E_UNSUPPORTED, "row too long");
+    if (s.vec > 1 && c->nx % s.vec) return fail(c, ABFT_E_UNSUPPORTED, "row not 16-byte multiple");
+    if (sweep_lds_bytes(c->dtype, c->nx, s) > kSweepLdsLimit)
+        return fail(c, ABFT_E_UNSUPPORTED, "rows too long for the LDS plane buffers");
+    const int ty = sweep_rows_per_block(s);
+    const int64_t nyb = (c->ny + ty - 1) / ty;
+    const int64_t nzb = (c->nz + s.tz - 1) / s.tz;
+    if (nyb * nzb > (int64_t)1 << 30) return fail(c, ABFT_E_UNSUPPORTED, "grid too large");
+    c->shape = s;
+    c->nyb = (int)nyb;
+    c->nzb = (int)nzb;
+    c->ntiles = (int)(nyb * nzb);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    return ABFT_OK;
+}
+
+std::string cache_key(const abft_ctx* c)
+{
+    std::ostringstream o;
+    o << c->dtype << ' ' << c->nx << ' ' << c->ny << ' ' << c->nz << ' ' << c->mode << ' '
+      << c->csum;
+    return o.str();
+}
+
+bool cache_lookup(const abft_ctx* c, SweepShape* s)
+{
+    if (c->cache_path.empty()) return false;
+    std::ifstream f(c->cache_path);
+    if (!f) return false;
+    const std::string key = cache_key(c);
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream in(line);
+        int d, nx, ny, nz, m, cs;
+        SweepShape r{};
+        if (!(in >> d >> nx >> ny >> nz >> m >> cs >> r.lpr >> r.nch >> r.vec >> r.tz)) continue;
+        std::ostringstream k;
+        k << d << ' ' << nx << ' ' << ny << ' ' << nz << ' ' << m << ' ' << cs;
+        if (k.str() == key) {
+            *s = r;
+            found = true;
+        }
+    }
+    return found;
+}
+
+void cache_store(const abft_ctx* c)
+{
+    if (c->cache_path.empty()) return;
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(c->cache_path);
+        std::string line;
+        const std::string key = cache_key(c);
+        while (f && std::getline(f, line))
+            if (line.compare(0, key.size() + 1, key + " ") != 0 && !line.empty())
+                keep.push_back(line);
+    }
+    std::ofstream f(c->cache_path, std::ios::trunc);
+    for (auto& l : keep) f << l << '\n';
+    f << cache_key(c) << ' ' << c->shape.lpr << ' ' << c->shape.nch << ' ' << c->shape.vec << ' '
+      << c->shape.tz << '\n';
+}
+
+// Offline check tiles: 64 rows x up to 16 layers of the checksum plane plus a k halo.
+void check_shape(abft_ctx* c, int k)
+{
+    CheckShape s;
+    const bool per = c->bc == ABFT_BC_PERIODIC;
+    s.tzi = std::min(c->nz, 16);
+    s.tyi = std::min(c->ny, 64);
+    for (;;) {
+        const int ry = per ? s.tyi + 2 * k : std::min(c->ny, s.tyi + 2 * k);
+        const int rz = per ? s.tzi + 2 * k : std::min(c->nz, s.tzi + 2 * k);
+        if (check_lds_bytes(ry, rz) <= kLdsLimit || (s.tyi == 1 && s.tzi == 1)) {
+            s.ry = ry;
+            s.rz = rz;
+            break;
+        }
+        if (s.tyi > s.tzi && s.tyi > 1) s.tyi = (s.tyi + 1) / 2;
+        else s.tzi = (s.tzi + 1) / 2;
+    }
+    s.nyt = (c->ny + s.tyi - 1) / s.tyi;
+    s.nzt = (c->nz + s.tzi - 1) / s.tzi;
+    c->ck = s;
+}
+
+SweepArgs base_args(const abft_ctx* c)
+{
+    SweepArgs a{};
+    a.C = c->C;
+    a.c_scalar = c->cs;
+    a.st = c->st;
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.nz = c->nz;
+    a.tz = c->shape.tz;
+    a.nyb = c->nyb;
+    a.ntiles = c->ntiles;
+    a.cB = c->cB;
+    a.eps = c->eps;
+    a.cnt = c->cnt;
+    a.ev = c->ev;
+    a.ev_cap = c->ev_cap;
+    a.faults = c->faults;
+    a.fault_first = c->fault_first;
+    a.fault_tmax = c->faults ? c->fault_tmax : 0;
+    return a;
+}
+
+bool need_boundary_terms(const abft_ctx* c)
+{
+    if (c->bc == ABFT_BC_PERIODIC) return false;
+    const bool xm = c->st.mask & (1u << W_XM), xp = c->st.mask & (1u << W_XP);
+    if (c->bc == ABFT_BC_CLAMP) return (xm != xp) || (xm && c->st.w[W_XM] != c->st.w[W_XP]);
+    return xm || xp;
+}
+
+int buf_of(const abft_ctx* c, int j) { return j == 0 ? c->ckpt : ((j & 1) ? c->wq : c->wr); }
+
+// ---- online / plain ------------------------------------------------------------------------
+abft_status enqueue_online(abft_ctx* c, int64_t n, const int64_t* tbase, int64_t t0)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t t = c->t + i;
+        SweepArgs a = base_args(c);
+        a.uin = c->u[c->cur];
+        a.uout = c->u[c->cur ^ 1];
+        a.t_base = tbase;
+        a.t_off = tbase ? t - t0 : t;
+        int mode = MODE_PLAIN;
+        if (c->mode == ABFT_MODE_ONLINE) {
+            mode = MODE_PROT;
+            a.Bt = c->B[c->bcur];
+            a.Bn = c->B[c->bcur ^ 1];
+            a.slot = c->slot[t & 1];
+            a.zero_ptr = &c->slot[(t + 1) & 1]->count;
+            a.zero_n = 1;
+        }
+        hipError_t e = launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
+        if (c->mode == ABFT_MODE_ONLINE && c->auto_correct) {
+            FixArgs f{};
+            f.uin = c->u[c->cur];
+            f.uout = c->u[c->cur ^ 1];
+            f.Bn = c->B[c->bcur ^ 1];
+            f.cA = c->cA;
+            f.st = c->st;
+            f.nx = c->nx;
+            f.ny = c->ny;
+            f.nz = c->nz;
+            f.eps = c->eps;
+            f.slot = c->slot[t & 1];
+            f.cnt = c->cnt;
+            f.ev = c->ev;
+            f.ev_cap = c->ev_cap;
+            f.t_base = tbase;
+            f.t_off = a.t_off;
+            e = launch_fixup(c->dtype, f, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "locate/correct launch");
+        }
+        c->cur ^= 1;
+        if (c->mode == ABFT_MODE_ONLINE) c->bcur ^= 1;
+    }
+    c->t += n;
+    return ABFT_OK;
+}
+
+// ---- offline ------------------------------------------------------------------------------
+abft_status offline_sweep(abft_ctx* c, int j, int k, int attempt, const uint32_t* guard)
+{
+    SweepArgs a = base_args(c);
+    a.uin = c->u[buf_of(c, j)];
+    a.uout = c->u[buf_of(c, j + 1)];
+    a.t_off = c->win_t0 + j;
+    a.attempt = attempt;
+    a.guard = guard;
+    a.Bn = c->B[c->bck ^ 1];
+    if (c->E) a.E = c->E + (size_t)j * c->nz * c->ny;
+    if (j == 0 && attempt == 0) {
+        a.zero_ptr = c->win + 2 * (c->win_index & 1);
+        a.zero_n = 2;
+    }
+    const int mode = (j == k - 1) ? MODE_CSUM : MODE_PLAIN;
+    hipError_t e = launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "offline sweep launch");
+    return ABFT_OK;
+}
+
+abft_status offline_check(abft_ctx* c, int k, int attempt, const uint32_t* guard)
+{
+    check_shape(c, k);
+    CheckArgs a{};
+    a.Bck = c->B[c->bck];
+    a.Bdir = c->B[c->bck ^ 1];
+    a.cB = c->cB;
+    a.E = c->E;
+    a.st = c->st;
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.nz = c->nz;
+    a.k = k;
+    a.eps = c->eps;
+    a.tyi = c->ck.tyi;
+    a.tzi = c->ck.tzi;
+    a.nyt = c->ck.nyt;
+    a.nzt = c->ck.nzt;
+    a.ry_max = c->ck.ry;
+    a.rz_max = c->ck.rz;
+    uint32_t* w = c->win + 2 * (c->win_index & 1);
+    a.flag_count = attempt == 0 ? w : w + 1;
+    a.guard = guard;
+    a.ticket = c->ticket;
+    a.cnt = c->cnt;
+    a.ev = c->ev;
+    a.ev_cap = c->ev_cap;
+    a.attempt = attempt;
+    a.auto_correct = c->auto_correct;
+    a.t_first = c->win_t0;
+    a.t_last = c->win_t0 + k - 1;
+    hipError_t e = launch_check(a, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "offline check launch");
+    return ABFT_OK;
+}
+
+void offline_rotate(abft_ctx* c, int k)
+{
+    const int nb = buf_of(c, k);
+    int others[2], m = 0;
+    for (int b = 0; b < 3; ++b)
+        if (b != nb) others[m++] = b;
+    c->ckpt = nb;
+    c->wq = others[0];
+    c->wr = others[1];
+    c->bck ^= 1;
+    c->win_t0 += k;
+    c->win_j = 0;
+    c->win_index++;
+    c->cur = c->ckpt;
+}
+
+// Recompute of the window from the checkpoint (attempt 1) and its re-check.
+abft_status offline_recompute(abft_ctx* c, int k, const uint32_t* guard)
+{
+    hipError_t e = launch_rollback_note(guard, c->cnt, c->ev, c->ev_cap, c->win_t0, k, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "rollback launch");
+    for (int j = 0; j < k; ++j) {
+        abft_status s = offline_sweep(c, j, k, 1, guard);
+        if (s) return s;
+    }
+    return offline_check(c, k, 1, guard);
+}
+
+abft_status offline_close_window(abft_ctx* c, int k)
+{
+    abft_status s = offline_check(c, k, 0, nullptr);
+    if (s) return s;
+    uint32_t* w = c->win + 2 * (c->win_index & 1);
+    if (c->auto_correct) {
+        s = offline_recompute(c, k, w);
+        if (s) return s;
+        offline_rotate(c, k);
+        return ABFT_OK;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    uint32_t flagged = 0;
+    HIPCHK(c, hipMemcpy(&flagged, w, sizeof(flagged), hipMemcpyDeviceToHost));
+    if (flagged) {
+        c->halted = true;
+        c->win_j = k;  // the window's sweeps are done; its result awaits correct()
+        return ABFT_OK;
+    }
+    offline_rotate(c, k);
+    return ABFT_OK;
+}
+
+abft_status enqueue_offline(abft_ctx* c, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        if (c->halted) {
+            c->skipped += n - i;
+            return ABFT_OK;
+        }
+        const int j = c->win_j;
+        abft_status s = offline_sweep(c, j, c->period, 0, nullptr);
+        if (s) return s;
+        c->win_j = j + 1;
+        c->t++;
+        c->cur = buf_of(c, c->win_j);
+        if (c->win_j == c->period) {
+            s = offline_close_window(c, c->period);
+            if (s) return s;
+        }
+    }
+    return ABFT_OK;
+}
+
+// "After completion" detection: a partial window is checked now and closed.
+abft_status offline_flush(abft_ctx* c)
+{
+    if (c->halted || c->win_j == 0) return ABFT_OK;
+    const int k = c->win_j;
+    hipError_t e = launch_row_sums(c->dtype, c->u[buf_of(c, k)], 0.0, c->nx,
+                                   (int64_t)c->nz * c->ny, c->B[c->bck ^ 1], c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "row checksum launch");
+    return offline_close_window(c, k);
+}
+
+abft_status read_counters(abft_ctx* c, Counters* h)
+{
+    HIPCHK(c, hipMemcpy(h, c->cnt, sizeof(Counters), hipMemcpyDeviceToHost));
+    return ABFT_OK;
+}
+
+abft_status validate_problem(const abft_problem* p)
+{
+    if (!p) return fail(nullptr, ABFT_E_INVAL, "problem is NULL");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(nullptr, ABFT_E_INVAL, "extent < 1");
+    if ((int64_t)p->nx * p->ny * p->nz > ((int64_t)1 << 40))
+        return fail(nullptr, ABFT_E_INVAL, "grid too large");
+    if (p->dtype != ABFT_F32 && p->dtype != ABFT_F64)
+        return fail(nullptr, ABFT_E_INVAL, "dtype");
+    if (p->bc < ABFT_BC_CLAMP || p->bc > ABFT_BC_CONSTANT)
+        return fail(nullptr, ABFT_E_INVAL, "boundary rule");
+    if (p->ntaps < 1 || p->ntaps > 7 || !p->taps)
+        return fail(nullptr, ABFT_E_INVAL, "taps (1..7 required)");
+    if (!p->u0 || !p->u1 || p->u0 == p->u1)
+        return fail(nullptr, ABFT_E_INVAL, "u0 and u1 must be distinct device buffers");
+    if (!std::isfinite(p->bc_value) || !std::isfinite(p->cterm_scalar))
+        return fail(nullptr, ABFT_E_INVAL, "non-finite constant");
+    return ABFT_OK;
+}
+
+abft_status validate_options(const abft_problem* p, const abft_options* o)
+{
+    if (!o) return fail(nullptr, ABFT_E_INVAL, "options is NULL");
+    if (o->mode < ABFT_MODE_NONE || o->mode > ABFT_MODE_OFFLINE)
+        return fail(nullptr, ABFT_E_INVAL, "mode");
+    if (o->mode == ABFT_MODE_OFFLINE && o->period < 1)
+        return fail(nullptr, ABFT_E_INVAL, "period must be >= 1");
+    if (o->mode == ABFT_MODE_OFFLINE && o->period > kMaxPeriod)
+        return fail(nullptr, ABFT_E_UNSUPPORTED, "period above 32");
+    if (o->mode != ABFT_MODE_NONE && !(o->threshold > 0.0 && std::isfinite(o->threshold)))
+        return fail(nullptr, ABFT_E_INVAL, "threshold must be > 0");
+    if (o->csum != ABFT_CSUM_F64 && o->csum != ABFT_CSUM_F32_COMP)
+        return fail(nullptr, ABFT_E_INVAL, "checksum accumulation");
+    if (o->csum == ABFT_CSUM_F32_COMP && p->dtype != ABFT_F32)
+        return fail(nullptr, ABFT_E_INVAL, "compensated fp32 checksums need an fp32 grid");
+    if (o->max_events < 0) return fail(nullptr, ABFT_E_INVAL, "max_events");
+    return ABFT_OK;
+}
+
+}  // namespace
+
+// ==========================================================================================
+extern "C" {
+
+const char* abft_strerror(abft_status s)
+{
+    switch (s) {
+    case ABFT_OK: return "ok";
+    case ABFT_E_INVAL: return "invalid argument";
+    case ABFT_E_UNSUPPORTED: return "not supported by the GPU kernels";
+    case ABFT_E_NOMEM: return "out of memory";
+    case ABFT_E_HIP: return "HIP runtime error";
+    case ABFT_E_STATE: return "call not allowed in the current state";
+    case ABFT_E_UNCORRECTABLE: return "detected corruption could not be corrected";
+    }
+    return "unknown status";
+}
+
+const char* abft_last_error(const abft_ctx* ctx)
+{
+    return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void* hip_stream,
+                              abft_ctx** out)
+{
+    g_init_error.clear();
+    if (!out) return fail(nullptr, ABFT_E_INVAL, "out is NULL");
+    *out = nullptr;
+    abft_status s = validate_problem(p);
+    if (s) return s;
+    s = validate_options(p, o);
+    if (s) return s;
+
+    abft_ctx* c = new abft_ctx();
+    c->nx = p->nx;
+    c->ny = p->ny;
+    c->nz = p->nz;
+    c->dtype = p->dtype;
+    c->bc = p->bc;
+    c->C = p->cterm;
+    c->cs = round_to(p->dtype, p->cterm_scalar);
+    c->u[0] = p->u0;
+    c->u[1] = p->u1;
+    c->mode = o->mode;
+    c->period = o->mode == ABFT_MODE_OFFLINE ? o->period : 1;
+    c->eps = o->threshold;
+    c->csum = o->csum == ABFT_CSUM_F32_COMP ? CS_F32C : CS_F64;
+    c->auto_correct = o->auto_correct ? 1 : 0;
+    c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
+    if (o->tuning_cache) c->cache_path = o->tuning_cache;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+
+    auto bail = [&](abft_status st) {
+        g_init_error = c->err;
+        free_all(c);
+        delete c;
+        return st;
+    };
+
+    s = map_taps(c, p);
+    if (s) return bail(s);
+    SweepShape shape{};
+    if (!cache_lookup(c, &shape) || !sweep_shape_supported(c->dtype, shape)) {
+        if (!default_shape(c->dtype, c->nx, c->ny, c->nz, &shape))
+            return bail(fail(c, ABFT_E_UNSUPPORTED, "row length beyond the GPU kernels"));
+    }
+    s = apply_shape(c, shape);
+    if (s) return bail(s);
+    if (fixup_lds_bytes(c->nx) > kLdsLimit || c->nx > 4 * kFixBlock)
+        return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
+
+    const size_t nrows = (size_t)c->nz * c->ny, ncols = (size_t)c->nz * c->nx;
+    const size_t gbytes = (size_t)c->nx * c->ny * c->nz * esize(c->dtype);
+    if ((s = dalloc(c, &c->B[0], nrows * 8)) || (s = dalloc(c, &c->B[1], nrows * 8)) ||
+        (s = dalloc(c, &c->cB, nrows * 8)) || (s = dalloc(c, &c->cA, ncols * 8)) ||
+        (s = dalloc(c, &c->slot[0], sizeof(FlagSlot))) ||
+        (s = dalloc(c, &c->slot[1], sizeof(FlagSlot))) ||
+        (s = dalloc(c, &c->cnt, sizeof(Counters))) ||
+        (s = dalloc(c, &c->ev, (size_t)c->ev_cap * sizeof(abft_event))) ||
+        (s = dalloc(c, &c->win, 4 * sizeof(uint32_t))) ||
+        (s = dalloc(c, &c->ticket, 4 * sizeof(uint32_t))) ||
+        (s = dalloc(c, &c->tbase, sizeof(int64_t))))
+        return bail(s);
+    if (c->mode == ABFT_MODE_OFFLINE) {
+        if (p->u2 != nullptr) {
+            if (p->u2 == p->u0 || p->u2 == p->u1)
+                return bail(fail(c, ABFT_E_INVAL, "u2 must differ from u0 and u1"));
+            c->u[2] = p->u2;
+        } else {
+            if ((s = dalloc(c, &c->u[2], gbytes))) return bail(s);
+            c->own_u2 = true;
+        }
+        if (need_boundary_terms(c) && (s = dalloc(c, &c->E, (size_t)c->period * nrows * 8)))
+            return bail(s);
+    }
+
+    hipError_t e;
+#define INIT_CHK(expr)                                      \
+    if ((e = (expr)) != hipSuccess) {                       \
+        hip_fail(c, e, #expr);                              \
+        return bail(ABFT_E_HIP);                            \
+    }
+    INIT_CHK(launch_fill_u32(reinterpret_cast<uint32_t*>(c->cnt), 0u,
+                             sizeof(Counters) / 4, c->stream));
+    INIT_CHK(launch_fill_u32(&c->slot[0]->count, 0u, 2, c->stream));
+    INIT_CHK(launch_fill_u32(&c->slot[1]->count, 0u, 2, c->stream));
+    INIT_CHK(launch_fill_u32(c->win, 0u, 4, c->stream));
+    INIT_CHK(launch_fill_u32(c->ticket, 0u, 4, c->stream));
+    INIT_CHK(launch_set_i64(c->tbase, 0, c->stream));
+    // Theorem 1's constant-term checksums and the checksums of u^0
+    INIT_CHK(launch_row_sums(c->dtype, c->C, c->cs, c->nx, (int64_t)nrows, c->cB, c->stream));
+    INIT_CHK(launch_col_sums(c->dtype, c->C, c->cs, c->nx, c->ny, c->nz, c->cA, c->stream));
+    INIT_CHK(launch_row_sums(c->dtype, c->u[0], 0.0, c->nx, (int64_t)nrows, c->B[0], c->stream));
+    INIT_CHK(hipStreamSynchronize(c->stream));
+#undef INIT_CHK
+    *out = c;
+    return ABFT_OK;
+}
+
+abft_status abft_stencil_step(abft_ctx* c, int64_t nsweeps)
+{
+    if (!c) return ABFT_E_INVAL;
+    if (nsweeps < 0) return fail(c, ABFT_E_INVAL, "nsweeps < 0");
+    if (c->halted) return fail(c, ABFT_E_STATE, "offline window awaits abft_stencil_correct");
+    if (c->mode == ABFT_MODE_OFFLINE) return enqueue_offline(c, nsweeps);
+    return enqueue_online(c, nsweeps, nullptr, 0);
+}
+
+abft_status abft_stencil_step_graph(abft_ctx* c, int64_t nsweeps)
+{
+    if (!c) return ABFT_E_INVAL;
+    if (nsweeps < 0) return fail(c, ABFT_E_INVAL, "nsweeps < 0");
+    if (nsweeps == 0) return ABFT_OK;
+    if (c->mode == ABFT_MODE_OFFLINE)
+        return fail(c, ABFT_E_UNSUPPORTED, "graph steps cover the online and plain modes");
+    if (c->stream == nullptr)
+        return fail(c, ABFT_E_UNSUPPORTED, "graph capture needs a non-null stream");
+    hipError_t e = launch_set_i64(c->tbase, c->t, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "sweep base");
+    const auto key = std::make_pair(nsweeps, c->cur);
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        const int64_t t_save = c->t;
+        const int cur_save = c->cur, bcur_save = c->bcur;
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+        abft_status s = enqueue_online(c, nsweeps, c->tbase, t_save);
+        hipGraph_t g = nullptr;
+        hipError_t ce = hipStreamEndCapture(c->stream, &g);
+        c->t = t_save;
+        c->cur = cur_save;
+        c->bcur = bcur_save;
+        if (s) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (ce != hipSuccess) return hip_fail(c, ce, "hipStreamEndCapture");
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+        it = c->graphs.emplace(key, ex).first;
+    }
+    HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+    c->t += nsweeps;
+    if (nsweeps & 1) {
+        c->cur ^= 1;
+        if (c->mode == ABFT_MODE_ONLINE) c->bcur ^= 1;
+    }
+    return ABFT_OK;
+}
+
+abft_status abft_stencil_check(abft_ctx* c, abft_report* out)
+{
+    if (!c) return ABFT_E_INVAL;
+    if (c->mode == ABFT_MODE_OFFLINE) {
+        abft_status s = offline_flush(c);
+        if (s) return s;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    Counters h{};
+    abft_status s = read_counters(c, &h);
+    if (s) return s;
+    int64_t pending = 0;
+    if (c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
+        uint32_t n = 0;
+        HIPCHK(c, hipMemcpy(&n, &c->slot[(c->t - 1) & 1]->count, 4, hipMemcpyDeviceToHost));
+        pending = n;
+    } else if (c->halted) {
+        uint32_t n = 0;
+        HIPCHK(c, hipMemcpy(&n, c->win + 2 * (c->win_index & 1), 4, hipMemcpyDeviceToHost));
+        pending = n;
+    }
+    if (out) {
+        out->sweeps_done = c->mode == ABFT_MODE_OFFLINE ? c->win_t0 + c->win_j : c->t;
+        out->rows_flagged = (int64_t)h.rows_flagged;
+        out->cols_flagged = (int64_t)h.cols_flagged;
+        out->corrected = (int64_t)h.corrected;
+        out->checksum_faults = (int64_t)h.checksum_faults;
+        out->uncorrectable = (int64_t)h.uncorrectable;
+        out->windows_checked = (int64_t)h.windows_checked;
+        out->windows_flagged = (int64_t)h.windows_flagged;
+        out->rollbacks = (int64_t)h.rollbacks;
+        out->persistent = (int64_t)h.persistent;
+        out->events_total = (int64_t)h.events_total;
+        out->pending = pending;
+        out->sweeps_skipped = c->skipped;
+        double nm = 0.0;
+        std::memcpy(&nm, &h.noise_bits, sizeof(nm));
+        out->max_noise = nm;
+        out->nevents = 0;
+        if (out->events && out->events_cap > 0) {
+            const int64_t n =
+                std::min<int64_t>({(int64_t)h.events_total, (int64_t)c->ev_cap,
+                                   (int64_t)out->events_cap});
+            if (n > 0)
+                HIPCHK(c, hipMemcpy(out->events, c->ev, (size_t)n * sizeof(abft_event),
+                                    hipMemcpyDeviceToHost));
+            out->nevents = (int32_t)n;
+        }
+    }
+    return ABFT_OK;
+}
+
+abft_status abft_stencil_correct(abft_ctx* c, abft_report* inout)
+{
+    if (!c) return ABFT_E_INVAL;
+    Counters before{};
+    abft_status s = read_counters(c, &before);
+    if (s) return s;
+    if (c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
+        const int64_t t = c->t - 1;
+        FixArgs f{};
+        f.uin = c->u[c->cur ^ 1];
+        f.uout = c->u[c->cur];
+        f.Bn = c->B[c->bcur];
+        f.cA = c->cA;
+        f.st = c->st;
+        f.nx = c->nx;
+        f.ny = c->ny;
+        f.nz = c->nz;
+        f.eps = c->eps;
+        f.slot = c->slot[t & 1];
+        f.cnt = c->cnt;
+        f.ev = c->ev;
+        f.ev_cap = c->ev_cap;
+        f.t_off = t;
+        hipError_t e = launch_fixup(c->dtype, f, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "locate/correct launch");
+    } else if (c->mode == ABFT_MODE_OFFLINE && c->halted) {
+        const int k = c->win_j;
+        s = offline_recompute(c, k, nullptr);
+        if (s) return s;
+        c->halted = false;
+        offline_rotate(c, k);
+    }
+    s = abft_stencil_check(c, inout);
+    if (s) return s;
+    Counters after{};
+    s = read_counters(c, &after);
+    if (s) return s;
+    if (after.uncorrectable > before.uncorrectable || after.persistent > before.persistent)
+        return fail(c, ABFT_E_UNCORRECTABLE, "detection could not be corrected");
+    return ABFT_OK;
+}
+
+abft_status abft_stencil_current(abft_ctx* c, int32_t grid, void** dev_ptr, int64_t* sweep)
+{
+    if (!c || grid != 0) return ABFT_E_INVAL;
+    if (dev_ptr) *dev_ptr = c->u[c->cur];
+    if (sweep) *sweep = c->mode == ABFT_MODE_OFFLINE ? c->win_t0 + c->win_j : c->t;
+    return ABFT_OK;
+}
+
+abft_status abft_stencil_checksums(abft_ctx* c, int32_t grid, double** dev_ptr)
+{
+    if (!c || grid != 0 || !dev_ptr) return ABFT_E_INVAL;
+    *dev_ptr = c->mode == ABFT_MODE_OFFLINE ? c->B[c->bck] : c->B[c->bcur];
+    return ABFT_OK;
+}
+
+abft_status abft_stencil_inject(abft_ctx* c, const abft_fault* f, int32_t n)
+{
+    if (!c || n < 0 || (n > 0 && !f)) return c ? fail(c, ABFT_E_INVAL, "fault plan") : ABFT_E_INVAL;
+    const int bits = c->dtype == ABFT_F32 ? 32 : 64;
+    std::vector<abft_fault> v(f, f + n);
+    for (const auto& x : v)
+        if (x.sweep < 0 || x.z < 0 || x.z >= c->nz || x.y < 0 || x.y >= c->ny || x.x < 0 ||
+            x.x >= c->nx || x.bit < 0 || x.bit >= bits || x.attempt < 0 || x.attempt > 1 ||
+            x.grid != 0)
+            return fail(c, ABFT_E_INVAL, "fault outside the grid or word");
+    std::stable_sort(v.begin(), v.end(),
+                     [](const abft_fault& a, const abft_fault& b) { return a.sweep < b.sweep; });
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // drop the old plan
+    for (void* p : {static_cast<void*>(c->faults), static_cast<void*>(c->fault_first)}) {
+        if (!p) continue;
+        auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+        if (it != c->allocs.end()) c->allocs.erase(it);
+        (void)hipFree(p);
+    }
+    c->faults = nullptr;
+    c->fault_first = nullptr;
+    c->fault_tmax = 0;
+    c->nfaults = 0;
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    if (n == 0) return ABFT_OK;
+    const int64_t tmax = v.back().sweep + 1;
+    if (tmax > (int64_t)1 << 26) return fail(c, ABFT_E_INVAL, "fault sweep index too large");
+    std::vector<int32_t> first((size_t)tmax + 1);
+    size_t i = 0;
+    for (int64_t t = 0; t <= tmax; ++t) {
+        while (i < v.size() && v[i].sweep < t) ++i;
+        first[(size_t)t] = (int32_t)i;
+    }
+    abft_status s;
+    if ((s = dalloc(c, &c->faults, v.size() * sizeof(abft_fault))) ||
+        (s = dalloc(c, &c->fault_first, first.size() * sizeof(int32_t))))
+        return s;
+    HIPCHK(c, hipMemcpy(c->faults, v.data(), v.size() * sizeof(abft_fault),
+                        hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->fault_first, first.data(), first.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice));
+    c->fault_tmax = tmax;
+    c->nfaults = n;
+    return ABFT_OK;
+}
+
+abft_status abft_stencil_autotune(abft_ctx* c)
+{
+    if (!c) return ABFT_E_INVAL;
+    if (c->mode == ABFT_MODE_OFFLINE && (c->win_j != 0 || c->halted))
+        return fail(c, ABFT_E_STATE, "autotune in offline mode needs a closed window");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // scratch control structures so that timing runs leave the context's state untouched
+    FlagSlot* sslot = nullptr;
+    Counters* scnt = nullptr;
+    double* sB = nullptr;
+    abft_status s;
+    const size_t nrows = (size_t)c->nz * c->ny;
+    if ((s = dalloc(c, &sslot, sizeof(FlagSlot))) || (s = dalloc(c, &scnt, sizeof(Counters))) ||
+        (s = dalloc(c, &sB, nrows * 8)))
+        return s;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const int vf = 16 / (int)esize(c->dtype);
+    std::vector<SweepShape> cands;
+    for (int vec : {vf, 1}) {
+        if (vec > 1 && c->nx % vec) continue;
+        for (int lpr : {16, 64})
+            for (int nch : {1, 2, 4, 8, 16}) {
+                SweepShape sh{lpr, nch, vec, 1};
+                if (!sweep_shape_supported(c->dtype, sh)) continue;
+                if ((int64_t)lpr * nch * vec < c->nx) continue;
+                if ((int64_t)lpr * (nch / 2) * vec >= c->nx && nch > 1) continue;  // minimal nch
+                if (sweep_lds_bytes(c->dtype, c->nx, sh) > kSweepLdsLimit) continue;
+                for (int tz : {2, 4, 8, 16, 32, 64, 128}) {
+                    if (tz > c->nz && tz != 2) continue;
+                    sh.tz = std::min(tz, c->nz);
+                    cands.push_back(sh);
+                }
+            }
+        if (!cands.empty()) break;  // prefer 16-byte accesses when they apply
+    }
+    const SweepShape keep = c->shape;
+    SweepShape best = keep;
+    float best_ms = 1e30f;
+    const int mode = c->mode == ABFT_MODE_ONLINE ? MODE_PROT : MODE_PLAIN;
+    for (const SweepShape& sh : cands) {
+        if (apply_shape(c, sh)) continue;
+        SweepArgs a = base_args(c);
+        a.uin = c->u[c->cur];
+        a.uout = c->u[c->cur ^ (c->mode == ABFT_MODE_OFFLINE ? 0 : 1)];
+        if (c->mode == ABFT_MODE_OFFLINE) a.uout = c->u[buf_of(c, 1)];
+        a.faults = nullptr;
+        a.cnt = scnt;
+        a.ev = nullptr;
+        a.ev_cap = 0;
+        a.slot = sslot;
+        a.Bt = c->mode == ABFT_MODE_OFFLINE ? c->B[c->bck] : c->B[c->bcur];
+        a.Bn = sB;
+        a.t_off = c->t;
+        bool ok = true;
+        for (int w = 0; w < 2 && ok; ++w)
+            ok = launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            continue;
+        }
+        const int reps = 5;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int r = 0; r < reps; ++r)
+            (void)launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream);
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (void* p : {static_cast<void*>(sslot), static_cast<void*>(scnt), static_cast<void*>(sB)}) {
+        auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+        if (it != c->allocs.end()) c->allocs.erase(it);
+        (void)hipFree(p);
+    }
+    s = apply_shape(c, best);
+    if (s) return s;
+    cache_store(c);
+    return ABFT_OK;
+}
+
+abft_status abft_stencil_launch_shape(const abft_ctx* c, int32_t* rows_per_block,
+                                      int32_t* planes_per_block, int32_t* lanes_per_row)
+{
+    if (!c) return ABFT_E_INVAL;
+    if (rows_per_block) *rows_per_block = sweep_rows_per_block(c->shape);
+    if (planes_per_block) *planes_per_block = c->shape.tz;
+    if (lanes_per_row) *lanes_per_row = c->shape.lpr;
+    return ABFT_OK;
+}
+
+void abft_stencil_destroy(abft_ctx* c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft_options* o,
+                                    void* hip_stream, abft_ctx** out)
+{
+    (void)p;
+    (void)n;
+    (void)o;
+    (void)hip_stream;
+    if (out) *out = nullptr;
+    return fail(nullptr, ABFT_E_UNSUPPORTED, "batched contexts are not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,387 @@
+// The fused sweep kernel: Eq.(1) for a radius-1 star stencil, with the row checksum (Eq.(3)),
+// its prediction (Theorem 1, Eq.(5)) and the mismatch test (Section 3.4) in the same pass.
+//
+// Work decomposition.  A block of 4 wavefronts owns TY whole rows (y0 .. y0+TY-1) of a slab of
+// planes z0 .. z0+tz-1 and marches along z.  Each row belongs to LPR lanes of one wavefront;
+// a lane holds NCH chunks of VEC consecutive x (16-byte accesses), so the row's checksum is a
+// reduction across the row's lanes (DPP) and never needs another pass over the data.  The
+// planes z-1, z, z+1 of the block's rows and the constant term of plane z are kept in
+// registers and rotated as the block advances one plane; the next plane is loaded while the
+// current one is computed.  The in-plane neighbours come from LDS: every plane step writes the
+// block's TY rows plus one halo row on each side (loaded cooperatively by the whole block)
+// into one of two LDS plane buffers, each row padded with its two x-ghost values.
+#pragma once
+
+#include "abft_device.h"
+
+namespace abft {
+
+template <typename T, int MODE, int CS, int LPR, int NCH, int VEC>
+__global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
+{
+    using V = VecOps<T, VEC>;
+    constexpr int RPW = 64 / LPR;                 // rows per wavefront
+    constexpr int TY = (kSweepBlock / 64) * RPW;  // rows per block
+    constexpr int SEGW = LPR * VEC;               // elements of one chunk of a row
+    constexpr int HMAX = (NCH * SEGW + kSweepBlock * VEC - 1) / (kSweepBlock * VEC);
+
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+
+    if (a.guard != nullptr && *a.guard == 0u) return;
+    const int64_t t = a.t_off + (a.t_base != nullptr ? *a.t_base : 0);
+
+    const int nx = a.nx, ny = a.ny, nz = a.nz, bc = a.st.bc;
+    const T g = (T)a.st.g;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int seg = lane / LPR, sl = lane % LPR;
+    const int stride = nx + 2 * VEC;  // LDS row: VEC pad (ghost x=-1 at VEC-1), nx, VEC pad
+    const int plane_elems = (TY + 2) * stride;
+
+    // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous run of tiles so
+    // that neighbouring row blocks (which share halo rows) meet in the same L2.
+    const int nt = a.ntiles, bid = blockIdx.x;
+    const int per = nt >> 3, rem = nt & 7, xcd = bid & 7, q = bid >> 3;
+    const int tile = xcd * per + (xcd < rem ? xcd : rem) + q;
+    const int yb = tile % a.nyb, zb = tile / a.nyb;
+    const int y0 = yb * TY, z0 = zb * a.tz;
+    const int z1 = min(z0 + a.tz, nz);
+    const int nrows = min(TY, ny - y0);
+    const int r = wave * RPW + seg;
+    const int y = y0 + r;
+    const bool row_ok = r < nrows;
+
+    if (a.zero_ptr != nullptr && bid == 0 && tid < a.zero_n) a.zero_ptr[tid] = 0u;
+
+    const T* uin = static_cast<const T*>(a.uin);
+    T* uout = static_cast<T*>(a.uout);
+    const T* Cp = static_cast<const T*>(a.C);
+    const T cs = (T)a.c_scalar;
+    const size_t pstride = (size_t)nx * (size_t)ny;
+    const uint32_t mask = a.st.mask;
+    const T w_c = (T)a.st.w[W_C], w_xm = (T)a.st.w[W_XM], w_xp = (T)a.st.w[W_XP];
+    const T w_ym = (T)a.st.w[W_YM], w_yp = (T)a.st.w[W_YP];
+    const T w_zm = (T)a.st.w[W_ZM], w_zp = (T)a.st.w[W_ZP];
+    const bool full = mask == 0x7Fu;
+
+    int flo = 0, fhi = 0;
+    if (a.faults != nullptr && t >= 0 && t < a.fault_tmax) {
+        flo = a.fault_first[t];
+        fhi = a.fault_first[t + 1];
+    }
+
+    // Halo rows of the block in LDS rows 0 and nrows + 1.
+    const int yh0 = map_coord(y0 - 1, ny, bc), yh1 = map_coord(y0 + nrows, ny, bc);
+    const int lh1 = nrows + 1;
+
+    T dn[NCH][VEC], cu[NCH][VEC], up[NCH][VEC], cc[NCH][VEC], nu[NCH][VEC], nc[NCH][VEC];
+    T hc[2][HMAX][VEC], hn[2][HMAX][VEC];
+
+    auto load_u = [&](T (&d)[NCH][VEC], int zz) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int x = c * SEGW + sl * VEC;
+            if (row_ok && x < nx) {
+                if (zz >= 0) {
+                    V::load(uin + (size_t)zz * pstride + (size_t)y * nx + x, d[c]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) d[c][v] = g;
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) d[c][v] = T(0);
+            }
+        }
+    };
+    auto load_c = [&](T (&d)[NCH][VEC], int zz) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int x = c * SEGW + sl * VEC;
+            if (row_ok && x < nx && Cp != nullptr) {
+                V::load_nt(Cp + (size_t)zz * pstride + (size_t)y * nx + x, d[c]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) d[c][v] = cs;
+            }
+        }
+    };
+    auto load_halo = [&](T (&d)[2][HMAX][VEC], int zz) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int yy = h ? yh1 : yh0;
+#pragma unroll
+            for (int k = 0; k < HMAX; ++k) {
+                const int x = (tid + k * kSweepBlock) * VEC;
+                if (x < nx && yy >= 0) {
+                    V::load(uin + (size_t)zz * pstride + (size_t)yy * nx + x, d[h][k]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) d[h][k][v] = g;
+                }
+            }
+        }
+    };
+    // Ghost values of one LDS row from the thread holding x = 0 or x = nx - VEC.
+    auto put_ghosts = [&](T* row, int x, const T (&d)[VEC]) {
+        if (x == 0) {
+            if (bc == ABFT_BC_CLAMP) row[-1] = d[0];
+            else if (bc == ABFT_BC_PERIODIC) row[nx] = d[0];
+            else { row[-1] = g; row[nx] = g; }
+        }
+        if (x + VEC == nx) {
+            if (bc == ABFT_BC_CLAMP) row[nx] = d[VEC - 1];
+            else if (bc == ABFT_BC_PERIODIC) row[-1] = d[VEC - 1];
+        }
+    };
+
+    load_u(dn, map_coord(z0 - 1, nz, bc));
+    load_u(cu, z0);
+    load_u(up, map_coord(z0 + 1, nz, bc));
+    load_c(cc, z0);
+    load_halo(hc, z0);
+
+    double noise = 0.0;
+
+    for (int z = z0; z < z1; ++z) {
+        // next plane in flight while this one is computed
+        if (z + 1 < z1) {
+            load_u(nu, map_coord(z + 2, nz, bc));
+            load_c(nc, z + 1);
+            load_halo(hn, z + 1);
+        }
+
+        T* buf = lds + ((z - z0) & 1) * plane_elems;
+        if (row_ok) {
+            T* row = buf + (r + 1) * stride + VEC;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int x = c * SEGW + sl * VEC;
+                if (x < nx) {
+                    V::store(row + x, cu[c]);
+                    put_ghosts(row, x, cu[c]);
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            T* row = buf + (h ? lh1 : 0) * stride + VEC;
+#pragma unroll
+            for (int k = 0; k < HMAX; ++k) {
+                const int x = (tid + k * kSweepBlock) * VEC;
+                if (x < nx) {
+                    V::store(row + x, hc[h][k]);
+                    put_ghosts(row, x, hc[h][k]);
+                }
+            }
+        }
+        __syncthreads();
+
+        // Eq.(1) on the block's rows of plane z.
+        const T* rowm = buf + r * stride + VEC;
+        const T* row0 = buf + (r + 1) * stride + VEC;
+        const T* rowp = buf + (r + 2) * stride + VEC;
+        T o[NCH][VEC];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int x = c * SEGW + sl * VEC;
+            if (row_ok && x < nx) {
+                T ym[VEC], yp[VEC];
+                V::load(rowm + x, ym);
+                V::load(rowp + x, yp);
+                const T xl = row0[x - 1], xr = row0[x + VEC];
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    const T xm = v > 0 ? cu[c][v - 1] : xl;
+                    const T xp = v < VEC - 1 ? cu[c][v + 1] : xr;
+                    T acc = cc[c][v];
+                    if (full) {
+                        acc = fma(w_c, cu[c][v], acc);
+                        acc = fma(w_xm, xm, acc);
+                        acc = fma(w_xp, xp, acc);
+                        acc = fma(w_ym, ym[v], acc);
+                        acc = fma(w_yp, yp[v], acc);
+                        acc = fma(w_zm, dn[c][v], acc);
+                        acc = fma(w_zp, up[c][v], acc);
+                    } else {
+                        // absent taps contribute nothing, also next to non-finite values
+                        acc = fma(w_c, (mask & 1u) ? cu[c][v] : T(0), acc);
+                        acc = fma(w_xm, (mask & 2u) ? xm : T(0), acc);
+                        acc = fma(w_xp, (mask & 4u) ? xp : T(0), acc);
+                        acc = fma(w_ym, (mask & 8u) ? ym[v] : T(0), acc);
+                        acc = fma(w_yp, (mask & 16u) ? yp[v] : T(0), acc);
+                        acc = fma(w_zm, (mask & 32u) ? dn[c][v] : T(0), acc);
+                        acc = fma(w_zp, (mask & 64u) ? up[c][v] : T(0), acc);
+                    }
+                    o[c][v] = acc;
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) o[c][v] = T(0);
+            }
+        }
+
+        // Fault model of Section 5.1: flip a bit of the value after the update, before the
+        // store; the checksum below sees the stored value.
+        for (int f = flo; f < fhi; ++f) {
+            const abft_fault F = a.faults[f];
+            if (F.attempt == a.attempt && F.grid == a.grid && F.z == z && F.y == y && row_ok) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v)
+                        if (c * SEGW + sl * VEC + v == F.x) {
+                            if constexpr (sizeof(T) == 4) {
+                                o[c][v] = __builtin_bit_cast(
+                                    T, __builtin_bit_cast(uint32_t, o[c][v]) ^ (1u << F.bit));
+                            } else {
+                                o[c][v] = __builtin_bit_cast(
+                                    T, __builtin_bit_cast(uint64_t, o[c][v]) ^ (1ull << F.bit));
+                            }
+                        }
+            }
+        }
+
+        if (row_ok) {
+            T* dst = uout + (size_t)z * pstride + (size_t)y * nx;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int x = c * SEGW + sl * VEC;
+                if (x < nx) V::store_nt(dst + x, o[c]);
+            }
+        }
+
+        // Row checksum of the output (Eq.(3)), reduced across the row's lanes.
+        if constexpr (MODE != MODE_PLAIN) {
+            double S;
+            if constexpr (CS == CS_F64) {
+                double p = 0.0;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) p += (double)o[c][v];
+                S = segment_total<LPR>(row16_sum(p));
+            } else {
+                CPair p{0.f, 0.f};
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) p = cpair_add1(p, (float)o[c][v]);
+                S = segment_total<LPR>(row16_pair(p));
+            }
+            if (row_ok && sl == 0) {
+                const size_t l = (size_t)z * ny + y;
+                a.Bn[l] = S;
+                if constexpr (MODE == MODE_PROT) {
+                    // Theorem 1 (Eq.(5)) on the checksum plane: the x shifts become boundary
+                    // terms of the input row, the y and z shifts read neighbouring checksums.
+                    const double uf = (double)row0[0], ul = (double)row0[nx - 1];
+                    double gl, gr;  // G(-1), G(nx)
+                    if (bc == ABFT_BC_CLAMP) { gl = uf; gr = ul; }
+                    else if (bc == ABFT_BC_PERIODIC) { gl = ul; gr = uf; }
+                    else { gl = (double)g; gr = (double)g; }
+                    auto brow = [&](int zz, int yy) -> double {
+                        const int mz = map_coord(zz, nz, bc), my = map_coord(yy, ny, bc);
+                        if (mz < 0 || my < 0) return (double)nx * (double)g;
+                        return a.Bt[(size_t)mz * ny + my];
+                    };
+                    const double b0 = a.Bt[l];
+                    double bp = a.cB[l];
+                    if (mask & 1u) bp += a.st.w[W_C] * b0;
+                    if (mask & 2u) bp += a.st.w[W_XM] * (b0 + (gl - ul));
+                    if (mask & 4u) bp += a.st.w[W_XP] * (b0 + (gr - uf));
+                    if (mask & 8u) bp += a.st.w[W_YM] * brow(z, y - 1);
+                    if (mask & 16u) bp += a.st.w[W_YP] * brow(z, y + 1);
+                    if (mask & 32u) bp += a.st.w[W_ZM] * brow(z - 1, y);
+                    if (mask & 64u) bp += a.st.w[W_ZP] * brow(z + 1, y);
+                    // Section 3.4, written so that NaN and Inf mismatches are flagged
+                    const double d = fabs(S - bp);
+                    if (!(d <= a.eps * fabs(bp))) {
+                        const unsigned i = atomicAdd(&a.slot->count, 1u);
+                        if (i < (unsigned)kMaxFlags) {
+                            RowFlag rf;
+                            rf.z = z;
+                            rf.y = y;
+                            rf.direct = S;
+                            rf.pred = bp;
+                            a.slot->rows[i] = rf;
+                        } else {
+                            atomicAdd(&a.cnt->overflow, 1ull);
+                        }
+                        atomicAdd(&a.cnt->rows_flagged, 1ull);
+                        emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_ROW_FLAG, z, y, -1, S, bp,
+                                   a.grid);
+                    } else if (bp != 0.0) {
+                        noise = fmax(noise, d / fabs(bp));
+                    }
+                }
+            }
+        }
+
+        // Offline windows with boundary terms that do not cancel record them per sweep.
+        if (a.E != nullptr && row_ok && sl == 0) {
+            const double uf = (double)row0[0], ul = (double)row0[nx - 1];
+            double gl, gr;
+            if (bc == ABFT_BC_CLAMP) { gl = uf; gr = ul; }
+            else if (bc == ABFT_BC_PERIODIC) { gl = ul; gr = uf; }
+            else { gl = (double)g; gr = (double)g; }
+            double e = 0.0;
+            if (mask & 2u) e += a.st.w[W_XM] * (gl - ul);
+            if (mask & 4u) e += a.st.w[W_XP] * (gr - uf);
+            a.E[(size_t)z * ny + y] = e;
+        }
+
+        // rotate the register planes
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                dn[c][v] = cu[c][v];
+                cu[c][v] = up[c][v];
+                up[c][v] = nu[c][v];
+                cc[c][v] = nc[c][v];
+            }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int k = 0; k < HMAX; ++k)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) hc[h][k][v] = hn[h][k][v];
+    }
+
+    if constexpr (MODE == MODE_PROT) record_noise(a.cnt, noise);
+}
+
+// Table of instantiated variants.
+template <typename T, int MODE, int CS>
+hipError_t launch_sweep_t(const SweepShape& s, const SweepArgs& a, hipStream_t st, size_t lds)
+{
+#define ABFT_SWEEP_CASE(LPR_, NCH_, VEC_)                                                      \
+    if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_) {                                     \
+        auto kern = sweep_kernel<T, MODE, CS, LPR_, NCH_, VEC_>;                               \
+        static int lds_set = 0;                                                                \
+        if (lds > 65536 && (int)lds > lds_set) {                                               \
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),             \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,      \
+                                               (int)lds);                                      \
+            if (e != hipSuccess) return e;                                                     \
+            lds_set = (int)lds;                                                                \
+        }                                                                                      \
+        hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(kSweepBlock), lds, st, a);               \
+        return hipGetLastError();                                                              \
+    }
+    constexpr int VF = 16 / (int)sizeof(T);
+    ABFT_SWEEP_CASE(16, 1, VF)
+    ABFT_SWEEP_CASE(16, 2, VF)
+    ABFT_SWEEP_CASE(16, 4, VF)
+    ABFT_SWEEP_CASE(64, 1, VF)
+    ABFT_SWEEP_CASE(64, 2, VF)
+    ABFT_SWEEP_CASE(64, 4, VF)
+    ABFT_SWEEP_CASE(64, 8, VF)
+    ABFT_SWEEP_CASE(64, 4, 1)
+    ABFT_SWEEP_CASE(64, 16, 1)
+#undef ABFT_SWEEP_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace abft

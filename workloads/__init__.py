@@ -27,7 +27,7 @@ FAULT_DTYPE = np.dtype([
     ("z", "<i4"), ("y", "<i4"), ("x", "<i4"),
     ("bit", "<i4"),      # bit position in the stored word (0 = LSB)
     ("attempt", "<i4"),  # fires only on this attempt (0 = first run, 1 = offline recompute)
-    ("pad", "<i4"),
+    ("grid", "<i4"),     # grid index in a batch of grids (0 for a single grid)
 ])
 
 # --------------------------------------------------------------------------------------
