@@ -227,15 +227,14 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // ------------------------------------------------------------------------------------------
 // Boundary rule on one coordinate: index inside [0, n), or -1 for a constant ghost.
+// Radius-1 stencils only ever step a few points outside the grid, so c lies in [-n, 2n) and
+// the periodic wrap needs no division.
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ int map_coord(int c, int n, int bc)
 {
     if (c >= 0 && c < n) return c;
     if (bc == ABFT_BC_CLAMP) return c < 0 ? 0 : n - 1;
-    if (bc == ABFT_BC_PERIODIC) {
-        const int m = c % n;
-        return m < 0 ? m + n : m;
-    }
+    if (bc == ABFT_BC_PERIODIC) return c < 0 ? c + n : c - n;
     return -1;
 }
 

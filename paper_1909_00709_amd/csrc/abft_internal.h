@@ -128,6 +128,7 @@ struct SweepShape {
     int32_t nch;   // chunks of lpr*vec elements per row: 1, 2, 4 or 8
     int32_t vec;   // elements per 16-byte access (1 for rows that are not 16-byte multiples)
     int32_t tz;    // planes per block
+    int32_t pf;    // planes loaded ahead of the one computed: 1 or 2
 };
 
 bool sweep_shape_supported(int dtype, const SweepShape& s);

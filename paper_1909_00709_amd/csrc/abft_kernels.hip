@@ -379,6 +379,8 @@ bool sweep_shape_supported(int dtype, const SweepShape& s)
 {
     const int vf = dtype == ABFT_F32 ? 4 : 2;
     if (s.tz < 1) return false;
+    if (s.pf == 2) return s.vec == vf && s.lpr == 64 && (s.nch == 2 || s.nch == 4);
+    if (s.pf != 1) return false;
     if (s.vec == vf) {
         if (s.lpr == 16) return s.nch == 1 || s.nch == 2 || s.nch == 4;
         if (s.lpr == 64) return s.nch == 1 || s.nch == 2 || s.nch == 4 || s.nch == 8;
@@ -393,7 +395,9 @@ int sweep_rows_per_block(const SweepShape& s) { return (kSweepBlock / 64) * (64 
 size_t sweep_lds_bytes(int dtype, int nx, const SweepShape& s)
 {
     const size_t es = dtype == ABFT_F32 ? 4 : 8;
-    return 2 * (size_t)(sweep_rows_per_block(s) + 2) * (size_t)(nx + 2 * s.vec) * es;
+    const size_t ty = (size_t)sweep_rows_per_block(s);
+    return 2 * (ty + 2) * (size_t)(nx + 2 * s.vec) * es   // two plane buffers
+           + 2 * ty * (size_t)s.tz * sizeof(double);        // checksum and boundary tables
 }
 
 hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, const SweepArgs& a,

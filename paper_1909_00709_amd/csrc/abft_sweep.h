@@ -16,7 +16,7 @@
 
 namespace abft {
 
-template <typename T, int MODE, int CS, int LPR, int NCH, int VEC>
+template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF>
 __global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
 {
     using V = VecOps<T, VEC>;
@@ -33,7 +33,10 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
 
     const int nx = a.nx, ny = a.ny, nz = a.nz, bc = a.st.bc;
     const T g = (T)a.st.g;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the wavefront index is uniform across the wavefront: keep it (and what derives from it)
+    // in scalar registers
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int seg = lane / LPR, sl = lane % LPR;
     const int stride = nx + 2 * VEC;  // LDS row: VEC pad (ghost x=-1 at VEC-1), nx, VEC pad
     const int plane_elems = (TY + 2) * stride;
@@ -74,8 +77,10 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
     const int yh0 = map_coord(y0 - 1, ny, bc), yh1 = map_coord(y0 + nrows, ny, bc);
     const int lh1 = nrows + 1;
 
+    // planes z-1, z, z+1 and the constant term of z in use; planes ahead in flight (PF deep)
     T dn[NCH][VEC], cu[NCH][VEC], up[NCH][VEC], cc[NCH][VEC], nu[NCH][VEC], nc[NCH][VEC];
     T hc[2][HMAX][VEC], hn[2][HMAX][VEC];
+    T nu2[PF > 1 ? NCH : 1][VEC], nc2[PF > 1 ? NCH : 1][VEC], hn2[2][PF > 1 ? HMAX : 1][VEC];
 
     auto load_u = [&](T (&d)[NCH][VEC], int zz) {
 #pragma unroll
@@ -140,15 +145,32 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
     load_u(up, map_coord(z0 + 1, nz, bc));
     load_c(cc, z0);
     load_halo(hc, z0);
-
-    double noise = 0.0;
+    if constexpr (PF > 1) {
+        if (z0 + 1 < z1) {
+            load_u(nu, map_coord(z0 + 2, nz, bc));
+            load_c(nc, z0 + 1);
+            load_halo(hn, z0 + 1);
+        }
+    }
+    // checksum and boundary-term table: [TY][tz] doubles each, after the two plane buffers
+    double* tabS = reinterpret_cast<double*>(smem_raw + (size_t)2 * plane_elems * sizeof(T));
+    double* tabE = tabS + TY * a.tz;
+    const bool keep_e = MODE == MODE_PROT || a.E != nullptr;
 
     for (int z = z0; z < z1; ++z) {
-        // next plane in flight while this one is computed
-        if (z + 1 < z1) {
-            load_u(nu, map_coord(z + 2, nz, bc));
-            load_c(nc, z + 1);
-            load_halo(hn, z + 1);
+        // planes ahead in flight while this one is computed
+        if constexpr (PF > 1) {
+            if (z + 2 < z1) {
+                load_u(nu2, map_coord(z + 3, nz, bc));
+                load_c(nc2, z + 2);
+                load_halo(hn2, z + 2);
+            }
+        } else {
+            if (z + 1 < z1) {
+                load_u(nu, map_coord(z + 2, nz, bc));
+                load_c(nc, z + 1);
+                load_halo(hn, z + 1);
+            }
         }
 
         T* buf = lds + ((z - z0) & 1) * plane_elems;
@@ -251,7 +273,10 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
             }
         }
 
-        // Row checksum of the output (Eq.(3)), reduced across the row's lanes.
+        // Row checksum of the output (Eq.(3)), reduced across the row's lanes, and the row's
+        // x-boundary term of Theorem 1 from the input row (its first and last points and the
+        // ghosts).  Both go to a small LDS table; the prediction and the comparison for all
+        // planes of the tile run after the march, so none of their loads sits in this loop.
         if constexpr (MODE != MODE_PLAIN) {
             double S;
             if constexpr (CS == CS_F64) {
@@ -269,27 +294,75 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
                     for (int v = 0; v < VEC; ++v) p = cpair_add1(p, (float)o[c][v]);
                 S = segment_total<LPR>(row16_pair(p));
             }
-            if (row_ok && sl == 0) {
-                const size_t l = (size_t)z * ny + y;
+            if (row_ok && sl == 0) tabS[r * a.tz + (z - z0)] = S;
+        }
+        if (keep_e && row_ok && sl == 0) {
+            const double uf = (double)row0[0], ul = (double)row0[nx - 1];
+            double gl, gr;  // G(-1), G(nx)
+            if (bc == ABFT_BC_CLAMP) { gl = uf; gr = ul; }
+            else if (bc == ABFT_BC_PERIODIC) { gl = ul; gr = uf; }
+            else { gl = (double)g; gr = (double)g; }
+            double e = 0.0;
+            if (mask & 2u) e += a.st.w[W_XM] * (gl - ul);
+            if (mask & 4u) e += a.st.w[W_XP] * (gr - uf);
+            tabE[r * a.tz + (z - z0)] = e;
+        }
+
+        // rotate the register planes
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                dn[c][v] = cu[c][v];
+                cu[c][v] = up[c][v];
+                up[c][v] = nu[c][v];
+                cc[c][v] = nc[c][v];
+                if constexpr (PF > 1) {
+                    nu[c][v] = nu2[c][v];
+                    nc[c][v] = nc2[c][v];
+                }
+            }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int k = 0; k < HMAX; ++k)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    hc[h][k][v] = hn[h][k][v];
+                    if constexpr (PF > 1) hn[h][k][v] = hn2[h][k][v];
+                }
+    }
+
+    if constexpr (MODE == MODE_PLAIN) {
+        if (a.E == nullptr) return;
+    }
+    __syncthreads();
+    // Epilogue: the segment's lanes take the tile's planes of their row in parallel.
+    const int nzt = z1 - z0;
+    double noise = 0.0;
+    if (row_ok) {
+        for (int pz = sl; pz < nzt; pz += LPR) {
+            const int z = z0 + pz;
+            const size_t l = (size_t)z * ny + y;
+            if (a.E != nullptr) a.E[l] = tabE[r * a.tz + pz];
+            if constexpr (MODE != MODE_PLAIN) {
+                const double S = tabS[r * a.tz + pz];
                 a.Bn[l] = S;
                 if constexpr (MODE == MODE_PROT) {
-                    // Theorem 1 (Eq.(5)) on the checksum plane: the x shifts become boundary
-                    // terms of the input row, the y and z shifts read neighbouring checksums.
-                    const double uf = (double)row0[0], ul = (double)row0[nx - 1];
-                    double gl, gr;  // G(-1), G(nx)
-                    if (bc == ABFT_BC_CLAMP) { gl = uf; gr = ul; }
-                    else if (bc == ABFT_BC_PERIODIC) { gl = ul; gr = uf; }
-                    else { gl = (double)g; gr = (double)g; }
-                    auto brow = [&](int zz, int yy) -> double {
-                        const int mz = map_coord(zz, nz, bc), my = map_coord(yy, ny, bc);
+                    // Theorem 1 (Eq.(5)) on the checksum plane: the x shifts become the
+                    // boundary term e of the input row, the y and z shifts read the
+                    // neighbouring rows' checksums.
+                    auto brow = [&](int z2, int y2) -> double {
+                        const int mz = map_coord(z2, nz, bc), my = map_coord(y2, ny, bc);
                         if (mz < 0 || my < 0) return (double)nx * (double)g;
                         return a.Bt[(size_t)mz * ny + my];
                     };
                     const double b0 = a.Bt[l];
                     double bp = a.cB[l];
                     if (mask & 1u) bp += a.st.w[W_C] * b0;
-                    if (mask & 2u) bp += a.st.w[W_XM] * (b0 + (gl - ul));
-                    if (mask & 4u) bp += a.st.w[W_XP] * (b0 + (gr - uf));
+                    if (mask & 2u) bp += a.st.w[W_XM] * b0;
+                    if (mask & 4u) bp += a.st.w[W_XP] * b0;
+                    bp += tabE[r * a.tz + pz];
                     if (mask & 8u) bp += a.st.w[W_YM] * brow(z, y - 1);
                     if (mask & 16u) bp += a.st.w[W_YP] * brow(z, y + 1);
                     if (mask & 32u) bp += a.st.w[W_ZM] * brow(z - 1, y);
@@ -317,38 +390,7 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
                 }
             }
         }
-
-        // Offline windows with boundary terms that do not cancel record them per sweep.
-        if (a.E != nullptr && row_ok && sl == 0) {
-            const double uf = (double)row0[0], ul = (double)row0[nx - 1];
-            double gl, gr;
-            if (bc == ABFT_BC_CLAMP) { gl = uf; gr = ul; }
-            else if (bc == ABFT_BC_PERIODIC) { gl = ul; gr = uf; }
-            else { gl = (double)g; gr = (double)g; }
-            double e = 0.0;
-            if (mask & 2u) e += a.st.w[W_XM] * (gl - ul);
-            if (mask & 4u) e += a.st.w[W_XP] * (gr - uf);
-            a.E[(size_t)z * ny + y] = e;
-        }
-
-        // rotate the register planes
-#pragma unroll
-        for (int c = 0; c < NCH; ++c)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                dn[c][v] = cu[c][v];
-                cu[c][v] = up[c][v];
-                up[c][v] = nu[c][v];
-                cc[c][v] = nc[c][v];
-            }
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int k = 0; k < HMAX; ++k)
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) hc[h][k][v] = hn[h][k][v];
     }
-
     if constexpr (MODE == MODE_PROT) record_noise(a.cnt, noise);
 }
 
@@ -356,9 +398,9 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
 template <typename T, int MODE, int CS>
 hipError_t launch_sweep_t(const SweepShape& s, const SweepArgs& a, hipStream_t st, size_t lds)
 {
-#define ABFT_SWEEP_CASE(LPR_, NCH_, VEC_)                                                      \
-    if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_) {                                     \
-        auto kern = sweep_kernel<T, MODE, CS, LPR_, NCH_, VEC_>;                               \
+#define ABFT_SWEEP_CASE_PF(LPR_, NCH_, VEC_, PF_)                                              \
+    if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_ && s.pf == PF_) {                      \
+        auto kern = sweep_kernel<T, MODE, CS, LPR_, NCH_, VEC_, PF_>;                          \
         static int lds_set = 0;                                                                \
         if (lds > 65536 && (int)lds > lds_set) {                                               \
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),             \
@@ -370,7 +412,10 @@ hipError_t launch_sweep_t(const SweepShape& s, const SweepArgs& a, hipStream_t s
         hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(kSweepBlock), lds, st, a);               \
         return hipGetLastError();                                                              \
     }
+#define ABFT_SWEEP_CASE(LPR_, NCH_, VEC_) ABFT_SWEEP_CASE_PF(LPR_, NCH_, VEC_, 1)
     constexpr int VF = 16 / (int)sizeof(T);
+    ABFT_SWEEP_CASE_PF(64, 2, VF, 2)
+    ABFT_SWEEP_CASE_PF(64, 4, VF, 2)
     ABFT_SWEEP_CASE(16, 1, VF)
     ABFT_SWEEP_CASE(16, 2, VF)
     ABFT_SWEEP_CASE(16, 4, VF)
@@ -381,6 +426,7 @@ hipError_t launch_sweep_t(const SweepShape& s, const SweepArgs& a, hipStream_t s
     ABFT_SWEEP_CASE(64, 4, 1)
     ABFT_SWEEP_CASE(64, 16, 1)
 #undef ABFT_SWEEP_CASE
+#undef ABFT_SWEEP_CASE_PF
     return hipErrorInvalidValue;
 }
 
