@@ -346,3 +346,54 @@ class Stencil:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Many independent grids swept together (abft_stencil_init_batch).  grids is a list of
+    (u0, C) pairs of contiguous device tensors (C may be None); all grids share the dtype, the
+    taps and the options."""
+
+    def __init__(self, grids, taps, *, c_scalar=0.0, bc="clamp", bc_value=0.0, mode="online",
+                 threshold=1e-7, csum="f64", auto_correct=True, max_events=4096, stream=None):
+        import torch
+        self.torch = torch
+        self.bufs, self.Cs, problems = [], [], []
+        for u0, C in grids:
+            if not u0.is_cuda or not u0.is_contiguous() or u0.dim() != 3:
+                raise ValueError("each u0 must be a contiguous 3D device tensor")
+            code = ABFT_F32 if u0.dtype == torch.float32 else ABFT_F64
+            pair = [u0, torch.empty_like(u0)]
+            self.bufs.append(pair)
+            self.Cs.append(C)
+            problems.append(make_problem(tuple(u0.shape), code, taps, u0.data_ptr(),
+                                         pair[1].data_ptr(), None,
+                                         C.data_ptr() if C is not None else None, c_scalar,
+                                         bc, bc_value))
+        self.problems = problems
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.max_events = max_events
+        self.options = make_options(mode, 1, threshold, csum, auto_correct, max_events)
+        s, ctx = abft_stencil_init_batch(problems, self.options, self.stream.cuda_stream)
+        if s != ABFT_OK:
+            raise AbftError(s, abft_last_error(None))
+        self.ctx = ctx
+
+    _chk = Stencil._chk
+    step = Stencil.step
+    step_graph = Stencil.step_graph
+    _report = Stencil._report
+    check = Stencil.check
+    correct = Stencil.correct
+    inject = Stencil.inject
+    autotune = Stencil.autotune
+    launch_shape = Stencil.launch_shape
+    close = Stencil.close
+    __del__ = Stencil.__del__
+
+    def current(self, g: int):
+        s, ptr, t = abft_stencil_current(self.ctx, g)
+        self._chk(s)
+        for b in self.bufs[g]:
+            if b.data_ptr() == ptr:
+                return b, t
+        raise RuntimeError("current grid is not one of the grid's buffers")

@@ -14,6 +14,7 @@ constexpr int kSweepBlock = 256;  // threads per block of the sweep kernel (4 wa
 constexpr int kFixBlock = 512;    // threads of the single locate/correct block
 constexpr int kCheckBlock = 256;  // threads per block of the offline window check
 constexpr int kMaxPeriod = 32;    // longest offline window handled by one check launch
+constexpr int kCheckCells = 16;   // checksum-plane cells per thread in the window check
 
 // Weight slots of the radius-1 star stencil: centre, x-1, x+1, y-1, y+1, z-1, z+1.
 enum { W_C = 0, W_XM, W_XP, W_YM, W_YP, W_ZM, W_ZP, W_COUNT };
@@ -122,6 +123,40 @@ struct CheckArgs {
     int64_t t_last;         // last sweep of the window
 };
 
+// One grid of a batch, as the batched kernels see it.
+struct GridDesc {
+    void* u[2];             // the grid's two buffers; u[t & 1] holds u^t
+    const void* C;
+    double c_scalar;
+    Stencil st;
+    int32_t nx, ny, nz;
+    int32_t tz, nyb, ntiles;
+    double* B[2];           // B[t & 1] holds the row checksums of u^t
+    const double* cB;
+    const double* cA;
+    FlagSlot* slot[2];      // flagged rows of sweeps with t & 1 == index
+};
+
+struct BatchArgs {
+    const GridDesc* grids;
+    int32_t ngrids;
+    int32_t ntiles;         // tiles of all grids
+    const int2* order;      // (grid, tile) in processing order (largest first)
+    uint32_t* queue;        // persistent launch: [0] next tile, [1] blocks finished
+    int32_t persistent;     // 1: blocks pop tiles from the queue; 0: one tile per block
+    int32_t parity;         // t & 1 of this sweep
+    const int64_t* t_base;
+    int64_t t_off;
+    int32_t attempt;
+    double eps;
+    Counters* cnt;
+    abft_event* ev;
+    int32_t ev_cap;
+    const abft_fault* faults;
+    const int32_t* fault_first;
+    int64_t fault_tmax;
+};
+
 // Kernel launchers (abft_kernels.hip).  Each returns hipSuccess or the launch error.
 struct SweepShape {
     int32_t lpr;   // lanes per row: 16 or 64
@@ -137,6 +172,13 @@ int sweep_rows_per_block(const SweepShape& s);
 hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, const SweepArgs& a,
                         hipStream_t st);
 hipError_t launch_fixup(int dtype, const FixArgs& a, hipStream_t st);
+hipError_t launch_fixup_batch(int dtype, const BatchArgs& b, int maxnx, hipStream_t st);
+// Batched sweep (abft_batch.hip): one launch sweeps every grid of the batch.
+bool batch_shape_supported(int dtype, const SweepShape& s);
+hipError_t launch_sweep_batch(int dtype, int mode, int csum, const SweepShape& s,
+                              const BatchArgs& b, int nblocks, size_t lds, hipStream_t st);
+size_t batch_lds_bytes(int dtype, int maxnx, int maxtz, const SweepShape& s);
+int batch_blocks_per_cu(int dtype, int mode, int csum, const SweepShape& s, size_t lds);
 size_t fixup_lds_bytes(int nx);
 hipError_t launch_check(const CheckArgs& a, hipStream_t st);
 size_t check_lds_bytes(int ry, int rz);

@@ -27,12 +27,8 @@ __device__ double block_sum(double v, double* red)
 // directly).  Exits at once when nothing was flagged.
 // ------------------------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kFixBlock) fixup_kernel(const FixArgs a)
+__device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* red, int& sh_K)
 {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    __shared__ double red[kFixBlock / 64];
-    __shared__ int sh_K;
-
     FlagSlot* slot = a.slot;
     const unsigned n_all = slot->count;
     if (n_all == 0u) return;
@@ -209,6 +205,46 @@ __global__ void __launch_bounds__(kFixBlock) fixup_kernel(const FixArgs a)
     if (tid == 0) slot->count = 0u;
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kFixBlock) fixup_kernel(const FixArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    __shared__ double red[kFixBlock / 64];
+    __shared__ int sh_K;
+    fixup_body<T>(a, smem_raw, red, sh_K);
+}
+
+// One block per grid of a batch; each exits at once unless its grid flagged a row.
+template <typename T>
+__global__ void __launch_bounds__(kFixBlock) fixup_batch_kernel(const BatchArgs b)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    __shared__ double red[kFixBlock / 64];
+    __shared__ int sh_K;
+    const int g = blockIdx.x;
+    const GridDesc& d = b.grids[g];
+    const int p = b.parity;
+    if (d.slot[p]->count == 0u) return;
+    FixArgs a{};
+    a.uin = d.u[p];
+    a.uout = d.u[p ^ 1];
+    a.Bn = d.B[p ^ 1];
+    a.cA = d.cA;
+    a.st = d.st;
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.nz = d.nz;
+    a.eps = b.eps;
+    a.slot = d.slot[p];
+    a.cnt = b.cnt;
+    a.ev = b.ev;
+    a.ev_cap = b.ev_cap;
+    a.grid = g;
+    a.t_base = b.t_base;
+    a.t_off = b.t_off;
+    fixup_body<T>(a, smem_raw, red, sh_K);
+}
+
 // ------------------------------------------------------------------------------------------
 // Offline window check (Section 4.1): the checksum interpolation applied k times from the
 // checkpoint's checksums, then compared with the direct checksums at the window end.  Each
@@ -241,42 +277,63 @@ __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
     double* nxt = cur + (size_t)a.ry_max * a.rz_max;
 
     auto wrap = [](int c, int n) { const int m = c % n; return m < 0 ? m + n : m; };
-    for (int i = tid; i < NC; i += kCheckBlock) {
-        const int yy = ry0 + i % RY, zz = rz0 + i / RY;
-        const int gy = per ? wrap(yy, ny) : yy, gz = per ? wrap(zz, nz) : zz;
-        cur[i] = a.Bck[(size_t)gz * ny + gy];
+    const double wx = ((mask & 1u) ? a.st.w[W_C] : 0.0) + ((mask & 2u) ? a.st.w[W_XM] : 0.0) +
+                      ((mask & 4u) ? a.st.w[W_XP] : 0.0);
+    const double wym = (mask & 8u) ? a.st.w[W_YM] : 0.0, wyp = (mask & 16u) ? a.st.w[W_YP] : 0.0;
+    const double wzm = (mask & 32u) ? a.st.w[W_ZM] : 0.0, wzp = (mask & 64u) ? a.st.w[W_ZP] : 0.0;
+
+    // Each thread owns the same cells at every step: their constant-term checksums, global
+    // offsets and neighbour cells stay in registers.  nb < 0 marks a neighbour that is a row
+    // of constant ghosts (sum nx * g); a neighbour outside the loaded region points at the
+    // cell itself (its value only reaches cells outside the tile).
+    double cbv[kCheckCells];
+    int gl[kCheckCells], nym[kCheckCells], nyp[kCheckCells], nzm[kCheckCells], nzp[kCheckCells];
+#pragma unroll
+    for (int q = 0; q < kCheckCells; ++q) {
+        const int i = tid + q * kCheckBlock;
+        cbv[q] = 0.0;
+        gl[q] = 0;
+        nym[q] = nyp[q] = nzm[q] = nzp[q] = i < NC ? i : 0;
+        if (i < NC) {
+            const int yy = ry0 + i % RY, zz = rz0 + i / RY;
+            const int gy = per ? wrap(yy, ny) : yy, gz = per ? wrap(zz, nz) : zz;
+            gl[q] = gz * ny + gy;
+            cbv[q] = a.cB[gl[q]];
+            cur[i] = a.Bck[gl[q]];
+            auto nbi = [&](int dz, int dy) -> int {
+                int y2 = yy + dy, z2 = zz + dz;
+                if (!per && (y2 < 0 || y2 >= ny || z2 < 0 || z2 >= nz)) {
+                    if (bc == ABFT_BC_CONSTANT) return -1;
+                    y2 = min(max(y2, 0), ny - 1);
+                    z2 = min(max(z2, 0), nz - 1);
+                }
+                if (y2 < ry0 || y2 >= ry1 || z2 < rz0 || z2 >= rz1) return i;
+                return (z2 - rz0) * RY + (y2 - ry0);
+            };
+            nym[q] = nbi(0, -1);
+            nyp[q] = nbi(0, 1);
+            nzm[q] = nbi(-1, 0);
+            nzp[q] = nbi(1, 0);
+        }
     }
     __syncthreads();
 
-    const double wx = ((mask & 1u) ? a.st.w[W_C] : 0.0) + ((mask & 2u) ? a.st.w[W_XM] : 0.0) +
-                      ((mask & 4u) ? a.st.w[W_XP] : 0.0);
+    const double ghost_row = (double)nx * gd;
     for (int s = 0; s < k; ++s) {
-        for (int i = tid; i < NC; i += kCheckBlock) {
-            const int iy = i % RY, iz = i / RY;
-            const int yy = ry0 + iy, zz = rz0 + iz;
-            const int gy = per ? wrap(yy, ny) : yy, gz = per ? wrap(zz, nz) : zz;
-            const double b = cur[i];
-            auto nb = [&](int dz, int dy) -> double {
-                int y2 = yy + dy, z2 = zz + dz;
-                if (!per) {
-                    if (y2 < 0 || y2 >= ny || z2 < 0 || z2 >= nz) {
-                        if (bc == ABFT_BC_CONSTANT) return (double)nx * gd;
-                        y2 = min(max(y2, 0), ny - 1);
-                        z2 = min(max(z2, 0), nz - 1);
-                    }
-                }
-                // outside the loaded region: only cells that do not reach the tile use it
-                if (y2 < ry0 || y2 >= ry1 || z2 < rz0 || z2 >= rz1) return b;
-                return cur[(z2 - rz0) * RY + (y2 - ry0)];
-            };
-            const size_t l = (size_t)gz * ny + gy;
-            double v = a.cB[l] + wx * b;
-            if (a.E != nullptr) v += a.E[(size_t)s * nz * ny + l];
-            if (mask & 8u) v += a.st.w[W_YM] * nb(0, -1);
-            if (mask & 16u) v += a.st.w[W_YP] * nb(0, 1);
-            if (mask & 32u) v += a.st.w[W_ZM] * nb(-1, 0);
-            if (mask & 64u) v += a.st.w[W_ZP] * nb(1, 0);
-            nxt[i] = v;
+        const double* Es = a.E != nullptr ? a.E + (size_t)s * nz * ny : nullptr;
+#pragma unroll
+        for (int q = 0; q < kCheckCells; ++q) {
+            const int i = tid + q * kCheckBlock;
+            if (i < NC) {
+                auto val = [&](int j) { return j < 0 ? ghost_row : cur[j]; };
+                double v = cbv[q] + wx * cur[i];
+                if (Es != nullptr) v += Es[gl[q]];
+                v += wym * val(nym[q]);
+                v += wyp * val(nyp[q]);
+                v += wzm * val(nzm[q]);
+                v += wzp * val(nzp[q]);
+                nxt[i] = v;
+            }
         }
         __syncthreads();
         double* tmp = cur;
@@ -285,7 +342,10 @@ __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
     }
 
     double noise = 0.0;
-    for (int i = tid; i < NC; i += kCheckBlock) {
+#pragma unroll
+    for (int q = 0; q < kCheckCells; ++q) {
+        const int i = tid + q * kCheckBlock;
+        if (i >= NC) continue;
         const int yy = ry0 + i % RY, zz = rz0 + i / RY;
         if (yy < iy0 || yy >= iy1 || zz < iz0 || zz >= iz1) continue;
         const double bp = cur[i];
@@ -417,6 +477,18 @@ hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, cons
 }
 
 size_t fixup_lds_bytes(int nx) { return (size_t)nx * (3 * sizeof(double) + 2 * sizeof(int)); }
+
+hipError_t launch_fixup_batch(int dtype, const BatchArgs& b, int maxnx, hipStream_t st)
+{
+    const size_t lds = fixup_lds_bytes(maxnx);
+    if (dtype == ABFT_F32)
+        hipLaunchKernelGGL(fixup_batch_kernel<float>, dim3(b.ngrids), dim3(kFixBlock), lds, st,
+                           b);
+    else
+        hipLaunchKernelGGL(fixup_batch_kernel<double>, dim3(b.ngrids), dim3(kFixBlock), lds, st,
+                           b);
+    return hipGetLastError();
+}
 
 hipError_t launch_fixup(int dtype, const FixArgs& a, hipStream_t st)
 {

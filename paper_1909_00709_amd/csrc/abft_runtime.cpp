@@ -82,6 +82,26 @@ struct abft_ctx {
     // graphs
     std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
     std::string err;
+    // batch of grids (abft_stencil_init_batch)
+    bool batch = false;
+    struct Grid {
+        int nx, ny, nz, tz, nyb, ntiles;
+        void* u[2];
+        const void* C;
+        double cs;
+        Stencil st;
+        double* B[2];
+        double* cB;
+        double* cA;
+        FlagSlot* slot[2];
+    };
+    std::vector<Grid> grids;
+    GridDesc* d_grids = nullptr;
+    int2* d_order = nullptr;
+    uint32_t* queue = nullptr;
+    int maxnx = 0, maxnz = 0, total_tiles = 0, persistent = 1, nblocks = 0, batch_tz = 0;
+    size_t batch_lds = 0;
+    int num_cus = 0;
 };
 
 namespace {
@@ -260,24 +280,31 @@ void cache_store(const abft_ctx* c)
       << c->shape.tz << ' ' << c->shape.pf << '\n';
 }
 
-// Offline check tiles: 64 rows x up to 16 layers of the checksum plane plus a k halo.
+// Offline check tiles: an interior of tyi rows x tzi layers of the checksum plane plus a halo
+// of k on each side, at most kCheckCells cells per thread, and enough tiles to spread over the
+// compute units.
 void check_shape(abft_ctx* c, int k)
 {
     CheckShape s;
     const bool per = c->bc == ABFT_BC_PERIODIC;
-    s.tzi = std::min(c->nz, 16);
-    s.tyi = std::min(c->ny, 64);
-    for (;;) {
-        const int ry = per ? s.tyi + 2 * k : std::min(c->ny, s.tyi + 2 * k);
-        const int rz = per ? s.tzi + 2 * k : std::min(c->nz, s.tzi + 2 * k);
-        if (check_lds_bytes(ry, rz) <= kLdsLimit || (s.tyi == 1 && s.tzi == 1)) {
-            s.ry = ry;
-            s.rz = rz;
-            break;
-        }
-        if (s.tyi > s.tzi && s.tyi > 1) s.tyi = (s.tyi + 1) / 2;
+    const int64_t cap = (int64_t)kCheckCells * kCheckBlock;
+    auto region = [&](int tyi, int tzi, int* ry, int* rz) {
+        *ry = per ? tyi + 2 * k : std::min(c->ny, tyi + 2 * k);
+        *rz = per ? tzi + 2 * k : std::min(c->nz, tzi + 2 * k);
+        return (int64_t)*ry * *rz;
+    };
+    s.tzi = std::min(c->nz, 8);
+    s.tyi = std::min(c->ny, 32);
+    int ry, rz;
+    while (region(s.tyi, s.tzi, &ry, &rz) > cap && (s.tyi > 1 || s.tzi > 1)) {
+        if (s.tyi >= s.tzi && s.tyi > 1) s.tyi = (s.tyi + 1) / 2;
         else s.tzi = (s.tzi + 1) / 2;
     }
+    auto tiles = [&](int tyi, int tzi) {
+        return (int64_t)((c->ny + tyi - 1) / tyi) * ((c->nz + tzi - 1) / tzi);
+    };
+    while (tiles(s.tyi, s.tzi) < 256 && s.tyi > 8) s.tyi /= 2;
+    region(s.tyi, s.tzi, &s.ry, &s.rz);
     s.nyt = (c->ny + s.tyi - 1) / s.tyi;
     s.nzt = (c->nz + s.tzi - 1) / s.tzi;
     c->ck = s;
@@ -548,6 +575,172 @@ abft_status validate_options(const abft_problem* p, const abft_options* o)
     return ABFT_OK;
 }
 
+// ---- batches of grids ------------------------------------------------------------------------
+// Tile layout of every grid for a slab depth (planes per tile), the processing order (largest
+// tiles first, so that the tail of a sweep is made of small tiles), and the launch size.
+abft_status batch_layout(abft_ctx* c, int tz_choice, int persistent)
+{
+    const int ty = sweep_rows_per_block(c->shape);
+    std::vector<GridDesc> desc(c->grids.size());
+    std::vector<std::pair<int64_t, int2>> tiles;
+    int maxtz = 1;
+    for (size_t g = 0; g < c->grids.size(); ++g) {
+        auto& G = c->grids[g];
+        G.tz = std::max(1, std::min(tz_choice, G.nz));
+        G.nyb = (G.ny + ty - 1) / ty;
+        G.ntiles = G.nyb * ((G.nz + G.tz - 1) / G.tz);
+        maxtz = std::max(maxtz, G.tz);
+        for (int t = 0; t < G.ntiles; ++t) {
+            const int yb = t % G.nyb, zb = t / G.nyb;
+            const int64_t rows = std::min(ty, G.ny - yb * ty);
+            const int64_t planes = std::min(G.tz, G.nz - zb * G.tz);
+            tiles.push_back({rows * planes * G.nx, int2((int)g, t)});
+        }
+        GridDesc& d = desc[g];
+        d.u[0] = G.u[0];
+        d.u[1] = G.u[1];
+        d.C = G.C;
+        d.c_scalar = G.cs;
+        d.st = G.st;
+        d.nx = G.nx;
+        d.ny = G.ny;
+        d.nz = G.nz;
+        d.tz = G.tz;
+        d.nyb = G.nyb;
+        d.ntiles = G.ntiles;
+        d.B[0] = G.B[0];
+        d.B[1] = G.B[1];
+        d.cB = G.cB;
+        d.cA = G.cA;
+        d.slot[0] = G.slot[0];
+        d.slot[1] = G.slot[1];
+    }
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [](const auto& a, const auto& b) { return a.first > b.first; });
+    std::vector<int2> order;
+    order.reserve(tiles.size());
+    for (auto& t : tiles) order.push_back(t.second);
+    const size_t lds = batch_lds_bytes(c->dtype, c->maxnx, maxtz, c->shape);
+    if (lds > kSweepLdsLimit) return fail(c, ABFT_E_UNSUPPORTED, "batch tiles exceed the LDS");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->d_order) {
+        auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)c->d_order);
+        if (it != c->allocs.end()) c->allocs.erase(it);
+        (void)hipFree(c->d_order);
+        c->d_order = nullptr;
+    }
+    abft_status s = dalloc(c, &c->d_order, order.size() * sizeof(int2));
+    if (s) return s;
+    HIPCHK(c, hipMemcpy(c->d_order, order.data(), order.size() * sizeof(int2),
+                        hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_grids, desc.data(), desc.size() * sizeof(GridDesc),
+                        hipMemcpyHostToDevice));
+    c->total_tiles = (int)order.size();
+    c->batch_lds = lds;
+    c->batch_tz = tz_choice;
+    c->persistent = persistent;
+    const int mode = c->mode == ABFT_MODE_ONLINE ? MODE_PROT : MODE_PLAIN;
+    const int per_cu = batch_blocks_per_cu(c->dtype, mode, c->csum, c->shape, lds);
+    c->nblocks = persistent ? std::min(c->total_tiles, per_cu * c->num_cus) : c->total_tiles;
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    return ABFT_OK;
+}
+
+BatchArgs batch_args(const abft_ctx* c, int64_t t, const int64_t* tbase, int64_t t0)
+{
+    BatchArgs b{};
+    b.grids = c->d_grids;
+    b.ngrids = (int)c->grids.size();
+    b.ntiles = c->total_tiles;
+    b.order = c->d_order;
+    b.queue = c->queue;
+    b.persistent = c->persistent;
+    b.parity = (int)(t & 1);
+    b.t_base = tbase;
+    b.t_off = tbase ? t - t0 : t;
+    b.eps = c->eps;
+    b.cnt = c->cnt;
+    b.ev = c->ev;
+    b.ev_cap = c->ev_cap;
+    b.faults = c->faults;
+    b.fault_first = c->fault_first;
+    b.fault_tmax = c->faults ? c->fault_tmax : 0;
+    return b;
+}
+
+abft_status enqueue_batch(abft_ctx* c, int64_t n, const int64_t* tbase, int64_t t0)
+{
+    const int mode = c->mode == ABFT_MODE_ONLINE ? MODE_PROT : MODE_PLAIN;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t t = c->t + i;
+        const BatchArgs b = batch_args(c, t, tbase, t0);
+        hipError_t e = launch_sweep_batch(c->dtype, mode, c->csum, c->shape, b, c->nblocks,
+                                          c->batch_lds, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "batched sweep launch");
+        if (c->mode == ABFT_MODE_ONLINE && c->auto_correct) {
+            e = launch_fixup_batch(c->dtype, b, c->maxnx, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "batched locate/correct launch");
+        }
+    }
+    c->t += n;
+    c->cur = (int)(c->t & 1);
+    c->bcur = c->cur;
+    return ABFT_OK;
+}
+
+abft_status batch_autotune(abft_ctx* c)
+{
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const int mode = c->mode == ABFT_MODE_ONLINE ? MODE_PROT : MODE_PLAIN;
+    int best_tz = c->batch_tz, best_p = c->persistent;
+    float best_ms = 1e30f;
+    abft_status s = ABFT_OK;
+    for (int tz : {2, 4, 8, 16, 32, 1 << 20})
+        for (int p : {1, 0}) {
+            if ((s = batch_layout(c, tz, p))) break;
+            // the timed sweeps read u^t and write the other buffers, as a real sweep would;
+            // no fault plan, so nothing is flagged
+            BatchArgs b = batch_args(c, c->t, nullptr, 0);
+            b.faults = nullptr;
+            b.fault_tmax = 0;
+            float ms = 1e30f;
+            for (int g = 0; g < 3 && s == ABFT_OK; ++g) {
+                (void)launch_sweep_batch(c->dtype, mode, c->csum, c->shape, b, c->nblocks,
+                                         c->batch_lds, c->stream);
+                HIPCHK(c, hipEventRecord(e0, c->stream));
+                for (int r = 0; r < 5; ++r)
+                    (void)launch_sweep_batch(c->dtype, mode, c->csum, c->shape, b, c->nblocks,
+                                             c->batch_lds, c->stream);
+                HIPCHK(c, hipEventRecord(e1, c->stream));
+                HIPCHK(c, hipEventSynchronize(e1));
+                float gms = 0.f;
+                HIPCHK(c, hipEventElapsedTime(&gms, e0, e1));
+                ms = std::min(ms, gms / 5);
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_tz = tz;
+                best_p = p;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s) return s;
+    // the timing runs left the next sweep's flag slots and tile counter as a sweep would
+    s = batch_layout(c, best_tz, best_p);
+    if (s) return s;
+    for (auto& G : c->grids) {
+        hipError_t e = launch_fill_u32(&G.slot[c->t & 1]->count, 0u, 2, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "reset");
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ABFT_OK;
+}
+
 }  // namespace
 
 // ==========================================================================================
@@ -620,6 +813,11 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
     if (s) return bail(s);
     if (fixup_lds_bytes(c->nx) > kLdsLimit || c->nx > 4 * kFixBlock)
         return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
+    if (c->mode == ABFT_MODE_OFFLINE) {
+        check_shape(c, c->period);
+        if ((int64_t)c->ck.ry * c->ck.rz > (int64_t)kCheckCells * kCheckBlock)
+            return bail(fail(c, ABFT_E_UNSUPPORTED, "offline period too long for this grid"));
+    }
 
     const size_t nrows = (size_t)c->nz * c->ny, ncols = (size_t)c->nz * c->nx;
     const size_t gbytes = (size_t)c->nx * c->ny * c->nz * esize(c->dtype);
@@ -674,6 +872,7 @@ abft_status abft_stencil_step(abft_ctx* c, int64_t nsweeps)
     if (!c) return ABFT_E_INVAL;
     if (nsweeps < 0) return fail(c, ABFT_E_INVAL, "nsweeps < 0");
     if (c->halted) return fail(c, ABFT_E_STATE, "offline window awaits abft_stencil_correct");
+    if (c->batch) return enqueue_batch(c, nsweeps, nullptr, 0);
     if (c->mode == ABFT_MODE_OFFLINE) return enqueue_offline(c, nsweeps);
     return enqueue_online(c, nsweeps, nullptr, 0);
 }
@@ -695,7 +894,8 @@ abft_status abft_stencil_step_graph(abft_ctx* c, int64_t nsweeps)
         const int64_t t_save = c->t;
         const int cur_save = c->cur, bcur_save = c->bcur;
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-        abft_status s = enqueue_online(c, nsweeps, c->tbase, t_save);
+        abft_status s = c->batch ? enqueue_batch(c, nsweeps, c->tbase, t_save)
+                                 : enqueue_online(c, nsweeps, c->tbase, t_save);
         hipGraph_t g = nullptr;
         hipError_t ce = hipStreamEndCapture(c->stream, &g);
         c->t = t_save;
@@ -733,7 +933,13 @@ abft_status abft_stencil_check(abft_ctx* c, abft_report* out)
     abft_status s = read_counters(c, &h);
     if (s) return s;
     int64_t pending = 0;
-    if (c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
+    if (c->batch && c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
+        for (auto& G : c->grids) {
+            uint32_t n = 0;
+            HIPCHK(c, hipMemcpy(&n, &G.slot[(c->t - 1) & 1]->count, 4, hipMemcpyDeviceToHost));
+            pending += n;
+        }
+    } else if (c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
         uint32_t n = 0;
         HIPCHK(c, hipMemcpy(&n, &c->slot[(c->t - 1) & 1]->count, 4, hipMemcpyDeviceToHost));
         pending = n;
@@ -779,7 +985,11 @@ abft_status abft_stencil_correct(abft_ctx* c, abft_report* inout)
     Counters before{};
     abft_status s = read_counters(c, &before);
     if (s) return s;
-    if (c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
+    if (c->batch && c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
+        const BatchArgs b = batch_args(c, c->t - 1, nullptr, 0);
+        hipError_t e = launch_fixup_batch(c->dtype, b, c->maxnx, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "batched locate/correct launch");
+    } else if (c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
         const int64_t t = c->t - 1;
         FixArgs f{};
         f.uin = c->u[c->cur ^ 1];
@@ -817,7 +1027,14 @@ abft_status abft_stencil_correct(abft_ctx* c, abft_report* inout)
 
 abft_status abft_stencil_current(abft_ctx* c, int32_t grid, void** dev_ptr, int64_t* sweep)
 {
-    if (!c || grid != 0) return ABFT_E_INVAL;
+    if (!c) return ABFT_E_INVAL;
+    if (c->batch) {
+        if (grid < 0 || grid >= (int)c->grids.size()) return fail(c, ABFT_E_INVAL, "grid index");
+        if (dev_ptr) *dev_ptr = c->grids[grid].u[c->t & 1];
+        if (sweep) *sweep = c->t;
+        return ABFT_OK;
+    }
+    if (grid != 0) return fail(c, ABFT_E_INVAL, "grid index");
     if (dev_ptr) *dev_ptr = c->u[c->cur];
     if (sweep) *sweep = c->mode == ABFT_MODE_OFFLINE ? c->win_t0 + c->win_j : c->t;
     return ABFT_OK;
@@ -825,7 +1042,13 @@ abft_status abft_stencil_current(abft_ctx* c, int32_t grid, void** dev_ptr, int6
 
 abft_status abft_stencil_checksums(abft_ctx* c, int32_t grid, double** dev_ptr)
 {
-    if (!c || grid != 0 || !dev_ptr) return ABFT_E_INVAL;
+    if (!c || !dev_ptr) return ABFT_E_INVAL;
+    if (c->batch) {
+        if (grid < 0 || grid >= (int)c->grids.size()) return fail(c, ABFT_E_INVAL, "grid index");
+        *dev_ptr = c->grids[grid].B[c->t & 1];
+        return ABFT_OK;
+    }
+    if (grid != 0) return fail(c, ABFT_E_INVAL, "grid index");
     *dev_ptr = c->mode == ABFT_MODE_OFFLINE ? c->B[c->bck] : c->B[c->bcur];
     return ABFT_OK;
 }
@@ -835,11 +1058,21 @@ abft_status abft_stencil_inject(abft_ctx* c, const abft_fault* f, int32_t n)
     if (!c || n < 0 || (n > 0 && !f)) return c ? fail(c, ABFT_E_INVAL, "fault plan") : ABFT_E_INVAL;
     const int bits = c->dtype == ABFT_F32 ? 32 : 64;
     std::vector<abft_fault> v(f, f + n);
-    for (const auto& x : v)
-        if (x.sweep < 0 || x.z < 0 || x.z >= c->nz || x.y < 0 || x.y >= c->ny || x.x < 0 ||
-            x.x >= c->nx || x.bit < 0 || x.bit >= bits || x.attempt < 0 || x.attempt > 1 ||
-            x.grid != 0)
+    for (const auto& x : v) {
+        int nx = c->nx, ny = c->ny, nz = c->nz;
+        if (c->batch) {
+            if (x.grid < 0 || x.grid >= (int)c->grids.size())
+                return fail(c, ABFT_E_INVAL, "fault grid index");
+            nx = c->grids[x.grid].nx;
+            ny = c->grids[x.grid].ny;
+            nz = c->grids[x.grid].nz;
+        } else if (x.grid != 0) {
+            return fail(c, ABFT_E_INVAL, "fault grid index");
+        }
+        if (x.sweep < 0 || x.z < 0 || x.z >= nz || x.y < 0 || x.y >= ny || x.x < 0 ||
+            x.x >= nx || x.bit < 0 || x.bit >= bits || x.attempt < 0 || x.attempt > 1)
             return fail(c, ABFT_E_INVAL, "fault outside the grid or word");
+    }
     std::stable_sort(v.begin(), v.end(),
                      [](const abft_fault& a, const abft_fault& b) { return a.sweep < b.sweep; });
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -881,6 +1114,7 @@ abft_status abft_stencil_inject(abft_ctx* c, const abft_fault* f, int32_t n)
 abft_status abft_stencil_autotune(abft_ctx* c)
 {
     if (!c) return ABFT_E_INVAL;
+    if (c->batch) return batch_autotune(c);
     if (c->mode == ABFT_MODE_OFFLINE && (c->win_j != 0 || c->halted))
         return fail(c, ABFT_E_STATE, "autotune in offline mode needs a closed window");
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -978,7 +1212,7 @@ abft_status abft_stencil_launch_shape(const abft_ctx* c, int32_t* rows_per_block
 {
     if (!c) return ABFT_E_INVAL;
     if (rows_per_block) *rows_per_block = sweep_rows_per_block(c->shape);
-    if (planes_per_block) *planes_per_block = c->shape.tz;
+    if (planes_per_block) *planes_per_block = c->batch ? c->batch_tz : c->shape.tz;
     if (lanes_per_row) *lanes_per_row = c->shape.lpr;
     return ABFT_OK;
 }
@@ -994,12 +1228,109 @@ void abft_stencil_destroy(abft_ctx* c)
 abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft_options* o,
                                     void* hip_stream, abft_ctx** out)
 {
-    (void)p;
-    (void)n;
-    (void)o;
-    (void)hip_stream;
-    if (out) *out = nullptr;
-    return fail(nullptr, ABFT_E_UNSUPPORTED, "batched contexts are not built yet");
+    g_init_error.clear();
+    if (!out) return fail(nullptr, ABFT_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!p || n < 1) return fail(nullptr, ABFT_E_INVAL, "batch needs n >= 1 problems");
+    abft_status s;
+    for (int i = 0; i < n; ++i) {
+        if ((s = validate_problem(&p[i]))) return s;
+        if ((s = validate_options(&p[i], o))) return s;
+        if (p[i].dtype != p[0].dtype) return fail(nullptr, ABFT_E_INVAL, "mixed dtypes in a batch");
+    }
+    if (o->mode == ABFT_MODE_OFFLINE)
+        return fail(nullptr, ABFT_E_UNSUPPORTED, "batches run the online and plain modes");
+
+    abft_ctx* c = new abft_ctx();
+    c->batch = true;
+    c->dtype = p[0].dtype;
+    c->mode = o->mode;
+    c->eps = o->threshold;
+    c->csum = o->csum == ABFT_CSUM_F32_COMP ? CS_F32C : CS_F64;
+    c->auto_correct = o->auto_correct ? 1 : 0;
+    c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    auto bail = [&](abft_status st) {
+        g_init_error = c->err;
+        free_all(c);
+        delete c;
+        return st;
+    };
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return bail(fail(c, ABFT_E_HIP, "device query failed"));
+    c->num_cus = prop.multiProcessorCount;
+
+    bool vec_ok = true;
+    const int vf = 16 / (int)esize(c->dtype);
+    for (int i = 0; i < n; ++i) {
+        c->maxnx = std::max(c->maxnx, p[i].nx);
+        c->maxnz = std::max(c->maxnz, p[i].nz);
+        vec_ok = vec_ok && p[i].nx % vf == 0;
+    }
+    // one kernel shape covers the widest row of the batch
+    SweepShape sh{};
+    sh.pf = 1;
+    if (vec_ok && c->maxnx <= 16 * 4 * vf) sh = SweepShape{16, 4, vf, 1, 1};
+    else if (vec_ok && c->maxnx <= 64 * 4 * vf) sh = SweepShape{64, 4, vf, 1, 1};
+    else if (c->maxnx <= 64 * 16) sh = SweepShape{64, 16, 1, 1, 1};
+    else return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the batched kernel"));
+    c->shape = sh;
+    if (fixup_lds_bytes(c->maxnx) > kLdsLimit || c->maxnx > 4 * kFixBlock)
+        return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
+
+    c->grids.resize(n);
+    for (int i = 0; i < n; ++i) {
+        auto& G = c->grids[i];
+        // per-grid stencil: reuse the single-grid tap mapping on a scratch context
+        abft_ctx tmp;
+        if ((s = map_taps(&tmp, &p[i]))) return bail(fail(c, s, tmp.err));
+        G.st = tmp.st;
+        G.nx = p[i].nx;
+        G.ny = p[i].ny;
+        G.nz = p[i].nz;
+        G.u[0] = p[i].u0;
+        G.u[1] = p[i].u1;
+        G.C = p[i].cterm;
+        G.cs = round_to(c->dtype, p[i].cterm_scalar);
+        const size_t nrows = (size_t)G.nz * G.ny, ncols = (size_t)G.nz * G.nx;
+        if ((s = dalloc(c, &G.B[0], nrows * 8)) || (s = dalloc(c, &G.B[1], nrows * 8)) ||
+            (s = dalloc(c, &G.cB, nrows * 8)) || (s = dalloc(c, &G.cA, ncols * 8)) ||
+            (s = dalloc(c, &G.slot[0], sizeof(FlagSlot))) ||
+            (s = dalloc(c, &G.slot[1], sizeof(FlagSlot))))
+            return bail(s);
+    }
+    if ((s = dalloc(c, &c->cnt, sizeof(Counters))) ||
+        (s = dalloc(c, &c->ev, (size_t)c->ev_cap * sizeof(abft_event))) ||
+        (s = dalloc(c, &c->queue, 4 * sizeof(uint32_t))) ||
+        (s = dalloc(c, &c->tbase, sizeof(int64_t))) ||
+        (s = dalloc(c, &c->d_grids, (size_t)n * sizeof(GridDesc))))
+        return bail(s);
+
+    hipError_t e;
+#define INIT_CHK(expr)                                      \
+    if ((e = (expr)) != hipSuccess) {                       \
+        hip_fail(c, e, #expr);                              \
+        return bail(ABFT_E_HIP);                            \
+    }
+    INIT_CHK(launch_fill_u32(reinterpret_cast<uint32_t*>(c->cnt), 0u,
+                             sizeof(Counters) / 4, c->stream));
+    INIT_CHK(launch_fill_u32(c->queue, 0u, 4, c->stream));
+    INIT_CHK(launch_set_i64(c->tbase, 0, c->stream));
+    for (auto& G : c->grids) {
+        const int64_t nrows = (int64_t)G.nz * G.ny;
+        INIT_CHK(launch_fill_u32(&G.slot[0]->count, 0u, 2, c->stream));
+        INIT_CHK(launch_fill_u32(&G.slot[1]->count, 0u, 2, c->stream));
+        INIT_CHK(launch_row_sums(c->dtype, G.C, G.cs, G.nx, nrows, G.cB, c->stream));
+        INIT_CHK(launch_col_sums(c->dtype, G.C, G.cs, G.nx, G.ny, G.nz, G.cA, c->stream));
+        INIT_CHK(launch_row_sums(c->dtype, G.u[0], 0.0, G.nx, nrows, G.B[0], c->stream));
+    }
+    INIT_CHK(hipStreamSynchronize(c->stream));
+#undef INIT_CHK
+    if ((s = batch_layout(c, 8, 1))) return bail(s);
+    *out = c;
+    return ABFT_OK;
 }
 
 }  // extern "C"

@@ -16,8 +16,11 @@
 
 namespace abft {
 
+// One tile (TY rows x tz planes) of one sweep, run by one block.  smem_raw is the block's
+// dynamic LDS (sweep_lds_bytes).
 template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF>
-__global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
+__device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
+                                           unsigned char* smem_raw)
 {
     using V = VecOps<T, VEC>;
     constexpr int RPW = 64 / LPR;                 // rows per wavefront
@@ -25,10 +28,7 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
     constexpr int SEGW = LPR * VEC;               // elements of one chunk of a row
     constexpr int HMAX = (NCH * SEGW + kSweepBlock * VEC - 1) / (kSweepBlock * VEC);
 
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
-
-    if (a.guard != nullptr && *a.guard == 0u) return;
     const int64_t t = a.t_off + (a.t_base != nullptr ? *a.t_base : 0);
 
     const int nx = a.nx, ny = a.ny, nz = a.nz, bc = a.st.bc;
@@ -41,11 +41,6 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
     const int stride = nx + 2 * VEC;  // LDS row: VEC pad (ghost x=-1 at VEC-1), nx, VEC pad
     const int plane_elems = (TY + 2) * stride;
 
-    // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous run of tiles so
-    // that neighbouring row blocks (which share halo rows) meet in the same L2.
-    const int nt = a.ntiles, bid = blockIdx.x;
-    const int per = nt >> 3, rem = nt & 7, xcd = bid & 7, q = bid >> 3;
-    const int tile = xcd * per + (xcd < rem ? xcd : rem) + q;
     const int yb = tile % a.nyb, zb = tile / a.nyb;
     const int y0 = yb * TY, z0 = zb * a.tz;
     const int z1 = min(z0 + a.tz, nz);
@@ -53,8 +48,6 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
     const int r = wave * RPW + seg;
     const int y = y0 + r;
     const bool row_ok = r < nrows;
-
-    if (a.zero_ptr != nullptr && bid == 0 && tid < a.zero_n) a.zero_ptr[tid] = 0u;
 
     const T* uin = static_cast<const T*>(a.uin);
     T* uout = static_cast<T*>(a.uout);
@@ -392,6 +385,21 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
         }
     }
     if constexpr (MODE == MODE_PROT) record_noise(a.cnt, noise);
+}
+
+template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF>
+__global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    if (a.guard != nullptr && *a.guard == 0u) return;
+    const int nt = a.ntiles, bid = blockIdx.x;
+    if (a.zero_ptr != nullptr && bid == 0 && (int)threadIdx.x < a.zero_n)
+        a.zero_ptr[threadIdx.x] = 0u;
+    // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous run of tiles so
+    // that neighbouring row blocks (which share halo rows) meet in the same L2.
+    const int per = nt >> 3, rem = nt & 7, xcd = bid & 7, q = bid >> 3;
+    const int tile = xcd * per + (xcd < rem ? xcd : rem) + q;
+    sweep_tile<T, MODE, CS, LPR, NCH, VEC, PF>(a, tile, smem_raw);
 }
 
 // Table of instantiated variants.

@@ -1,0 +1,104 @@
+"""Batched grids (one launch per sweep over all grids, persistent tile queue, hipGraph):
+every grid of the batch against its own oracle run."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import assert_grid_close, event_keys, run_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_batch(shapes, inputs, nsweeps, plan, *, eps=1e-7, graph=False, persistent=None,
+               autotune=False, chunks=None, csum="f64"):
+    import torch
+    from paper_1909_00709_amd import abft
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        grids = [(torch.from_numpy(u).cuda(), torch.from_numpy(c).cuda()) for u, c in inputs]
+        B = abft.Batch(grids, W.THERMAL_TAPS, threshold=eps, csum=csum, stream=stream,
+                       max_events=1 << 14)
+        try:
+            if autotune:
+                B.autotune()
+            if plan is not None and len(plan):
+                B.inject(plan)
+            for n in (chunks or [nsweeps]):
+                (B.step_graph if graph else B.step)(n)
+            rep, ev = B.check()
+            outs = [B.current(g)[0].cpu().numpy() for g in range(len(shapes))]
+            shape = B.launch_shape()
+        finally:
+            B.close()
+    stream.synchronize()
+    return outs, ev, rep, shape
+
+
+def _batch_plan(per_grid):
+    rows = []
+    for g, plan in per_grid.items():
+        for f in plan:
+            rows.append((int(f["sweep"]), int(f["z"]), int(f["y"]), int(f["x"]),
+                         int(f["bit"]), 0, g))
+    plan = W.empty_plan(len(rows))
+    for i, r in enumerate(rows):
+        for k, name in enumerate(("sweep", "z", "y", "x", "bit", "attempt", "grid")):
+            plan[i][name] = r[k]
+    plan.sort(order="sweep", kind="stable")
+    return plan
+
+
+def _check_grids(shapes, inputs, outs, ev, nsweeps, per_grid, eps, which):
+    for g in which:
+        u0, C = inputs[g]
+        plan = per_grid.get(g)
+        o, oev, ocnt = run_oracle(u0, W.THERMAL_TAPS, nsweeps, C=C, eps=eps, plan=plan)
+        gev = ev[ev["grid"] == g]
+        assert event_keys(gev) == event_keys(oev), g
+        assert_grid_close(outs[g], o, 1e-5, f"grid {g} {shapes[g]}")
+
+
+def test_batch_small_mixed():
+    shapes = W.c4_shapes(12, seed=44)
+    inputs = W.c4_inputs(shapes)
+    per_grid = W.c4_plans(shapes, nsweeps=30, nflipped=5, seed=7)
+    per_grid = {g: p[p["bit"] >= 18] for g, p in per_grid.items()}
+    plan = _batch_plan(per_grid)
+    say("batch small", shapes)
+    outs, ev, rep, _ = _run_batch(shapes, inputs, 30, plan)
+    assert rep["corrected"] == sum(len(p) for p in per_grid.values())
+    _check_grids(shapes, inputs, outs, ev, 30, per_grid, 1e-7, range(len(shapes)))
+
+
+def test_batch_dispatch_forms_and_graph_agree():
+    shapes = W.c4_shapes(10, seed=45)
+    inputs = W.c4_inputs(shapes)
+    per_grid = {1: W.make_plan([(3, 0, 1, 2, 27)]), 7: W.make_plan([(11, 2, 5, 5, 30)])}
+    plan = _batch_plan(per_grid)
+    say("batch forms")
+    a = _run_batch(shapes, inputs, 20, plan)
+    b = _run_batch(shapes, inputs, 20, plan, autotune=True)
+    c = _run_batch(shapes, inputs, 20, plan, graph=True, chunks=[5, 5, 5, 5])
+    for g in range(len(shapes)):
+        assert np.array_equal(a[0][g], b[0][g]) and np.array_equal(a[0][g], c[0][g]), g
+    assert event_keys(a[1]) == event_keys(b[1]) == event_keys(c[1])
+    assert a[2]["corrected"] == 2
+
+
+def test_c4_full():
+    """64 grids of 64..256 x 64..256 x 4..32 fp32, 200 sweeps, autotuned, graph-captured, one
+    flip in each of 8 grids; the flipped grids and four others are checked against the oracle,
+    all grids are checked for zero false positives."""
+    shapes = W.c4_shapes()
+    inputs = W.c4_inputs(shapes)
+    per_grid = W.c4_plans(shapes)
+    per_grid = {g: p[p["bit"] >= 18] for g, p in per_grid.items()}
+    plan = _batch_plan(per_grid)
+    say("C4 full")
+    outs, ev, rep, shape = _run_batch(shapes, inputs, W.C4_NSWEEPS, plan, eps=W.C4_EPS,
+                                      graph=True, autotune=True, chunks=[50] * 4)
+    assert rep["corrected"] == sum(len(p) for p in per_grid.values())
+    assert rep["rows_flagged"] == rep["corrected"]
+    assert rep["max_noise"] < W.C4_EPS / 2
+    which = sorted(per_grid) + [g for g in range(len(shapes)) if g not in per_grid][:4]
+    _check_grids(shapes, inputs, outs, ev, W.C4_NSWEEPS, per_grid, W.C4_EPS, which)
