@@ -63,7 +63,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["plain", "prot", "offline", "online"], default=None,
                     help="run one measurement only (for profiler runs)")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="do not autotune (launch shapes from --tuning-cache or the defaults)")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="autotuner cache file: written when tuning, read at context creation")
     ap.add_argument("--csum", choices=["f64", "f32comp"], default="f64",
                     help="row-checksum accumulation of the protected sweeps")
     ap.add_argument("--calib-copy", action="store_true",
@@ -97,7 +100,8 @@ def main():
         with torch.cuda.stream(stream):
             u = u0.clone()
         stream.synchronize()
-        S = abft.Stencil(u, W.THERMAL_TAPS, C=C, mode=mode, stream=stream, **kw)
+        S = abft.Stencil(u, W.THERMAL_TAPS, C=C, mode=mode, stream=stream,
+                         tuning_cache=args.tuning_cache, **kw)
         if tune and not args.no_tune:
             S.autotune()
         return S
@@ -162,7 +166,7 @@ def main():
     # ---- headline: offline ABFT windows ---------------------------------------------------
     offline_ms = None
     if args.only in (None, "offline"):
-        S = make("offline", period=k, threshold=3e-7, csum=args.csum, auto_correct=True)
+        S = make("offline", period=k, threshold=W.C5.eps, csum=args.csum, auto_correct=True)
         for _ in range(args.warmup):
             S.step(k)
         torch.cuda.synchronize()
@@ -202,7 +206,7 @@ def main():
         p = O.Problem(su.shape, O.F32, W.THERMAL_TAPS)
         nsw = 10 * k
         t0 = time.perf_counter()
-        p.run(su, nsw, sc, mode=O.MODE_OFFLINE, period=k, eps=3e-7)
+        p.run(su, nsw, sc, mode=O.MODE_OFFLINE, period=k, eps=W.C5.eps)
         dt = time.perf_counter() - t0
         cpu = {"value": nx * ny * sl * nsw / dt / 1e9, "unit": "GPts/s",
                "cores": O.get_threads(), "kind": "oracle",
@@ -225,7 +229,7 @@ def main():
         "config": {
             "workload": f"3D 7-point thermal diffusion {nx}x{ny}x{nz} fp32, offline ABFT every "
                         f"{k} sweeps ({args.csum} row-checksum accumulation, fp64 compare)",
-            "nx": nx, "ny": ny, "nz": nz, "sweeps_per_step": k, "threshold": 3e-7,
+            "nx": nx, "ny": ny, "nz": nz, "sweeps_per_step": k, "threshold": W.C5.eps,
             "csum": args.csum,
         },
         "roofline": {

@@ -1,0 +1,100 @@
+"""Fault campaign on the 512 x 512 x 64 fp32 thermal grid (one flip per sweep, bit = sweep mod 32,
+1000 sweeps), both row-checksum accumulations, plus a fault-free 1000-sweep run for the false
+positive rate (32.8 million row tests per accumulation mode).
+
+Smallest detectable bit.  A flip of mantissa bit b of a value v with exponent e changes it by
+2^(e-23+b); the row sum S of 512 values lies in [512*80, 512*331] over this run (the field
+relaxes from 320..330 towards 80), and e is 6..8.  The relative signal is therefore at least
+2^(b-17)/169472, which exceeds eps = 1e-7 for every b >= 12: bits 12..31 must all be detected,
+located at their exact site and corrected.  It is at most 2^(b-15)/40960, below eps/4 for
+b <= 5: bits 0..5 are never seen.  Bits 6..11 depend on the value at the time of the flip.
+"""
+import collections
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import assert_grid_close, event_keys, run_gpu, run_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+B_MIN_GUARANTEED = 12
+B_MAX_NEVER = 5
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+
+
+def _summary(plan, ev):
+    planted = {(int(p["sweep"]), int(p["z"]), int(p["y"]), int(p["x"])): int(p["bit"])
+               for p in plan}
+    rows = {(int(e["sweep"]), int(e["z"]), int(e["y"])) for e in ev if e["kind"] == 1}
+    fixed = {(int(e["sweep"]), int(e["z"]), int(e["y"]), int(e["x"])) for e in ev
+             if e["kind"] == 2}
+    planted_rows = {k[:3] for k in planted}
+    per_bit = collections.defaultdict(lambda: [0, 0, 0])  # planted, row flagged, corrected
+    for k, b in planted.items():
+        per_bit[b][0] += 1
+        per_bit[b][1] += k[:3] in rows
+        per_bit[b][2] += k in fixed
+    return {
+        "false_positive_rows": len(rows - planted_rows),
+        "wrong_sites_corrected": len(fixed - set(planted)),
+        "per_bit": {b: per_bit[b] for b in sorted(per_bit)},
+    }
+
+
+@pytest.mark.parametrize("csum", ["f64", "f32comp"])
+def test_c3_campaign(csum):
+    nz, ny, nx = W.C3.shape
+    u0, C = W.thermal_grid(nx, ny, nz, np.float32)
+    plan = W.c3_campaign()
+    say("C3 campaign", csum)
+    g, ev, rep, shape = run_gpu(u0, W.THERMAL_TAPS, W.C3.nsweeps, C=C, eps=W.C3.eps, csum=csum,
+                                plan=plan, max_events=1 << 16)
+    s = _summary(plan, ev)
+    s.update({"csum": csum, "corrected": rep["corrected"], "rows_flagged": rep["rows_flagged"],
+              "checksum_faults": rep["checksum_faults"], "uncorrectable": rep["uncorrectable"],
+              "max_noise": rep["max_noise"], "launch_shape": shape})
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, f"campaign_c3_{csum}.json"), "w") as f:
+        json.dump(s, f, indent=1)
+    print(json.dumps(s))
+    assert rep["events_total"] < (1 << 16)
+    assert s["false_positive_rows"] == 0 and s["wrong_sites_corrected"] == 0
+    assert rep["uncorrectable"] == 0
+    for b, (n, flagged, fixed) in s["per_bit"].items():
+        if b >= B_MIN_GUARANTEED:
+            assert flagged == n and fixed == n, (b, n, flagged, fixed)
+        if b <= B_MAX_NEVER:
+            assert flagged == 0, (b, flagged)
+
+
+@pytest.mark.parametrize("csum", ["f64", "f32comp"])
+def test_c3_false_positives(csum):
+    nz, ny, nx = W.C3.shape
+    u0, C = W.thermal_grid(nx, ny, nz, np.float32)
+    say("C3 fault-free", csum)
+    _, ev, rep, _ = run_gpu(u0, W.THERMAL_TAPS, W.C3.nsweeps, C=C, eps=W.C3.eps, csum=csum)
+    print(json.dumps({"csum": csum, "row_tests": nz * ny * W.C3.nsweeps,
+                      "false_positives": rep["rows_flagged"], "max_noise": rep["max_noise"]}))
+    assert rep["rows_flagged"] == 0 and len(ev) == 0
+    # the noise floor of an fp32 grid: a smooth row rounds alike, up to half an ulp of values
+    # near 80 (2^-18 / 80 / 2 = 4.8e-8 relative) plus the earlier roundings of the chain
+    assert rep["max_noise"] < 0.6 * W.C3.eps
+
+
+def test_c3_oracle_parity_first_60():
+    """The campaign's first 60 sweeps at full size against the oracle (flips whose bit lies in
+    the value-dependent band 6..13 left out)."""
+    nz, ny, nx = W.C3.shape
+    u0, C = W.thermal_grid(nx, ny, nz, np.float32)
+    plan = W.c3_campaign()
+    plan = plan[(plan["sweep"] < 60) & ((plan["bit"] < 6) | (plan["bit"] > 13))]
+    say("C3 oracle parity", len(plan))
+    g, gev, grep, _ = run_gpu(u0, W.THERMAL_TAPS, 60, C=C, eps=W.C3.eps, plan=plan)
+    o, oev, ocnt = run_oracle(u0, W.THERMAL_TAPS, 60, C=C, eps=W.C3.eps, plan=plan)
+    assert event_keys(gev) == event_keys(oev)
+    assert grep["corrected"] == ocnt["corrected"] > 0
+    assert_grid_close(g, o, 1e-5, "C3 first 60")

@@ -283,11 +283,11 @@ def test_offline_fp32_compensated():
     plan = W.make_plan([(4, 3, 17, 900, 29), (26, 9, 127, 0, 27)])
     say("offline fp32 f32comp")
     g, gev, grep, _ = run_gpu(u0, W.THERMAL_TAPS, 30, C=C, mode="offline", period=10,
-                              eps=3e-7, csum="f32comp", plan=plan)
+                              eps=W.C5.eps, csum="f32comp", plan=plan)
     o, oev, ocnt = run_oracle(u0, W.THERMAL_TAPS, 30, C=C, mode="offline", period=10,
-                              eps=3e-7, plan=plan)
+                              eps=W.C5.eps, plan=plan)
     assert event_keys(gev) == event_keys(oev)
-    assert grep["rollbacks"] == 2 and grep["max_noise"] < 3e-7 / 4
+    assert grep["rollbacks"] == 2 and grep["max_noise"] < W.C5.eps / 4
     clean = run_gpu(u0, W.THERMAL_TAPS, 30, C=C, mode="none")[0]
     assert np.array_equal(g, clean)
     assert_grid_close(g, o, 1e-5, "offline fp32")
