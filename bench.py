@@ -28,11 +28,13 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources the sweep kernel is compiled from (not the host runtime)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1909_00709_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        if f in ("abft_sweep.h", "abft_device.h", "abft_internal.h") or f.startswith("sweep_"):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
