@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_batch_kernel(const BatchArg
         a.faults = b.faults;
         a.fault_first = b.fault_first;
         a.fault_tmax = b.fault_tmax;
-        sweep_tile<T, MODE, CS, LPR, NCH, VEC, 1>(a, gt.y, smem_raw);
+        sweep_tile<T, MODE, CS, LPR, NCH, VEC, 1, kSweepBlock / 64>(a, gt.y, smem_raw);
         if (!b.persistent) break;
         __syncthreads();
         it = sh_next;
@@ -123,6 +123,7 @@ static int occupancy_t(const SweepShape& s, size_t lds)
 bool batch_shape_supported(int dtype, const SweepShape& s)
 {
     const int vf = dtype == ABFT_F32 ? 4 : 2;
+    if (s.nw != kSweepBlock / 64) return false;
     if (s.vec == vf) return (s.lpr == 16 || s.lpr == 64) && s.nch == 4;
     return s.vec == 1 && s.lpr == 64 && s.nch == 16;
 }

@@ -10,7 +10,8 @@
 namespace abft {
 
 constexpr int kMaxFlags = 1024;   // flagged rows remembered per sweep for location
-constexpr int kSweepBlock = 256;  // threads per block of the sweep kernel (4 wavefronts)
+constexpr int kSweepBlock = 256;  // threads per block of the batched sweep (4 wavefronts)
+constexpr int kWideBlockLaneBytes = 64;  // most row bytes per lane for 8-wavefront sweep blocks
 constexpr int kFixBlock = 512;    // threads of the single locate/correct block
 constexpr int kCheckBlock = 256;  // threads per block of the offline window check
 constexpr int kMaxPeriod = 32;    // longest offline window handled by one check launch
@@ -164,6 +165,7 @@ struct SweepShape {
     int32_t vec;   // elements per 16-byte access (1 for rows that are not 16-byte multiples)
     int32_t tz;    // planes per block
     int32_t pf;    // planes loaded ahead of the one computed: 1 or 2
+    int32_t nw = 4;  // wavefronts per block: 4 or 8 (each holds 64 / lpr rows)
 };
 
 bool sweep_shape_supported(int dtype, const SweepShape& s);

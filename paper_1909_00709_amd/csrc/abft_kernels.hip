@@ -438,7 +438,8 @@ __global__ void set_i64_kernel(int64_t* p, int64_t v)
 bool sweep_shape_supported(int dtype, const SweepShape& s)
 {
     const int vf = dtype == ABFT_F32 ? 4 : 2;
-    if (s.tz < 1) return false;
+    if (s.tz < 1 || (s.nw != 4 && s.nw != 8)) return false;
+    if (s.nw == 8 && s.nch * s.vec * (vf == 4 ? 4 : 8) > kWideBlockLaneBytes) return false;
     if (s.pf == 2) return s.vec == vf && s.lpr == 64 && (s.nch == 2 || s.nch == 4);
     if (s.pf != 1) return false;
     if (s.vec == vf) {
@@ -450,7 +451,7 @@ bool sweep_shape_supported(int dtype, const SweepShape& s)
     return false;
 }
 
-int sweep_rows_per_block(const SweepShape& s) { return (kSweepBlock / 64) * (64 / s.lpr); }
+int sweep_rows_per_block(const SweepShape& s) { return s.nw * (64 / s.lpr); }
 
 size_t sweep_lds_bytes(int dtype, int nx, const SweepShape& s)
 {

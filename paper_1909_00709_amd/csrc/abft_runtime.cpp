@@ -24,7 +24,8 @@ thread_local std::string g_init_error;
 constexpr int kDefaultEvents = 4096;
 constexpr size_t kLdsLimit = 64 * 1024;       // check and locate kernels
 constexpr size_t kSweepLdsLimit = 160 * 1024; // gfx950: 160 KB of LDS per compute unit
-constexpr int kTargetTiles = 1024;
+constexpr int kTargetTiles = 1024;     // blocks of 4 wavefronts per sweep, untuned default
+constexpr int kTargetTilesWide = 256;  // blocks of 8 wavefronts: one per compute unit
 
 size_t esize(int dtype) { return dtype == ABFT_F32 ? 4 : 8; }
 
@@ -176,8 +177,10 @@ abft_status map_taps(abft_ctx* c, const abft_problem* p)
 }
 
 // Default launch shape: 16-byte accesses when rows are 16-byte multiples, 16 lanes per row for
-// short rows (4 rows per wavefront), 64 lanes for long rows, and enough z-slabs for ~1024
-// blocks.
+// short rows (4 rows per wavefront), 64 lanes for long rows.  Grids with rows enough for one
+// block of 8 wavefronts per compute unit take that (the deeper block halves the share of halo
+// rows it loads and keeps more loads in flight per CU), cut into about that many z-slabs;
+// smaller grids take blocks of 4 wavefronts and enough z-slabs for ~1024 blocks.
 bool default_shape(int dtype, int nx, int ny, int nz, SweepShape* s)
 {
     const int vf = 16 / (int)esize(dtype);
@@ -202,10 +205,19 @@ bool default_shape(int dtype, int nx, int ny, int nz, SweepShape* s)
         else return false;
     }
     r.pf = 1;
-    const int ty = sweep_rows_per_block(r);
-    const int nyb = (ny + ty - 1) / ty;
-    int nzb = std::max(1, std::min(nz, (kTargetTiles + nyb - 1) / nyb));
-    r.tz = (nz + nzb - 1) / nzb;
+    auto slabs = [&](int target) {
+        const int ty = sweep_rows_per_block(r);
+        const int64_t nyb = (ny + ty - 1) / ty;
+        const int64_t nzb = std::max<int64_t>(1, std::min<int64_t>(nz, (target + nyb - 1) / nyb));
+        r.tz = (int)((nz + nzb - 1) / nzb);
+        return nyb * nz;  // blocks at one plane per block
+    };
+    r.nw = 8;
+    if (slabs(kTargetTilesWide) < kTargetTilesWide || !sweep_shape_supported(dtype, r) ||
+        sweep_lds_bytes(dtype, nx, r) > kSweepLdsLimit) {
+        r.nw = 4;
+        slabs(kTargetTiles);
+    }
     *s = r;
     return true;
 }
@@ -252,6 +264,7 @@ bool cache_lookup(const abft_ctx* c, SweepShape* s)
         SweepShape r{};
         if (!(in >> d >> nx >> ny >> nz >> m >> cs >> r.lpr >> r.nch >> r.vec >> r.tz)) continue;
         if (!(in >> r.pf)) r.pf = 1;
+        if (!(in >> r.nw)) r.nw = 4;
         std::ostringstream k;
         k << d << ' ' << nx << ' ' << ny << ' ' << nz << ' ' << m << ' ' << cs;
         if (k.str() == key) {
@@ -277,7 +290,7 @@ void cache_store(const abft_ctx* c)
     std::ofstream f(c->cache_path, std::ios::trunc);
     for (auto& l : keep) f << l << '\n';
     f << cache_key(c) << ' ' << c->shape.lpr << ' ' << c->shape.nch << ' ' << c->shape.vec << ' '
-      << c->shape.tz << ' ' << c->shape.pf << '\n';
+      << c->shape.tz << ' ' << c->shape.pf << ' ' << c->shape.nw << '\n';
 }
 
 // Offline check tiles: an interior of tyi rows x tzi layers of the checksum plane plus a halo
@@ -1136,18 +1149,19 @@ abft_status abft_stencil_autotune(abft_ctx* c)
         if (vec > 1 && c->nx % vec) continue;
         for (int lpr : {16, 64})
             for (int nch : {1, 2, 4, 8, 16}) {
-                for (int pf : {1, 2}) {
-                    SweepShape sh{lpr, nch, vec, 1, pf};
-                    if (!sweep_shape_supported(c->dtype, sh)) continue;
-                    if ((int64_t)lpr * nch * vec < c->nx) continue;
-                    if ((int64_t)lpr * (nch / 2) * vec >= c->nx && nch > 1) continue;  // minimal
-                    if (sweep_lds_bytes(c->dtype, c->nx, sh) > kSweepLdsLimit) continue;
-                    for (int tz : {2, 4, 8, 16, 32, 64, 128}) {
-                        if (tz > c->nz && tz != 2) continue;
-                        sh.tz = std::min(tz, c->nz);
-                        cands.push_back(sh);
+                for (int pf : {1, 2})
+                    for (int nw : {4, 8}) {
+                        SweepShape sh{lpr, nch, vec, 1, pf, nw};
+                        if (!sweep_shape_supported(c->dtype, sh)) continue;
+                        if ((int64_t)lpr * nch * vec < c->nx) continue;
+                        if ((int64_t)lpr * (nch / 2) * vec >= c->nx && nch > 1) continue;  // minimal
+                        if (sweep_lds_bytes(c->dtype, c->nx, sh) > kSweepLdsLimit) continue;
+                        for (int tz : {2, 4, 8, 16, 32, 64, 128}) {
+                            if (tz > c->nz && tz != 2) continue;
+                            sh.tz = std::min(tz, c->nz);
+                            cands.push_back(sh);
+                        }
                     }
-                }
             }
         if (!cands.empty()) break;  // prefer 16-byte accesses when they apply
     }

@@ -1,7 +1,7 @@
 // The fused sweep kernel: Eq.(1) for a radius-1 star stencil, with the row checksum (Eq.(3)),
 // its prediction (Theorem 1, Eq.(5)) and the mismatch test (Section 3.4) in the same pass.
 //
-// Work decomposition.  A block of 4 wavefronts owns TY whole rows (y0 .. y0+TY-1) of a slab of
+// Work decomposition.  A block of NW wavefronts (4 or 8) owns TY whole rows (y0 .. y0+TY-1) of a slab of
 // planes z0 .. z0+tz-1 and marches along z.  Each row belongs to LPR lanes of one wavefront;
 // a lane holds NCH chunks of VEC consecutive x (16-byte accesses), so the row's checksum is a
 // reduction across the row's lanes (DPP) and never needs another pass over the data.  The
@@ -27,15 +27,16 @@ constexpr bool kStencilAccF64 = false;
 
 // One tile (TY rows x tz planes) of one sweep, run by one block.  smem_raw is the block's
 // dynamic LDS (sweep_lds_bytes).
-template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF>
+template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF, int NW>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                                            unsigned char* smem_raw)
 {
     using V = VecOps<T, VEC>;
-    constexpr int RPW = 64 / LPR;                 // rows per wavefront
-    constexpr int TY = (kSweepBlock / 64) * RPW;  // rows per block
-    constexpr int SEGW = LPR * VEC;               // elements of one chunk of a row
-    constexpr int HMAX = (NCH * SEGW + kSweepBlock * VEC - 1) / (kSweepBlock * VEC);
+    constexpr int NT = NW * 64;       // threads per block
+    constexpr int RPW = 64 / LPR;     // rows per wavefront
+    constexpr int TY = NW * RPW;      // rows per block
+    constexpr int SEGW = LPR * VEC;   // elements of one chunk of a row
+    constexpr int HMAX = (NCH * SEGW + NT * VEC - 1) / (NT * VEC);
 
     T* lds = reinterpret_cast<T*>(smem_raw);
     const int64_t t = a.t_off + (a.t_base != nullptr ? *a.t_base : 0);
@@ -121,7 +122,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             const int yy = h ? yh1 : yh0;
 #pragma unroll
             for (int k = 0; k < HMAX; ++k) {
-                const int x = (tid + k * kSweepBlock) * VEC;
+                const int x = (tid + k * NT) * VEC;
                 if (x < nx && yy >= 0) {
                     V::load(uin + (size_t)zz * pstride + (size_t)yy * nx + x, d[h][k]);
                 } else {
@@ -194,7 +195,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             T* row = buf + (h ? lh1 : 0) * stride + VEC;
 #pragma unroll
             for (int k = 0; k < HMAX; ++k) {
-                const int x = (tid + k * kSweepBlock) * VEC;
+                const int x = (tid + k * NT) * VEC;
                 if (x < nx) {
                     V::store(row + x, hc[h][k]);
                     put_ghosts(row, x, hc[h][k]);
@@ -398,8 +399,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
     if constexpr (MODE == MODE_PROT) record_noise(a.cnt, noise);
 }
 
-template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF>
-__global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
+template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF, int NW>
+__global__ void __launch_bounds__(NW * 64) sweep_kernel(const SweepArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     if (a.guard != nullptr && *a.guard == 0u) return;
@@ -410,16 +411,16 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_kernel(const SweepArgs a)
     // that neighbouring row blocks (which share halo rows) meet in the same L2.
     const int per = nt >> 3, rem = nt & 7, xcd = bid & 7, q = bid >> 3;
     const int tile = xcd * per + (xcd < rem ? xcd : rem) + q;
-    sweep_tile<T, MODE, CS, LPR, NCH, VEC, PF>(a, tile, smem_raw);
+    sweep_tile<T, MODE, CS, LPR, NCH, VEC, PF, NW>(a, tile, smem_raw);
 }
 
 // Table of instantiated variants.
 template <typename T, int MODE, int CS>
 hipError_t launch_sweep_t(const SweepShape& s, const SweepArgs& a, hipStream_t st, size_t lds)
 {
-#define ABFT_SWEEP_CASE_PF(LPR_, NCH_, VEC_, PF_)                                              \
-    if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_ && s.pf == PF_) {                      \
-        auto kern = sweep_kernel<T, MODE, CS, LPR_, NCH_, VEC_, PF_>;                          \
+#define ABFT_SWEEP_CASE_NW(LPR_, NCH_, VEC_, PF_, NW_)                                        \
+    if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_ && s.pf == PF_ && s.nw == NW_) {       \
+        auto kern = sweep_kernel<T, MODE, CS, LPR_, NCH_, VEC_, PF_, NW_>;                     \
         static int lds_set = 0;                                                                \
         if (lds > 65536 && (int)lds > lds_set) {                                               \
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),             \
@@ -428,8 +429,15 @@ hipError_t launch_sweep_t(const SweepShape& s, const SweepArgs& a, hipStream_t s
             if (e != hipSuccess) return e;                                                     \
             lds_set = (int)lds;                                                                \
         }                                                                                      \
-        hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(kSweepBlock), lds, st, a);               \
+        hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(NW_ * 64), lds, st, a);                  \
         return hipGetLastError();                                                              \
+    }
+// Blocks of 8 wavefronts only where a lane's share of a row is at most 64 bytes: with more,
+// the planes held in registers exceed the 256 registers a lane may have at that block size.
+#define ABFT_SWEEP_CASE_PF(LPR_, NCH_, VEC_, PF_)                                              \
+    ABFT_SWEEP_CASE_NW(LPR_, NCH_, VEC_, PF_, 4)                                               \
+    if constexpr (NCH_ * VEC_ * sizeof(T) <= kWideBlockLaneBytes) {                            \
+        ABFT_SWEEP_CASE_NW(LPR_, NCH_, VEC_, PF_, 8)                                           \
     }
 #define ABFT_SWEEP_CASE(LPR_, NCH_, VEC_) ABFT_SWEEP_CASE_PF(LPR_, NCH_, VEC_, 1)
     constexpr int VF = 16 / (int)sizeof(T);
@@ -446,6 +454,7 @@ hipError_t launch_sweep_t(const SweepShape& s, const SweepArgs& a, hipStream_t s
     ABFT_SWEEP_CASE(64, 16, 1)
 #undef ABFT_SWEEP_CASE
 #undef ABFT_SWEEP_CASE_PF
+#undef ABFT_SWEEP_CASE_NW
     return hipErrorInvalidValue;
 }
 
