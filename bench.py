@@ -9,6 +9,8 @@ HBM when the timed region starts.
 Also measured on the same grid (not part of the timed headline): the plain sweep (the
 overhead baseline, same kernel template with checksums off), online ABFT (every sweep
 checked, locate/correct launch after each sweep), and the protected sweep kernel alone.
+And the batched workload: 64 uneven fp32 grids (64..256 x 64..256 x 4..32) swept by one
+launch per sweep, online and plain, captured in hipGraphs, beside one context per grid.
 
 Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
 """
@@ -53,6 +55,63 @@ def load_traffic(kernel_key: str):
     return e.get("bytes_per_launch")
 
 
+def bench_batch(stream, timed, tune=True, chunk=50):
+    """The 64-grid batch (200 sweeps per run in the tests): ms per sweep of the batched launch,
+    online (protected sweep + per-grid locate launch) and plain, each captured in a hipGraph of
+    `chunk` sweeps, and of the same grids stepped one context per grid (online, eager)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1909_00709_amd import abft
+
+    shapes = W.c4_shapes()
+    inputs = W.c4_inputs(shapes)
+    npts = sum(nz * ny * nx for nz, ny, nx in shapes)
+    with torch.cuda.stream(stream):
+        dev = [(torch.from_numpy(u).cuda(), torch.from_numpy(c).cuda()) for u, c in inputs]
+    stream.synchronize()
+    res = {"workload": f"{len(shapes)} fp32 thermal grids, 64..256 x 64..256 x 4..32 "
+                       f"({npts / 1e6:.1f} M points), online threshold {W.C4_EPS}",
+           "grids": len(shapes), "points": npts}
+    for mode in ("online", "none"):
+        with torch.cuda.stream(stream):
+            grids = [(u.clone(), c) for u, c in dev]
+        B = abft.Batch(grids, W.THERMAL_TAPS, mode=mode, threshold=W.C4_EPS, stream=stream)
+        if tune:
+            B.autotune()
+        B.step_graph(chunk)
+        ms = timed(lambda: B.step_graph(chunk), 4) / chunk
+        rep, _ = B.check()
+        assert rep["rows_flagged"] == 0, rep
+        res[f"{mode}_ms_per_sweep"] = round(ms, 5)
+        res[f"{mode}_gpts"] = round(npts / (ms * 1e-3) / 1e9, 3)
+        res[f"{mode}_shape"] = B.launch_shape()
+        B.close()
+    res["algorithmic_GBs_online"] = round(12.0 * npts / (res["online_ms_per_sweep"] * 1e-3) / 1e9, 1)
+    res["overhead_online_pct"] = round((res["online_ms_per_sweep"] / res["none_ms_per_sweep"] - 1)
+                                       * 100, 2)
+    # the same grids, one context each, stepped one after another (eager launches)
+    ctxs = []
+    for u, c in dev:
+        with torch.cuda.stream(stream):
+            uu = u.clone()
+        ctxs.append(abft.Stencil(uu, W.THERMAL_TAPS, C=c, mode="online", threshold=W.C4_EPS,
+                                 stream=stream))
+    def sweep_all():
+        for S in ctxs:
+            S.step(1)
+    sweep_all()
+    ms = timed(sweep_all, 20)
+    for S in ctxs:
+        rep, _ = S.check()
+        assert rep["rows_flagged"] == 0, rep
+        S.close()
+    res["per_grid_contexts_ms_per_sweep"] = round(ms, 5)
+    res["per_grid_contexts_gpts"] = round(npts / (ms * 1e-3) / 1e9, 3)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,7 +122,7 @@ def main():
     ap.add_argument("--nz", type=int, default=128)
     ap.add_argument("--period", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["plain", "prot", "offline", "online"], default=None,
+    ap.add_argument("--only", choices=["plain", "prot", "offline", "online", "batch"], default=None,
                     help="run one measurement only (for profiler runs)")
     ap.add_argument("--no-tune", action="store_true",
                     help="do not autotune (launch shapes from --tuning-cache or the defaults)")
@@ -189,9 +248,15 @@ def main():
         out["wall_s"] = wall
         S.close()
 
+    # ---- batched grids: 64 uneven grids, one launch per sweep, hipGraph ----------------------
+    batch = None
+    if args.only in (None, "batch"):
+        batch = bench_batch(stream, timed, tune=not args.no_tune)
+
     if args.only is not None:
         print(json.dumps({"only": args.only, "plain_ms": plain_ms, "prot_ms": prot_ms,
-                          "online_ms_per_sweep": online_ms, "offline_ms_per_window": offline_ms}))
+                          "online_ms_per_sweep": online_ms, "offline_ms_per_window": offline_ms,
+                          "batch": batch}))
         return
 
     gpts = lambda ms, sweeps=1: npts * sweeps / (ms * 1e-3) / 1e9
@@ -264,6 +329,7 @@ def main():
         "paper_context": "paper: <8% ABFT overhead, Xeon E5-2640 v4, 8 OpenMP threads, "
                          "512x512x8 fp32 HotSpot3D tiles (CPU, other hardware)",
         "cpu_baseline": cpu,
+        "batch": batch,
         "noise": {"online_f64": out.get("prot_noise_f64"),
                   "online_f32comp": out.get("prot_noise_f32comp"),
                   "offline": out.get("offline_noise")},
