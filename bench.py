@@ -112,6 +112,89 @@ def bench_batch(stream, timed, tune=True, chunk=50):
     return res
 
 
+def bench_configs(stream, timed, tune=True):
+    """The smaller workloads (64x64 fp64 Jacobi, 512x512x8 fp64 and 512x512x64 fp32 thermal) and
+    the large fp32 grid's oracle rates: GPU GPts/s for plain, online (hipGraph of 10-sweep
+    chunks) and offline (k = 10) runs, and the oracle's plain and online GPts/s on a bounded
+    number of sweeps with all host threads (and with one thread for the large grid)."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    import workloads as W
+    from paper_1909_00709_amd import abft
+
+    out = {}
+    for w, modes, csums in ((W.C1, ("none", "online"), ("f64",)),
+                            (W.C2, ("none", "online", "offline"), ("f64",)),
+                            (W.C3, ("none", "online", "offline"), ("f64", "f32comp"))):
+        u0n, Cn = w.inputs()
+        r = {"shape": [w.nz, w.ny, w.nx], "dtype": "f64" if w.dtype == W.F64 else "f32",
+             "points": w.npoints}
+        with torch.cuda.stream(stream):
+            u0 = torch.from_numpy(u0n).cuda()
+            C = torch.from_numpy(Cn).cuda() if Cn is not None else None
+        stream.synchronize()
+        chunk = 10
+        for mode in modes + ("prot",):
+            for cs in (csums if mode != "none" else ("f64",)):
+                with torch.cuda.stream(stream):
+                    u = u0.clone()
+                eps = w.eps if not (mode == "offline" and w.dtype == W.F32) else W.C5.eps
+                # "prot": the protected sweep kernel alone (online, no locate launches)
+                S = abft.Stencil(u, w.taps, C=C, mode="online" if mode == "prot" else mode,
+                                 threshold=eps, csum=cs, period=chunk, stream=stream,
+                                 auto_correct=mode != "prot")
+                if tune:
+                    S.autotune()
+                if mode == "offline":
+                    S.step(chunk)
+                    ms = timed(lambda: S.step(chunk), 20) / chunk
+                else:
+                    S.step_graph(chunk)
+                    ms = timed(lambda: S.step_graph(chunk), 20) / chunk
+                rep, _ = S.check()
+                assert rep["rows_flagged"] == 0 and rep["windows_flagged"] == 0, rep
+                key = mode if mode == "none" else f"{mode}_{cs}"
+                r[f"gpu_{key}_gpts"] = round(w.npoints / (ms * 1e-3) / 1e9, 3)
+                r[f"gpu_{key}_us_per_sweep"] = round(ms * 1e3, 3)
+                S.close()
+        # the oracle on the same grid, all host threads
+        p = O.Problem(u0n.shape, O.F64 if w.dtype == W.F64 else O.F32, w.taps)
+        nsw = max(2, min(w.nsweeps, int(2e9 // w.npoints)))
+        for mode, m in (("none", O.MODE_NONE), ("online", O.MODE_ONLINE)):
+            t0 = time.perf_counter()
+            p.run(u0n, nsw, Cn, mode=m, eps=w.eps)
+            dt = time.perf_counter() - t0
+            r[f"oracle_{mode}_gpts"] = round(w.npoints * nsw / dt / 1e9, 4)
+        r["oracle_sweeps"] = nsw
+        r["oracle_threads"] = O.get_threads()
+        out[w.name] = r
+        del u0, C
+    # the large fp32 grid: oracle plain / online with all threads, plain with one thread
+    w = W.C5
+    u0n, Cn = w.inputs()
+    p = O.Problem(u0n.shape, O.F32, w.taps)
+    r = {"points": w.npoints, "oracle_threads": O.get_threads()}
+    for mode, m, nsw in (("none", O.MODE_NONE, 30), ("online", O.MODE_ONLINE, 30)):
+        t0 = time.perf_counter()
+        p.run(u0n, nsw, Cn, mode=m, eps=1e-7)
+        dt = time.perf_counter() - t0
+        r[f"oracle_{mode}_gpts"] = round(w.npoints * nsw / dt / 1e9, 4)
+    r["oracle_online_overhead_pct"] = round(
+        (r["oracle_none_gpts"] / r["oracle_online_gpts"] - 1) * 100, 2)
+    nthreads = O.get_threads()
+    O.set_threads(1)
+    t0 = time.perf_counter()
+    p.run(u0n, 3, Cn, mode=O.MODE_NONE)
+    r["oracle_none_1thread_gpts"] = round(w.npoints * 3 / (time.perf_counter() - t0) / 1e9, 4)
+    O.set_threads(nthreads)
+    r["oracle_sweeps"] = "30 (all threads), 3 (one thread); each run includes the first touch " \
+                         "of its output buffer"
+    out[w.name] = r
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,7 +205,8 @@ def main():
     ap.add_argument("--nz", type=int, default=128)
     ap.add_argument("--period", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["plain", "prot", "offline", "online", "batch"], default=None,
+    ap.add_argument("--only", choices=["plain", "prot", "offline", "online", "batch", "configs"],
+                    default=None,
                     help="run one measurement only (for profiler runs)")
     ap.add_argument("--no-tune", action="store_true",
                     help="do not autotune (launch shapes from --tuning-cache or the defaults)")
@@ -252,6 +336,11 @@ def main():
     batch = None
     if args.only in (None, "batch"):
         batch = bench_batch(stream, timed, tune=not args.no_tune)
+
+    if args.only == "configs":
+        print(json.dumps({"only": "configs", "configs": bench_configs(stream, timed,
+                                                                      tune=not args.no_tune)}))
+        return
 
     if args.only is not None:
         print(json.dumps({"only": args.only, "plain_ms": plain_ms, "prot_ms": prot_ms,

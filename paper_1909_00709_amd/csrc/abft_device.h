@@ -258,18 +258,29 @@ __device__ __forceinline__ void emit_event(Counters* cnt, abft_event* ev, int ca
     }
 }
 
-__device__ __forceinline__ void record_noise(Counters* cnt, double noise)
+// The stored maximum, read early by a caller that wants the read's latency out of its tail.
+__device__ __forceinline__ unsigned long long noise_known(const Counters* cnt)
 {
-    // Every wavefront of a sweep reaches this at about the same time, and atomics on one
-    // address serialise at the coherence point (measured: ~12 us per 2048-wavefront sweep).
-    // The maximum only grows, so a wavefront whose value does not exceed the one already
-    // stored (even a stale read of it) can skip the atomic without changing the result.
+    return __hip_atomic_load(&cnt->noise_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Every wavefront of a sweep reaches this at about the same time, and atomics on one address
+// serialise at the coherence point (measured: ~12 us per 2048-wavefront sweep).  The maximum
+// only grows, so a wavefront whose value does not exceed a value already stored (known, read
+// at any earlier time) can skip the atomic without changing the result.
+__device__ __forceinline__ void record_noise(Counters* cnt, double noise,
+                                             unsigned long long known)
+{
     const double m = wave_max(noise);
     if ((threadIdx.x & 63) == 0 && m > 0.0) {
         const unsigned long long b = (unsigned long long)__double_as_longlong(m);
-        if (b > __hip_atomic_load(&cnt->noise_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            atomicMax(&cnt->noise_bits, b);
+        if (b > known) atomicMax(&cnt->noise_bits, b);
     }
+}
+
+__device__ __forceinline__ void record_noise(Counters* cnt, double noise)
+{
+    record_noise(cnt, noise, noise_known(cnt));
 }
 
 }  // namespace abft

@@ -145,6 +145,30 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
         }
     };
 
+    // The checksums the epilogue's prediction reads for this lane's first plane (its own row's,
+    // the four neighbouring rows' and the constant term's) are loaded now, so that their
+    // latency hides behind the march instead of adding to the end of every tile.
+    auto brow = [&](int z2, int y2) -> double {
+        const int mz = map_coord(z2, nz, bc), my = map_coord(y2, ny, bc);
+        if (mz < 0 || my < 0) return (double)nx * (double)g;
+        return a.Bt[(size_t)mz * ny + my];
+    };
+    double pb0 = 0.0, pcb = 0.0, pym = 0.0, pyp = 0.0, pzm = 0.0, pzp = 0.0;
+    unsigned long long nknown = 0ull;
+    if constexpr (MODE == MODE_PROT) {
+        nknown = noise_known(a.cnt);
+        if (row_ok && sl < z1 - z0) {
+            const int z = z0 + sl;
+            const size_t l = (size_t)z * ny + y;
+            pb0 = a.Bt[l];
+            pcb = a.cB[l];
+            if (mask & 8u) pym = brow(z, y - 1);
+            if (mask & 16u) pyp = brow(z, y + 1);
+            if (mask & 32u) pzm = brow(z - 1, y);
+            if (mask & 64u) pzp = brow(z + 1, y);
+        }
+    }
+
     load_u(dn, map_coord(z0 - 1, nz, bc));
     load_u(cu, z0);
     load_u(up, map_coord(z0 + 1, nz, bc));
@@ -356,22 +380,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                 if constexpr (MODE == MODE_PROT) {
                     // Theorem 1 (Eq.(5)) on the checksum plane: the x shifts become the
                     // boundary term e of the input row, the y and z shifts read the
-                    // neighbouring rows' checksums.
-                    auto brow = [&](int z2, int y2) -> double {
-                        const int mz = map_coord(z2, nz, bc), my = map_coord(y2, ny, bc);
-                        if (mz < 0 || my < 0) return (double)nx * (double)g;
-                        return a.Bt[(size_t)mz * ny + my];
-                    };
-                    const double b0 = a.Bt[l];
-                    double bp = a.cB[l];
+                    // neighbouring rows' checksums (loaded before the march for the first
+                    // plane of the lane).
+                    const bool first = pz == sl;
+                    const double b0 = first ? pb0 : a.Bt[l];
+                    double bp = first ? pcb : a.cB[l];
                     if (mask & 1u) bp += a.st.w[W_C] * b0;
                     if (mask & 2u) bp += a.st.w[W_XM] * b0;
                     if (mask & 4u) bp += a.st.w[W_XP] * b0;
                     bp += tabE[r * a.tz + pz];
-                    if (mask & 8u) bp += a.st.w[W_YM] * brow(z, y - 1);
-                    if (mask & 16u) bp += a.st.w[W_YP] * brow(z, y + 1);
-                    if (mask & 32u) bp += a.st.w[W_ZM] * brow(z - 1, y);
-                    if (mask & 64u) bp += a.st.w[W_ZP] * brow(z + 1, y);
+                    if (mask & 8u) bp += a.st.w[W_YM] * (first ? pym : brow(z, y - 1));
+                    if (mask & 16u) bp += a.st.w[W_YP] * (first ? pyp : brow(z, y + 1));
+                    if (mask & 32u) bp += a.st.w[W_ZM] * (first ? pzm : brow(z - 1, y));
+                    if (mask & 64u) bp += a.st.w[W_ZP] * (first ? pzp : brow(z + 1, y));
                     // Section 3.4, written so that NaN and Inf mismatches are flagged
                     const double d = fabs(S - bp);
                     if (!(d <= a.eps * fabs(bp))) {
@@ -396,7 +417,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             }
         }
     }
-    if constexpr (MODE == MODE_PROT) record_noise(a.cnt, noise);
+    if constexpr (MODE == MODE_PROT) record_noise(a.cnt, noise, nknown);
 }
 
 template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF, int NW>
