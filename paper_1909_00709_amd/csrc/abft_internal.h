@@ -13,9 +13,10 @@ constexpr int kMaxFlags = 1024;   // flagged rows remembered per sweep for locat
 constexpr int kSweepBlock = 256;  // threads per block of the batched sweep (4 wavefronts)
 constexpr int kWideBlockLaneBytes = 64;  // most row bytes per lane for 8-wavefront sweep blocks
 constexpr int kFixBlock = 512;    // threads of the single locate/correct block
-constexpr int kCheckBlock = 256;  // threads per block of the offline window check
+constexpr int kCheckBlock = 1024; // threads per block of the offline window check
 constexpr int kMaxPeriod = 32;    // longest offline window handled by one check launch
-constexpr int kCheckCells = 16;   // checksum-plane cells per thread in the window check
+constexpr int kCheckCells = 4;    // checksum-plane cells per thread in the window check
+constexpr unsigned kBarrierSpinLimit = 1u << 26;  // polls (~50 ns each) before a grid barrier gives up
 
 // Weight slots of the radius-1 star stencil: centre, x-1, x+1, y-1, y+1, z-1, z+1.
 enum { W_C = 0, W_XM, W_XP, W_YM, W_YP, W_ZM, W_ZP, W_COUNT };
@@ -45,6 +46,7 @@ struct Counters {
     unsigned long long events_total;
     unsigned long long noise_bits;  // bit pattern of the largest non-negative noise (double)
     unsigned long long overflow;    // sweeps whose flagged rows exceeded kMaxFlags
+    unsigned long long barrier_timeouts;  // recovery grid barriers that gave up waiting
 };
 
 // Sweep kernel variants.
@@ -124,6 +126,18 @@ struct CheckArgs {
     int64_t t_last;         // last sweep of the window
 };
 
+// The rollback recompute of an offline window in one launch: the window's k sweeps from the
+// checkpoint (attempt 1), separated by grid barriers.
+struct RecoverArgs {
+    SweepArgs a;                      // fields shared by the window's sweeps
+    const void* seq[kMaxPeriod + 1];  // sweep j reads seq[j] and writes seq[j + 1]
+    double* E;                        // [k][nz][ny] boundary terms of the sweeps, or null
+    int32_t k;                        // sweeps in the window
+    int64_t t_first;                  // first sweep of the window
+    const uint32_t* guard;            // run only when *guard != 0, or null
+    uint32_t* bar;                    // [0] barrier arrivals, [1] departures; zero between launches
+};
+
 // One grid of a batch, as the batched kernels see it.
 struct GridDesc {
     void* u[2];             // the grid's two buffers; u[t & 1] holds u^t
@@ -191,6 +205,15 @@ hipError_t launch_col_sums(int dtype, const void* u, double cs, int nx, int ny, 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_rollback_note(const uint32_t* guard, Counters* cnt, abft_event* ev, int cap,
                                 int64_t t_first, int k, hipStream_t st);
+// Offline rollback recompute (abft_recover.h), one launch of at most one wave of blocks with
+// grid barriers; the shape's lanes, chunks, vector width and wavefronts (prefetch depth 1).
+bool recover_shape_supported(int dtype, const SweepShape& s);
+hipError_t launch_recover(int dtype, int csum, const SweepShape& s, const RecoverArgs& r,
+                          int num_cus, hipStream_t st);
+hipError_t launch_recover_f32(int csum, const SweepShape& s, const RecoverArgs& r, size_t lds,
+                              int num_cus, hipStream_t st);
+hipError_t launch_recover_f64(int csum, const SweepShape& s, const RecoverArgs& r, size_t lds,
+                              int num_cus, hipStream_t st);
 
 // Per-variant sweep launchers (one translation unit each).
 #define ABFT_DECL_SWEEP(NAME)                                                                 \

@@ -477,6 +477,25 @@ hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, cons
     return launch_sweep_f64_prot(csum, s, a, st, lds);
 }
 
+// The recompute kernel keeps a few bytes of static LDS (its barrier flag) next to the sweep's
+// dynamic LDS; shapes are those of the sweep at prefetch depth 1.
+bool recover_shape_supported(int dtype, const SweepShape& s)
+{
+    SweepShape t = s;
+    t.pf = 1;
+    return sweep_shape_supported(dtype, t);
+}
+
+hipError_t launch_recover(int dtype, int csum, const SweepShape& s, const RecoverArgs& r,
+                          int num_cus, hipStream_t st)
+{
+    if (!recover_shape_supported(dtype, s) || r.k < 1 || r.k > kMaxPeriod || num_cus < 1)
+        return hipErrorInvalidValue;
+    const size_t lds = sweep_lds_bytes(dtype, r.a.nx, s);
+    if (dtype == ABFT_F32) return launch_recover_f32(csum, s, r, lds, num_cus, st);
+    return launch_recover_f64(csum, s, r, lds, num_cus, st);
+}
+
 size_t fixup_lds_bytes(int nx) { return (size_t)nx * (3 * sizeof(double) + 2 * sizeof(int)); }
 
 hipError_t launch_fixup_batch(int dtype, const BatchArgs& b, int maxnx, hipStream_t st)

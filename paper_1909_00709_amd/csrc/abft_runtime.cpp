@@ -306,7 +306,7 @@ void check_shape(abft_ctx* c, int k)
         *rz = per ? tzi + 2 * k : std::min(c->nz, tzi + 2 * k);
         return (int64_t)*ry * *rz;
     };
-    s.tzi = std::min(c->nz, 8);
+    s.tzi = std::min(c->nz, 16);
     s.tyi = std::min(c->ny, 32);
     int ry, rz;
     while (region(s.tyi, s.tzi, &ry, &rz) > cap && (s.tyi > 1 || s.tzi > 1)) {
@@ -316,7 +316,10 @@ void check_shape(abft_ctx* c, int k)
     auto tiles = [&](int tyi, int tzi) {
         return (int64_t)((c->ny + tyi - 1) / tyi) * ((c->nz + tzi - 1) / tzi);
     };
-    while (tiles(s.tyi, s.tzi) < 256 && s.tyi > 8) s.tyi /= 2;
+    while (tiles(s.tyi, s.tzi) < 256 && (s.tyi > 8 || s.tzi > 4)) {
+        if (s.tyi > 8) s.tyi /= 2;
+        else s.tzi /= 2;
+    }
     region(s.tyi, s.tzi, &s.ry, &s.rz);
     s.nyt = (c->ny + s.tyi - 1) / s.tyi;
     s.nzt = (c->nz + s.tzi - 1) / s.tzi;
@@ -477,9 +480,27 @@ void offline_rotate(abft_ctx* c, int k)
     c->cur = c->ckpt;
 }
 
-// Recompute of the window from the checkpoint (attempt 1) and its re-check.
+// Recompute of the window from the checkpoint (attempt 1) and its re-check.  One launch runs
+// the k sweeps with grid barriers between them; where the shape's LDS leaves no room for that
+// kernel's own few bytes, k guarded sweep launches do the same work.
 abft_status offline_recompute(abft_ctx* c, int k, const uint32_t* guard)
 {
+    if (c->num_cus > 0 && recover_shape_supported(c->dtype, c->shape) &&
+        sweep_lds_bytes(c->dtype, c->nx, c->shape) + 256 <= kSweepLdsLimit) {
+        RecoverArgs r{};
+        r.a = base_args(c);
+        r.a.attempt = 1;
+        r.a.Bn = c->B[c->bck ^ 1];
+        for (int j = 0; j <= k; ++j) r.seq[j] = c->u[buf_of(c, j)];
+        r.E = c->E;
+        r.k = k;
+        r.t_first = c->win_t0;
+        r.guard = guard;
+        r.bar = c->ticket + 2;
+        hipError_t e = launch_recover(c->dtype, c->csum, c->shape, r, c->num_cus, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "rollback recompute launch");
+        return offline_check(c, k, 1, guard);
+    }
     hipError_t e = launch_rollback_note(guard, c->cnt, c->ev, c->ev_cap, c->win_t0, k, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "rollback launch");
     for (int j = 0; j < k; ++j) {
@@ -814,6 +835,13 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
         delete c;
         return st;
     };
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+            return bail(fail(c, ABFT_E_HIP, "device query failed"));
+        c->num_cus = prop.multiProcessorCount;
+    }
 
     s = map_taps(c, p);
     if (s) return bail(s);
@@ -945,6 +973,16 @@ abft_status abft_stencil_check(abft_ctx* c, abft_report* out)
     Counters h{};
     abft_status s = read_counters(c, &h);
     if (s) return s;
+    if (h.barrier_timeouts > 0) {
+        // a recompute gave up waiting for its grid: its result and the barrier are not to be
+        // trusted; the barrier words are cleared so that the next recompute can run
+        uint32_t* bt = reinterpret_cast<uint32_t*>(&c->cnt->barrier_timeouts);
+        hipError_t e = launch_fill_u32(c->ticket + 2, 0u, 2, c->stream);
+        if (e == hipSuccess) e = launch_fill_u32(bt, 0u, 2, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "barrier reset");
+        return fail(c, ABFT_E_HIP, "offline recompute: a grid barrier timed out");
+    }
     int64_t pending = 0;
     if (c->batch && c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
         for (auto& G : c->grids) {
