@@ -195,6 +195,44 @@ def bench_configs(stream, timed, tune=True):
     return out
 
 
+def bench_periods(stream, timed, u0, C, tune=True, prerun=300, nsweeps=320):
+    """Offline detection period k on the large grid: throughput of windows of k sweeps and the
+    largest fault-free noise of the window comparison, from the near-steady field reached after
+    `prerun` plain sweeps, with threshold k * 1e-7 (at least 1e-7)."""
+    import torch
+
+    import workloads as W
+    from paper_1909_00709_amd import abft
+
+    with torch.cuda.stream(stream):
+        P = abft.Stencil(u0.clone(), W.THERMAL_TAPS, C=C, mode="none", stream=stream)
+        if tune:
+            P.autotune()
+        P.step(prerun)
+        start = P.current()[0].clone()
+        plain_ms = timed(lambda: P.step(32), 5) / 32
+        P.close()
+    npts = start.numel()
+    out = {"prerun_sweeps": prerun, "sweeps": nsweeps,
+           "plain_gpts": round(npts / (plain_ms * 1e-3) / 1e9, 3), "periods": {}}
+    for k in (1, 2, 4, 8, 10, 16, 32):
+        eps = max(1e-7, k * 1e-7)
+        with torch.cuda.stream(stream):
+            S = abft.Stencil(start.clone(), W.THERMAL_TAPS, C=C, mode="offline", period=k,
+                             threshold=eps, stream=stream)
+            if tune:
+                S.autotune()
+            S.step(k)
+            ms = timed(lambda: S.step(nsweeps), 1) / nsweeps
+            rep, _ = S.check()
+            S.close()
+        out["periods"][k] = {"threshold": eps, "gpts": round(npts / (ms * 1e-3) / 1e9, 3),
+                             "overhead_pct": round((ms / plain_ms - 1) * 100, 2),
+                             "max_noise": rep["max_noise"],
+                             "windows_flagged": rep["windows_flagged"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,7 +243,8 @@ def main():
     ap.add_argument("--nz", type=int, default=128)
     ap.add_argument("--period", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["plain", "prot", "offline", "online", "batch", "configs"],
+    ap.add_argument("--only", choices=["plain", "prot", "offline", "online", "batch", "configs",
+                                       "periods"],
                     default=None,
                     help="run one measurement only (for profiler runs)")
     ap.add_argument("--no-tune", action="store_true",
@@ -336,6 +375,11 @@ def main():
     batch = None
     if args.only in (None, "batch"):
         batch = bench_batch(stream, timed, tune=not args.no_tune)
+
+    if args.only == "periods":
+        print(json.dumps({"only": "periods", "periods": bench_periods(stream, timed, u0, C,
+                                                                      tune=not args.no_tune)}))
+        return
 
     if args.only == "configs":
         print(json.dumps({"only": "configs", "configs": bench_configs(stream, timed,

@@ -16,6 +16,7 @@ constexpr int kFixBlock = 512;    // threads of the single locate/correct block
 constexpr int kCheckBlock = 1024; // threads per block of the offline window check
 constexpr int kMaxPeriod = 32;    // longest offline window handled by one check launch
 constexpr int kCheckCells = 4;    // checksum-plane cells per thread in the window check
+constexpr int kCheckChunk = 16;   // interpolation steps per window-check launch at most
 constexpr unsigned kBarrierSpinLimit = 1u << 26;  // polls (~50 ns each) before a grid barrier gives up
 
 // Weight slots of the radius-1 star stencil: centre, x-1, x+1, y-1, y+1, z-1, z+1.
@@ -104,13 +105,15 @@ struct FixArgs {
 };
 
 struct CheckArgs {
-    const double* Bck;      // checksums at the checkpoint
+    const double* Bin;      // checksums the launch starts from (the checkpoint's, or a chunk's)
+    double* Bout;           // interpolated checksums after this launch's steps, or null in the
+                            // window's last launch, which compares instead
     const double* Bdir;     // direct checksums at the window end
     const double* cB;
     const double* E;        // [k][nz][ny] boundary terms, or null
     Stencil st;
     int32_t nx, ny, nz;
-    int32_t k;              // window length
+    int32_t s0, ns;         // the window's steps s0 .. s0 + ns - 1 are done by this launch
     double eps;
     int32_t tyi, tzi, nyt, nzt;   // interior tile sizes and tile counts
     int32_t ry_max, rz_max;       // region extents the LDS was sized for

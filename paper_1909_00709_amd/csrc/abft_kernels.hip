@@ -249,15 +249,16 @@ __global__ void __launch_bounds__(kFixBlock) fixup_batch_kernel(const BatchArgs 
 // Offline window check (Section 4.1): the checksum interpolation applied k times from the
 // checkpoint's checksums, then compared with the direct checksums at the window end.  Each
 // block owns a tile of the (z, y) checksum plane and iterates the plane stencil in LDS on the
-// tile plus a halo of k rows / layers (the k-step dependency cone), so one launch does all k
-// steps.
+// tile plus a halo of ns rows / layers (the ns-step dependency cone), so one launch does ns
+// steps: all k of a window up to kCheckChunk, else the window's steps in chunks, each but the
+// last writing its tiles' interiors to an intermediate plane.
 // ------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     if (a.guard != nullptr && *a.guard == 0u) return;
 
-    const int nx = a.nx, ny = a.ny, nz = a.nz, bc = a.st.bc, k = a.k;
+    const int nx = a.nx, ny = a.ny, nz = a.nz, bc = a.st.bc, k = a.ns;
     const bool per = bc == ABFT_BC_PERIODIC;
     const double gd = a.st.g;
     const uint32_t mask = a.st.mask;
@@ -299,7 +300,7 @@ __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
             const int gy = per ? wrap(yy, ny) : yy, gz = per ? wrap(zz, nz) : zz;
             gl[q] = gz * ny + gy;
             cbv[q] = a.cB[gl[q]];
-            cur[i] = a.Bck[gl[q]];
+            cur[i] = a.Bin[gl[q]];
             auto nbi = [&](int dz, int dy) -> int {
                 int y2 = yy + dy, z2 = zz + dz;
                 if (!per && (y2 < 0 || y2 >= ny || z2 < 0 || z2 >= nz)) {
@@ -320,7 +321,7 @@ __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
 
     const double ghost_row = (double)nx * gd;
     for (int s = 0; s < k; ++s) {
-        const double* Es = a.E != nullptr ? a.E + (size_t)s * nz * ny : nullptr;
+        const double* Es = a.E != nullptr ? a.E + (size_t)(a.s0 + s) * nz * ny : nullptr;
 #pragma unroll
         for (int q = 0; q < kCheckCells; ++q) {
             const int i = tid + q * kCheckBlock;
@@ -339,6 +340,18 @@ __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
         double* tmp = cur;
         cur = nxt;
         nxt = tmp;
+    }
+
+    if (a.Bout != nullptr) {  // an intermediate chunk: hand the tile's interior on
+#pragma unroll
+        for (int q = 0; q < kCheckCells; ++q) {
+            const int i = tid + q * kCheckBlock;
+            if (i >= NC) continue;
+            const int yy = ry0 + i % RY, zz = rz0 + i / RY;
+            if (yy < iy0 || yy >= iy1 || zz < iz0 || zz >= iz1) continue;
+            a.Bout[(size_t)zz * ny + yy] = cur[i];
+        }
+        return;
     }
 
     double noise = 0.0;

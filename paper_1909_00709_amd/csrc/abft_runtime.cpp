@@ -63,6 +63,7 @@ struct abft_ctx {
     uint32_t* ticket = nullptr;
     int64_t* tbase = nullptr;
     double* E = nullptr;         // [period][nz][ny] when the boundary terms do not cancel
+    double* Btmp[2] = {nullptr, nullptr};  // interpolation between check chunks (long windows)
     abft_fault* faults = nullptr;
     int32_t* fault_first = nullptr;
     int64_t fault_tmax = 0;
@@ -430,9 +431,9 @@ abft_status offline_sweep(abft_ctx* c, int j, int k, int attempt, const uint32_t
 
 abft_status offline_check(abft_ctx* c, int k, int attempt, const uint32_t* guard)
 {
-    check_shape(c, k);
+    const int chunk = std::min(k, kCheckChunk);
+    check_shape(c, chunk);
     CheckArgs a{};
-    a.Bck = c->B[c->bck];
     a.Bdir = c->B[c->bck ^ 1];
     a.cB = c->cB;
     a.E = c->E;
@@ -440,7 +441,6 @@ abft_status offline_check(abft_ctx* c, int k, int attempt, const uint32_t* guard
     a.nx = c->nx;
     a.ny = c->ny;
     a.nz = c->nz;
-    a.k = k;
     a.eps = c->eps;
     a.tyi = c->ck.tyi;
     a.tzi = c->ck.tzi;
@@ -459,8 +459,15 @@ abft_status offline_check(abft_ctx* c, int k, int attempt, const uint32_t* guard
     a.auto_correct = c->auto_correct;
     a.t_first = c->win_t0;
     a.t_last = c->win_t0 + k - 1;
-    hipError_t e = launch_check(a, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "offline check launch");
+    const int nchunks = (k + chunk - 1) / chunk;
+    for (int ch = 0; ch < nchunks; ++ch) {
+        a.s0 = ch * chunk;
+        a.ns = std::min(chunk, k - a.s0);
+        a.Bin = ch == 0 ? c->B[c->bck] : c->Btmp[(ch - 1) & 1];
+        a.Bout = ch == nchunks - 1 ? nullptr : c->Btmp[ch & 1];
+        hipError_t e = launch_check(a, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "offline check launch");
+    }
     return ABFT_OK;
 }
 
@@ -855,7 +862,7 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
     if (fixup_lds_bytes(c->nx) > kLdsLimit || c->nx > 4 * kFixBlock)
         return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
     if (c->mode == ABFT_MODE_OFFLINE) {
-        check_shape(c, c->period);
+        check_shape(c, std::min(c->period, kCheckChunk));
         if ((int64_t)c->ck.ry * c->ck.rz > (int64_t)kCheckCells * kCheckBlock)
             return bail(fail(c, ABFT_E_UNSUPPORTED, "offline period too long for this grid"));
     }
@@ -882,6 +889,9 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
             c->own_u2 = true;
         }
         if (need_boundary_terms(c) && (s = dalloc(c, &c->E, (size_t)c->period * nrows * 8)))
+            return bail(s);
+        if (c->period > kCheckChunk &&
+            ((s = dalloc(c, &c->Btmp[0], nrows * 8)) || (s = dalloc(c, &c->Btmp[1], nrows * 8))))
             return bail(s);
     }
 
