@@ -93,7 +93,7 @@ typedef struct {
 
 typedef struct {
     int32_t mode;               /* abft_mode */
-    int32_t period;             /* offline window length (sweeps per check), >= 1 */
+    int32_t period;             /* offline window length (sweeps per check), 1..32 */
     double threshold;           /* relative detection threshold eps of Section 3.4, > 0 */
     int32_t csum;               /* abft_csum */
     int32_t auto_correct;       /* 1: locate and correct (online) or roll back and recompute
@@ -179,7 +179,10 @@ abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft
 /* Enqueues nsweeps sweeps on the context's stream and returns without waiting for them
  * (offline mode without auto-correct is the exception: it waits at each window end and stops
  * after the first flagged window).  nsweeps >= 0.  ABFT_E_STATE while a detection awaits
- * abft_stencil_correct. */
+ * abft_stencil_correct.  Offline with auto-correct, every window end enqueues the check and a
+ * rollback recompute that runs only when the check flagged a mismatch: one launch of at most
+ * one block per free block slot of the device, whose blocks wait for each other between the
+ * window's sweeps, so compute units held by other streams delay it. */
 abft_status abft_stencil_step(abft_ctx* ctx, int64_t nsweeps);
 
 /* Enqueues nsweeps sweeps as one captured HIP graph (built on first use for a given nsweeps,
@@ -188,7 +191,9 @@ abft_status abft_stencil_step(abft_ctx* ctx, int64_t nsweeps);
 abft_status abft_stencil_step_graph(abft_ctx* ctx, int64_t nsweeps);
 
 /* Waits for the stream and reports.  In offline mode a partial window is checked first (the
- * "after completion" detection), which also closes it.  `out` may be NULL. */
+ * "after completion" detection), which also closes it.  `out` may be NULL.  Returns
+ * ABFT_E_HIP if a rollback recompute gave up waiting for its blocks (about three seconds at
+ * one barrier): the recomputed window is then not to be trusted; the barrier is reset. */
 abft_status abft_stencil_check(abft_ctx* ctx, abft_report* out);
 
 /* Acts on pending detections: online, locates and corrects the flagged rows of the last
