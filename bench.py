@@ -195,10 +195,12 @@ def bench_configs(stream, timed, tune=True):
     return out
 
 
-def bench_periods(stream, timed, u0, C, tune=True, prerun=300, nsweeps=320):
-    """Offline detection period k on the large grid: throughput of windows of k sweeps and the
-    largest fault-free noise of the window comparison, from the near-steady field reached after
-    `prerun` plain sweeps, with threshold k * 1e-7 (at least 1e-7)."""
+def bench_periods(stream, timed, u0, C, tune=True, prerun=300, nsweeps=640):
+    """Offline detection period k on the large grid, from the near-steady field reached after
+    `prerun` plain sweeps, with threshold k * 1e-7 (at least 1e-7): throughput of a fault-free
+    run of `nsweeps` sweeps and its largest window-comparison noise, and the time of the same
+    run with one flip (bit 28, in the middle sweep), whose window is rolled back and
+    recomputed."""
     import torch
 
     import workloads as W
@@ -210,26 +212,41 @@ def bench_periods(stream, timed, u0, C, tune=True, prerun=300, nsweeps=320):
             P.autotune()
         P.step(prerun)
         start = P.current()[0].clone()
-        plain_ms = timed(lambda: P.step(32), 5) / 32
+        plain_ms = timed(lambda: P.step(64), 5) / 64
         P.close()
     npts = start.numel()
+    nz, ny, nx = start.shape
     out = {"prerun_sweeps": prerun, "sweeps": nsweeps,
            "plain_gpts": round(npts / (plain_ms * 1e-3) / 1e9, 3), "periods": {}}
-    for k in (1, 2, 4, 8, 10, 16, 32):
+    flip = W.make_plan([(nsweeps // 2, nz // 2, ny // 3, nx // 5, 28)])
+    for k in (1, 2, 4, 8, 16, 32, 64, 128):
         eps = max(1e-7, k * 1e-7)
-        with torch.cuda.stream(stream):
-            S = abft.Stencil(start.clone(), W.THERMAL_TAPS, C=C, mode="offline", period=k,
-                             threshold=eps, stream=stream)
-            if tune:
-                S.autotune()
-            S.step(k)
-            ms = timed(lambda: S.step(nsweeps), 1) / nsweeps
-            rep, _ = S.check()
-            S.close()
-        out["periods"][k] = {"threshold": eps, "gpts": round(npts / (ms * 1e-3) / 1e9, 3),
-                             "overhead_pct": round((ms / plain_ms - 1) * 100, 2),
-                             "max_noise": rep["max_noise"],
-                             "windows_flagged": rep["windows_flagged"]}
+        r = {"threshold": eps}
+        for faulty in (False, True):
+            with torch.cuda.stream(stream):
+                S = abft.Stencil(start.clone(), W.THERMAL_TAPS, C=C, mode="offline", period=k,
+                                 threshold=eps, stream=stream)
+                if tune and not faulty:
+                    S.autotune()
+                S.step(k)
+                if faulty:
+                    S.inject(W.make_plan([(int(f["sweep"]) + k, int(f["z"]), int(f["y"]),
+                                           int(f["x"]), int(f["bit"])) for f in flip]))
+                ms = timed(lambda: S.step(nsweeps), 1) / nsweeps
+                rep, _ = S.check()
+                S.close()
+            if faulty:
+                r["one_flip_ms_per_sweep"] = round(ms, 5)
+                r["one_flip_rollbacks"] = rep["rollbacks"]
+            else:
+                r["gpts"] = round(npts / (ms * 1e-3) / 1e9, 3)
+                r["ms_per_sweep"] = round(ms, 5)
+                r["overhead_pct"] = round((ms / plain_ms - 1) * 100, 2)
+                r["max_noise"] = rep["max_noise"]
+                r["windows_flagged"] = rep["windows_flagged"]
+        r["one_flip_extra_ms"] = round((r["one_flip_ms_per_sweep"] - r["ms_per_sweep"]) * nsweeps,
+                                       3)
+        out["periods"][k] = r
     return out
 
 

@@ -93,7 +93,7 @@ typedef struct {
 
 typedef struct {
     int32_t mode;               /* abft_mode */
-    int32_t period;             /* offline window length (sweeps per check), 1..32 */
+    int32_t period;             /* offline window length (sweeps per check), 1..128 */
     double threshold;           /* relative detection threshold eps of Section 3.4, > 0 */
     int32_t csum;               /* abft_csum */
     int32_t auto_correct;       /* 1: locate and correct (online) or roll back and recompute

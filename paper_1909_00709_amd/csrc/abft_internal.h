@@ -14,7 +14,7 @@ constexpr int kSweepBlock = 256;  // threads per block of the batched sweep (4 w
 constexpr int kWideBlockLaneBytes = 64;  // most row bytes per lane for 8-wavefront sweep blocks
 constexpr int kFixBlock = 512;    // threads of the single locate/correct block
 constexpr int kCheckBlock = 1024; // threads per block of the offline window check
-constexpr int kMaxPeriod = 32;    // longest offline window handled by one check launch
+constexpr int kMaxPeriod = 128;   // longest offline window (sweeps per check)
 constexpr int kCheckCells = 4;    // checksum-plane cells per thread in the window check
 constexpr int kCheckChunk = 16;   // interpolation steps per window-check launch at most
 constexpr unsigned kBarrierSpinLimit = 1u << 26;  // polls (~50 ns each) before a grid barrier gives up
@@ -133,7 +133,9 @@ struct CheckArgs {
 // checkpoint (attempt 1), separated by grid barriers.
 struct RecoverArgs {
     SweepArgs a;                      // fields shared by the window's sweeps
-    const void* seq[kMaxPeriod + 1];  // sweep j reads seq[j] and writes seq[j + 1]
+    const void* ckpt;                 // the checkpoint: sweep 0 reads it
+    const void* odd;                  // sweep j writes `odd` for even j, `even` for odd j,
+    const void* even;                 // and reads what sweep j - 1 wrote
     double* E;                        // [k][nz][ny] boundary terms of the sweeps, or null
     int32_t k;                        // sweeps in the window
     int64_t t_first;                  // first sweep of the window

@@ -61,8 +61,8 @@ __global__ void __launch_bounds__(NW * 64) recover_kernel(const RecoverArgs r)
     const unsigned nb = gridDim.x;
     for (int j = 0; j < r.k; ++j) {
         SweepArgs a = r.a;
-        a.uin = r.seq[j];
-        a.uout = const_cast<void*>(r.seq[j + 1]);
+        a.uin = j == 0 ? r.ckpt : ((j & 1) ? r.odd : r.even);
+        a.uout = const_cast<void*>((j & 1) ? r.even : r.odd);
         a.t_off = r.t_first + j;
         a.E = r.E != nullptr ? r.E + (size_t)j * a.nz * a.ny : nullptr;
         for (int tile = blockIdx.x; tile < a.ntiles; tile += (int)nb) {

@@ -498,7 +498,9 @@ abft_status offline_recompute(abft_ctx* c, int k, const uint32_t* guard)
         r.a = base_args(c);
         r.a.attempt = 1;
         r.a.Bn = c->B[c->bck ^ 1];
-        for (int j = 0; j <= k; ++j) r.seq[j] = c->u[buf_of(c, j)];
+        r.ckpt = c->u[buf_of(c, 0)];
+        r.odd = c->u[buf_of(c, 1)];
+        r.even = c->u[buf_of(c, 2)];
         r.E = c->E;
         r.k = k;
         r.t_first = c->win_t0;
@@ -605,7 +607,7 @@ abft_status validate_options(const abft_problem* p, const abft_options* o)
     if (o->mode == ABFT_MODE_OFFLINE && o->period < 1)
         return fail(nullptr, ABFT_E_INVAL, "period must be >= 1");
     if (o->mode == ABFT_MODE_OFFLINE && o->period > kMaxPeriod)
-        return fail(nullptr, ABFT_E_UNSUPPORTED, "period above 32");
+        return fail(nullptr, ABFT_E_UNSUPPORTED, "period above 128");
     if (o->mode != ABFT_MODE_NONE && !(o->threshold > 0.0 && std::isfinite(o->threshold)))
         return fail(nullptr, ABFT_E_INVAL, "threshold must be > 0");
     if (o->csum != ABFT_CSUM_F64 && o->csum != ABFT_CSUM_F32_COMP)

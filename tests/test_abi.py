@@ -98,7 +98,7 @@ def test_strerror_and_host_validation():
     f64 = abft.make_problem((1, 4, 4), abft.ABFT_F64, taps, 0x1000, 0x2000)
     s, _ = abft.abft_stencil_init(f64, abft.make_options("online", csum="f32comp"), 0)
     assert s == abft.ABFT_E_INVAL
-    s, _ = abft.abft_stencil_init(good, abft.make_options("offline", period=33), 0)
+    s, _ = abft.abft_stencil_init(good, abft.make_options("offline", period=129), 0)
     assert s == abft.ABFT_E_UNSUPPORTED
     # null context is rejected, destroy(NULL) is a no-op
     assert abft.abft_stencil_step(None, 1) == abft.ABFT_E_INVAL

@@ -86,9 +86,10 @@ def test_several_tiles_per_block(nw):
     assert np.array_equal(g, clean)
 
 
-@pytest.mark.parametrize("period", [1, 2, 32])
+@pytest.mark.parametrize("period", [1, 2, 32, 128])
 def test_window_lengths(period):
-    """The shortest windows (no barrier, one barrier) and the longest (31 barriers)."""
+    """The shortest windows (no barrier, one barrier) and long ones (checked in chunks of 16
+    interpolation steps; 127 barriers in the longest recompute)."""
     nz, ny, nx = 8, 32, 128
     u0, C = W.thermal_grid(nx, ny, nz, np.float64)
     nsweeps = 2 * period + 1
