@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_batch_kernel(const BatchArg
         a.faults = b.faults;
         a.fault_first = b.fault_first;
         a.fault_tmax = b.fault_tmax;
-        sweep_tile<T, MODE, CS, LPR, NCH, VEC, 1, kSweepBlock / 64>(a, gt.y, smem_raw);
+        sweep_tile<T, MODE, CS, LPR, NCH, VEC, 1, kSweepBlock / 64, 1>(a, gt.y, smem_raw);
         if (!b.persistent) break;
         __syncthreads();
         it = sh_next;

@@ -19,14 +19,27 @@ constexpr int kCheckCells = 4;    // checksum-plane cells per thread in the wind
 constexpr int kCheckChunk = 16;   // interpolation steps per window-check launch at most
 constexpr unsigned kBarrierSpinLimit = 1u << 26;  // polls (~50 ns each) before a grid barrier gives up
 
-// Weight slots of the radius-1 star stencil: centre, x-1, x+1, y-1, y+1, z-1, z+1.
-enum { W_C = 0, W_XM, W_XP, W_YM, W_YP, W_ZM, W_ZP, W_COUNT };
+// Weight slots of the star stencils of radius 1 and 2: centre, the six face neighbours at
+// distance 1 (x-1, x+1, y-1, y+1, z-1, z+1), then the six at distance 2.
+enum {
+    W_C = 0, W_XM, W_XP, W_YM, W_YP, W_ZM, W_ZP,
+    W_XM2, W_XP2, W_YM2, W_YP2, W_ZM2, W_ZP2, W_COUNT
+};
+
+// Slot of the tap at distance d (1 or 2) along axis (0 = x, 1 = y, 2 = z), on the minus
+// (sign < 0) or plus side.
+__host__ __device__ constexpr int w_slot(int axis, int d, int sign)
+{
+    return (d == 1 ? W_XM : W_XM2) + 2 * axis + (sign > 0 ? 1 : 0);
+}
 
 struct Stencil {
     double w[W_COUNT];  // weights rounded to the grid dtype, held as double
     uint32_t mask;      // bit k set when slot k is a tap of the stencil
     int32_t bc;         // abft_bc
     double g;           // constant ghost value (rounded to the grid dtype)
+    int32_t rad;        // 1, or 2 when a distance-2 tap is present
+    int32_t pad;
 };
 
 struct RowFlag {
@@ -185,6 +198,7 @@ struct SweepShape {
     int32_t tz;    // planes per block
     int32_t pf;    // planes loaded ahead of the one computed: 1 or 2
     int32_t nw = 4;  // wavefronts per block: 4 or 8 (each holds 64 / lpr rows)
+    int32_t rad = 1; // stencil radius the kernel is built for: 1 or 2
 };
 
 bool sweep_shape_supported(int dtype, const SweepShape& s);
@@ -219,6 +233,18 @@ hipError_t launch_recover_f32(int csum, const SweepShape& s, const RecoverArgs& 
                               int num_cus, hipStream_t st);
 hipError_t launch_recover_f64(int csum, const SweepShape& s, const RecoverArgs& r, size_t lds,
                               int num_cus, hipStream_t st);
+hipError_t launch_recover_r2_f32(int csum, const SweepShape& s, const RecoverArgs& r, size_t lds,
+                                 int num_cus, hipStream_t st);
+hipError_t launch_recover_r2_f64(int csum, const SweepShape& s, const RecoverArgs& r, size_t lds,
+                                 int num_cus, hipStream_t st);
+
+// Radius-2 sweep launchers (prefetch depth 1).
+hipError_t launch_sweep_r2_f32_pc(int mode, int csum, const SweepShape& s, const SweepArgs& a,
+                                  hipStream_t st, size_t lds);
+hipError_t launch_sweep_r2_f32_prot(int csum, const SweepShape& s, const SweepArgs& a,
+                                    hipStream_t st, size_t lds);
+hipError_t launch_sweep_r2_f64(int mode, int csum, const SweepShape& s, const SweepArgs& a,
+                               hipStream_t st, size_t lds);
 
 // Per-variant sweep launchers (one translation unit each).
 #define ABFT_DECL_SWEEP(NAME)                                                                 \

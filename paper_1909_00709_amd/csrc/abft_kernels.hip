@@ -1,5 +1,7 @@
 // gfx950 kernels other than the sweep: locate and correct (Section 3.5), the offline window
 // check (Section 4.1), and the initial checksums.
+#include <algorithm>
+
 #include "abft_device.h"
 
 namespace abft {
@@ -26,7 +28,7 @@ __device__ double block_sum(double v, double* red)
 // correction of the intersections (Eq.(10), with the partial sum over the other points taken
 // directly).  Exits at once when nothing was flagged.
 // ------------------------------------------------------------------------------------------
-template <typename T>
+template <typename T, int RAD>
 __device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* red, int& sh_K)
 {
     FlagSlot* slot = a.slot;
@@ -79,30 +81,48 @@ __device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* re
         int j = i;
         while (j < n && slot->rows[j].z == z) ++j;
         const int R = j - i;
-        const int zm = map_coord(z - 1, nz, bc), zp = map_coord(z + 1, nz, bc);
+        // layers z - d and z + d for d = 1 .. RAD (mapped by the boundary rule)
+        int zl[RAD][2];
+#pragma unroll
+        for (int d = 0; d < RAD; ++d) {
+            zl[d][0] = map_coord(z - d - 1, nz, bc);
+            zl[d][1] = map_coord(z + d + 1, nz, bc);
+        }
 
-        // column checksums of the layer (input: z and its z-neighbours; output: z)
-        double s_zm[kFixXPT], s_zp[kFixXPT], u_f[kFixXPT], u_l[kFixXPT];
+        // column checksums of the layer (input: z and its z-neighbours; output: z), and the
+        // first and last RAD points of each input column (the y-boundary terms)
+        double s_z[RAD][2][kFixXPT], u_f[RAD][kFixXPT], u_l[RAD][kFixXPT];
 #pragma unroll
         for (int k = 0; k < kFixXPT; ++k) {
             const int x = tid + k * kFixBlock;
-            s_zm[k] = s_zp[k] = u_f[k] = u_l[k] = 0.0;
+#pragma unroll
+            for (int d = 0; d < RAD; ++d) s_z[d][0][k] = s_z[d][1][k] = u_f[d][k] = u_l[d][k] = 0.0;
             if (x < nx) {
-                double sz = 0.0, szm = 0.0, szp = 0.0, sn = 0.0;
+                double sz = 0.0, sn = 0.0, sl[RAD][2];
+#pragma unroll
+                for (int d = 0; d < RAD; ++d) sl[d][0] = sl[d][1] = 0.0;
 #pragma unroll 4
                 for (int yy = 0; yy < ny; ++yy) {
                     const size_t o = (size_t)yy * nx + x;
                     sz += (double)uin[(size_t)z * ps + o];
-                    if (zm >= 0) szm += (double)uin[(size_t)zm * ps + o];
-                    if (zp >= 0) szp += (double)uin[(size_t)zp * ps + o];
+#pragma unroll
+                    for (int d = 0; d < RAD; ++d)
+#pragma unroll
+                        for (int sg = 0; sg < 2; ++sg)
+                            if (zl[d][sg] >= 0) sl[d][sg] += (double)uin[(size_t)zl[d][sg] * ps + o];
                     sn += (double)uout[(size_t)z * ps + o];
                 }
                 At[x] = sz;
                 An[x] = sn;
-                s_zm[k] = zm >= 0 ? szm : (double)ny * gd;
-                s_zp[k] = zp >= 0 ? szp : (double)ny * gd;
-                u_f[k] = (double)uin[(size_t)z * ps + x];
-                u_l[k] = (double)uin[(size_t)z * ps + (size_t)(ny - 1) * nx + x];
+#pragma unroll
+                for (int d = 0; d < RAD; ++d) {
+#pragma unroll
+                    for (int sg = 0; sg < 2; ++sg)
+                        s_z[d][sg][k] = zl[d][sg] >= 0 ? sl[d][sg] : (double)ny * gd;
+                    const int yf = d < ny ? d : ny - 1, yl = ny - 1 - d >= 0 ? ny - 1 - d : 0;
+                    u_f[d][k] = (double)uin[(size_t)z * ps + (size_t)yf * nx + x];
+                    u_l[d][k] = (double)uin[(size_t)z * ps + (size_t)yl * nx + x];
+                }
             }
         }
         __syncthreads();
@@ -111,25 +131,45 @@ __device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* re
             const int x = tid + k * kFixBlock;
             if (x < nx) {
                 const double a0 = At[x];
-                double gt, gb;  // G(y = -1), G(y = ny)
-                if (bc == ABFT_BC_CLAMP) { gt = u_f[k]; gb = u_l[k]; }
-                else if (bc == ABFT_BC_PERIODIC) { gt = u_l[k]; gb = u_f[k]; }
-                else { gt = gd; gb = gd; }
+                // G of the column at y = -q and y = ny - 1 + q (q = 1 .. RAD)
+                auto g_lo = [&](int q) -> double {
+                    if (bc == ABFT_BC_CLAMP) return u_f[0][k];
+                    if (bc == ABFT_BC_PERIODIC) return u_l[q - 1][k];
+                    return gd;
+                };
+                auto g_hi = [&](int q) -> double {
+                    if (bc == ABFT_BC_CLAMP) return u_l[0][k];
+                    if (bc == ABFT_BC_PERIODIC) return u_f[q - 1][k];
+                    return gd;
+                };
                 auto acol = [&](int xx) -> double {
                     const int mx = map_coord(xx, nx, bc);
                     return mx < 0 ? (double)ny * gd : At[mx];
                 };
                 double ap = a.cA[(size_t)z * nx + x];
-                if (mask & 1u) ap += a.st.w[W_C] * a0;
-                if (mask & 2u) ap += a.st.w[W_XM] * acol(x - 1);
-                if (mask & 4u) ap += a.st.w[W_XP] * acol(x + 1);
-                if (mask & 8u) ap += a.st.w[W_YM] * (a0 + (gt - u_l[k]));
-                if (mask & 16u) ap += a.st.w[W_YP] * (a0 + (gb - u_f[k]));
-                if (mask & 32u) ap += a.st.w[W_ZM] * s_zm[k];
-                if (mask & 64u) ap += a.st.w[W_ZP] * s_zp[k];
+                if (mask & (1u << W_C)) ap += a.st.w[W_C] * a0;
+#pragma unroll
+                for (int d = 1; d <= RAD; ++d) {
+                    if (mask & (1u << w_slot(0, d, -1))) ap += a.st.w[w_slot(0, d, -1)] * acol(x - d);
+                    if (mask & (1u << w_slot(0, d, 1))) ap += a.st.w[w_slot(0, d, 1)] * acol(x + d);
+                    // shift dy = -d reads G(-d .. -1) and drops the last d points; dy = +d
+                    // reads G(ny .. ny+d-1) and drops the first d points
+                    if (mask & (1u << w_slot(1, d, -1))) {
+                        double b = 0.0;
+                        for (int q = 1; q <= d; ++q) b += g_lo(q) - u_l[q - 1][k];
+                        ap += a.st.w[w_slot(1, d, -1)] * (a0 + b);
+                    }
+                    if (mask & (1u << w_slot(1, d, 1))) {
+                        double b = 0.0;
+                        for (int q = 1; q <= d; ++q) b += g_hi(q) - u_f[q - 1][k];
+                        ap += a.st.w[w_slot(1, d, 1)] * (a0 + b);
+                    }
+                    if (mask & (1u << w_slot(2, d, -1))) ap += a.st.w[w_slot(2, d, -1)] * s_z[d - 1][0][k];
+                    if (mask & (1u << w_slot(2, d, 1))) ap += a.st.w[w_slot(2, d, 1)] * s_z[d - 1][1][k];
+                }
                 Ap[x] = ap;
-                const double d = fabs(An[x] - ap);
-                cflag[x] = !(d <= a.eps * fabs(ap));
+                const double dd = fabs(An[x] - ap);
+                cflag[x] = !(dd <= a.eps * fabs(ap));
             }
         }
         __syncthreads();
@@ -205,13 +245,13 @@ __device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* re
     if (tid == 0) slot->count = 0u;
 }
 
-template <typename T>
+template <typename T, int RAD>
 __global__ void __launch_bounds__(kFixBlock) fixup_kernel(const FixArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ double red[kFixBlock / 64];
     __shared__ int sh_K;
-    fixup_body<T>(a, smem_raw, red, sh_K);
+    fixup_body<T, RAD>(a, smem_raw, red, sh_K);
 }
 
 // One block per grid of a batch; each exits at once unless its grid flagged a row.
@@ -242,7 +282,7 @@ __global__ void __launch_bounds__(kFixBlock) fixup_batch_kernel(const BatchArgs 
     a.grid = g;
     a.t_base = b.t_base;
     a.t_off = b.t_off;
-    fixup_body<T>(a, smem_raw, red, sh_K);
+    fixup_body<T, 1>(a, smem_raw, red, sh_K);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -253,12 +293,13 @@ __global__ void __launch_bounds__(kFixBlock) fixup_batch_kernel(const BatchArgs 
 // steps: all k of a window up to kCheckChunk, else the window's steps in chunks, each but the
 // last writing its tiles' interiors to an intermediate plane.
 // ------------------------------------------------------------------------------------------
+template <int RAD>
 __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     if (a.guard != nullptr && *a.guard == 0u) return;
 
-    const int nx = a.nx, ny = a.ny, nz = a.nz, bc = a.st.bc, k = a.ns;
+    const int nx = a.nx, ny = a.ny, nz = a.nz, bc = a.st.bc, k = a.ns, hal = RAD * a.ns;
     const bool per = bc == ABFT_BC_PERIODIC;
     const double gd = a.st.g;
     const uint32_t mask = a.st.mask;
@@ -268,33 +309,45 @@ __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
     const int iz0 = zt * a.tzi, iz1 = min(iz0 + a.tzi, nz);
     int ry0, ry1, rz0, rz1;
     if (per) {
-        ry0 = iy0 - k; ry1 = iy1 + k; rz0 = iz0 - k; rz1 = iz1 + k;
+        ry0 = iy0 - hal; ry1 = iy1 + hal; rz0 = iz0 - hal; rz1 = iz1 + hal;
     } else {
-        ry0 = max(0, iy0 - k); ry1 = min(ny, iy1 + k);
-        rz0 = max(0, iz0 - k); rz1 = min(nz, iz1 + k);
+        ry0 = max(0, iy0 - hal); ry1 = min(ny, iy1 + hal);
+        rz0 = max(0, iz0 - hal); rz1 = min(nz, iz1 + hal);
     }
     const int RY = ry1 - ry0, RZ = rz1 - rz0, NC = RY * RZ;
     double* cur = reinterpret_cast<double*>(smem_raw);
     double* nxt = cur + (size_t)a.ry_max * a.rz_max;
 
     auto wrap = [](int c, int n) { const int m = c % n; return m < 0 ? m + n : m; };
-    const double wx = ((mask & 1u) ? a.st.w[W_C] : 0.0) + ((mask & 2u) ? a.st.w[W_XM] : 0.0) +
-                      ((mask & 4u) ? a.st.w[W_XP] : 0.0);
-    const double wym = (mask & 8u) ? a.st.w[W_YM] : 0.0, wyp = (mask & 16u) ? a.st.w[W_YP] : 0.0;
-    const double wzm = (mask & 32u) ? a.st.w[W_ZM] : 0.0, wzp = (mask & 64u) ? a.st.w[W_ZP] : 0.0;
+    auto wt = [&](int slot) { return ((mask >> slot) & 1u) ? a.st.w[slot] : 0.0; };
+    // the x taps collapse onto the row itself (their boundary terms come from E)
+    double wx = wt(W_C);
+    double wy[RAD][2], wz[RAD][2];
+#pragma unroll
+    for (int d = 0; d < RAD; ++d) {
+        wx += wt(w_slot(0, d + 1, -1)) + wt(w_slot(0, d + 1, 1));
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            wy[d][sg] = wt(w_slot(1, d + 1, sg ? 1 : -1));
+            wz[d][sg] = wt(w_slot(2, d + 1, sg ? 1 : -1));
+        }
+    }
 
     // Each thread owns the same cells at every step: their constant-term checksums, global
     // offsets and neighbour cells stay in registers.  nb < 0 marks a neighbour that is a row
     // of constant ghosts (sum nx * g); a neighbour outside the loaded region points at the
     // cell itself (its value only reaches cells outside the tile).
     double cbv[kCheckCells];
-    int gl[kCheckCells], nym[kCheckCells], nyp[kCheckCells], nzm[kCheckCells], nzp[kCheckCells];
+    int gl[kCheckCells], nby[kCheckCells][RAD][2], nbz[kCheckCells][RAD][2];
 #pragma unroll
     for (int q = 0; q < kCheckCells; ++q) {
         const int i = tid + q * kCheckBlock;
         cbv[q] = 0.0;
         gl[q] = 0;
-        nym[q] = nyp[q] = nzm[q] = nzp[q] = i < NC ? i : 0;
+#pragma unroll
+        for (int d = 0; d < RAD; ++d)
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg) nby[q][d][sg] = nbz[q][d][sg] = i < NC ? i : 0;
         if (i < NC) {
             const int yy = ry0 + i % RY, zz = rz0 + i / RY;
             const int gy = per ? wrap(yy, ny) : yy, gz = per ? wrap(zz, nz) : zz;
@@ -311,10 +364,13 @@ __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
                 if (y2 < ry0 || y2 >= ry1 || z2 < rz0 || z2 >= rz1) return i;
                 return (z2 - rz0) * RY + (y2 - ry0);
             };
-            nym[q] = nbi(0, -1);
-            nyp[q] = nbi(0, 1);
-            nzm[q] = nbi(-1, 0);
-            nzp[q] = nbi(1, 0);
+#pragma unroll
+            for (int d = 0; d < RAD; ++d) {
+                nby[q][d][0] = nbi(0, -d - 1);
+                nby[q][d][1] = nbi(0, d + 1);
+                nbz[q][d][0] = nbi(-d - 1, 0);
+                nbz[q][d][1] = nbi(d + 1, 0);
+            }
         }
     }
     __syncthreads();
@@ -329,10 +385,13 @@ __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
                 auto val = [&](int j) { return j < 0 ? ghost_row : cur[j]; };
                 double v = cbv[q] + wx * cur[i];
                 if (Es != nullptr) v += Es[gl[q]];
-                v += wym * val(nym[q]);
-                v += wyp * val(nyp[q]);
-                v += wzm * val(nzm[q]);
-                v += wzp * val(nzp[q]);
+#pragma unroll
+                for (int d = 0; d < RAD; ++d) {
+                    v += wy[d][0] * val(nby[q][d][0]);
+                    v += wy[d][1] * val(nby[q][d][1]);
+                    v += wz[d][0] * val(nbz[q][d][0]);
+                    v += wz[d][1] * val(nbz[q][d][1]);
+                }
                 nxt[i] = v;
             }
         }
@@ -451,9 +510,11 @@ __global__ void set_i64_kernel(int64_t* p, int64_t v)
 bool sweep_shape_supported(int dtype, const SweepShape& s)
 {
     const int vf = dtype == ABFT_F32 ? 4 : 2;
-    if (s.tz < 1 || (s.nw != 4 && s.nw != 8)) return false;
-    if (s.nw == 8 && s.nch * s.vec * (vf == 4 ? 4 : 8) > kWideBlockLaneBytes) return false;
-    if (s.pf == 2) return s.vec == vf && s.lpr == 64 && (s.nch == 2 || s.nch == 4);
+    if (s.tz < 1 || (s.nw != 4 && s.nw != 8) || (s.rad != 1 && s.rad != 2)) return false;
+    if (s.nw == 8 && s.nch * s.vec * (vf == 4 ? 4 : 8) * s.rad > kWideBlockLaneBytes)
+        return false;
+    if (s.pf == 2)
+        return s.rad == 1 && s.vec == vf && s.lpr == 64 && (s.nch == 2 || s.nch == 4);
     if (s.pf != 1) return false;
     if (s.vec == vf) {
         if (s.lpr == 16) return s.nch == 1 || s.nch == 2 || s.nch == 4;
@@ -470,8 +531,9 @@ size_t sweep_lds_bytes(int dtype, int nx, const SweepShape& s)
 {
     const size_t es = dtype == ABFT_F32 ? 4 : 8;
     const size_t ty = (size_t)sweep_rows_per_block(s);
-    return 2 * (ty + 2) * (size_t)(nx + 2 * s.vec) * es   // two plane buffers
-           + 2 * ty * (size_t)s.tz * sizeof(double);        // checksum and boundary tables
+    const size_t pad = (size_t)std::max(s.vec, s.rad);
+    return 2 * (ty + 2 * s.rad) * (nx + 2 * pad) * es   // two plane buffers with halo rows
+           + 2 * ty * (size_t)s.tz * sizeof(double);     // checksum and boundary tables
 }
 
 hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, const SweepArgs& a,
@@ -480,6 +542,13 @@ hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, cons
     if (!sweep_shape_supported(dtype, s)) return hipErrorInvalidValue;
     const size_t lds = sweep_lds_bytes(dtype, a.nx, s);
     if (mode == MODE_PLAIN) csum = CS_F64;  // no checksum in the plain variant
+    if (s.rad == 2) {
+        if (dtype == ABFT_F32) {
+            if (mode == MODE_PROT) return launch_sweep_r2_f32_prot(csum, s, a, st, lds);
+            return launch_sweep_r2_f32_pc(mode, csum, s, a, st, lds);
+        }
+        return launch_sweep_r2_f64(mode, csum, s, a, st, lds);
+    }
     if (dtype == ABFT_F32) {
         if (mode == MODE_PLAIN) return launch_sweep_f32_plain(csum, s, a, st, lds);
         if (mode == MODE_CSUM) return launch_sweep_f32_csum(csum, s, a, st, lds);
@@ -505,6 +574,10 @@ hipError_t launch_recover(int dtype, int csum, const SweepShape& s, const Recove
     if (!recover_shape_supported(dtype, s) || r.k < 1 || r.k > kMaxPeriod || num_cus < 1)
         return hipErrorInvalidValue;
     const size_t lds = sweep_lds_bytes(dtype, r.a.nx, s);
+    if (s.rad == 2) {
+        if (dtype == ABFT_F32) return launch_recover_r2_f32(csum, s, r, lds, num_cus, st);
+        return launch_recover_r2_f64(csum, s, r, lds, num_cus, st);
+    }
     if (dtype == ABFT_F32) return launch_recover_f32(csum, s, r, lds, num_cus, st);
     return launch_recover_f64(csum, s, r, lds, num_cus, st);
 }
@@ -526,10 +599,14 @@ hipError_t launch_fixup_batch(int dtype, const BatchArgs& b, int maxnx, hipStrea
 hipError_t launch_fixup(int dtype, const FixArgs& a, hipStream_t st)
 {
     const size_t lds = fixup_lds_bytes(a.nx);
-    if (dtype == ABFT_F32)
-        hipLaunchKernelGGL(fixup_kernel<float>, dim3(1), dim3(kFixBlock), lds, st, a);
-    else
-        hipLaunchKernelGGL(fixup_kernel<double>, dim3(1), dim3(kFixBlock), lds, st, a);
+    const bool r2 = a.st.rad == 2;
+    if (dtype == ABFT_F32) {
+        if (r2) hipLaunchKernelGGL((fixup_kernel<float, 2>), dim3(1), dim3(kFixBlock), lds, st, a);
+        else hipLaunchKernelGGL((fixup_kernel<float, 1>), dim3(1), dim3(kFixBlock), lds, st, a);
+    } else {
+        if (r2) hipLaunchKernelGGL((fixup_kernel<double, 2>), dim3(1), dim3(kFixBlock), lds, st, a);
+        else hipLaunchKernelGGL((fixup_kernel<double, 1>), dim3(1), dim3(kFixBlock), lds, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -537,8 +614,11 @@ size_t check_lds_bytes(int ry, int rz) { return (size_t)2 * ry * rz * sizeof(dou
 
 hipError_t launch_check(const CheckArgs& a, hipStream_t st)
 {
-    hipLaunchKernelGGL(check_kernel, dim3(a.nyt * a.nzt), dim3(kCheckBlock),
-                       check_lds_bytes(a.ry_max, a.rz_max), st, a);
+    const size_t lds = check_lds_bytes(a.ry_max, a.rz_max);
+    if (a.st.rad == 2)
+        hipLaunchKernelGGL(check_kernel<2>, dim3(a.nyt * a.nzt), dim3(kCheckBlock), lds, st, a);
+    else
+        hipLaunchKernelGGL(check_kernel<1>, dim3(a.nyt * a.nzt), dim3(kCheckBlock), lds, st, a);
     return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* bar, unsigned target,
     return ok != 0;
 }
 
-template <typename T, int CS, int LPR, int NCH, int VEC, int NW>
+template <typename T, int CS, int LPR, int NCH, int VEC, int NW, int RAD>
 __global__ void __launch_bounds__(NW * 64) recover_kernel(const RecoverArgs r)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -67,9 +67,9 @@ __global__ void __launch_bounds__(NW * 64) recover_kernel(const RecoverArgs r)
         a.E = r.E != nullptr ? r.E + (size_t)j * a.nz * a.ny : nullptr;
         for (int tile = blockIdx.x; tile < a.ntiles; tile += (int)nb) {
             if (j == r.k - 1)
-                sweep_tile<T, MODE_CSUM, CS, LPR, NCH, VEC, 1, NW>(a, tile, smem_raw);
+                sweep_tile<T, MODE_CSUM, CS, LPR, NCH, VEC, 1, NW, RAD>(a, tile, smem_raw);
             else
-                sweep_tile<T, MODE_PLAIN, CS, LPR, NCH, VEC, 1, NW>(a, tile, smem_raw);
+                sweep_tile<T, MODE_PLAIN, CS, LPR, NCH, VEC, 1, NW, RAD>(a, tile, smem_raw);
             __syncthreads();  // the tile's LDS use is over
         }
         if (j + 1 < r.k && !grid_barrier(r.bar, (unsigned)(j + 1) * nb, &cnt->barrier_timeouts))
@@ -82,13 +82,13 @@ __global__ void __launch_bounds__(NW * 64) recover_kernel(const RecoverArgs r)
     }
 }
 
-template <typename T, int CS>
+template <typename T, int CS, int RAD>
 hipError_t launch_recover_t(const SweepShape& s, const RecoverArgs& r, size_t lds, int num_cus,
                             hipStream_t st)
 {
 #define ABFT_RECOVER_CASE_NW(LPR_, NCH_, VEC_, NW_)                                            \
     if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_ && s.nw == NW_) {                      \
-        auto kern = recover_kernel<T, CS, LPR_, NCH_, VEC_, NW_>;                              \
+        auto kern = recover_kernel<T, CS, LPR_, NCH_, VEC_, NW_, RAD>;                         \
         static int lds_set = 0;                                                                \
         static size_t occ_lds = 0;                                                             \
         static int occ = 0;                                                                    \
@@ -113,7 +113,7 @@ hipError_t launch_recover_t(const SweepShape& s, const RecoverArgs& r, size_t ld
     }
 #define ABFT_RECOVER_CASE(LPR_, NCH_, VEC_)                                                    \
     ABFT_RECOVER_CASE_NW(LPR_, NCH_, VEC_, 4)                                                  \
-    if constexpr (NCH_ * VEC_ * sizeof(T) <= kWideBlockLaneBytes) {                            \
+    if constexpr (NCH_ * VEC_ * sizeof(T) * RAD <= kWideBlockLaneBytes) {                      \
         ABFT_RECOVER_CASE_NW(LPR_, NCH_, VEC_, 8)                                              \
     }
     constexpr int VF = 16 / (int)sizeof(T);

@@ -149,30 +149,31 @@ void free_all(abft_ctx* c)
     c->allocs.clear();
 }
 
-// Radius-1 star taps -> weight slots.
+// Star taps of radius 1 or 2 (the centre and points along one axis at distance 1 or 2) ->
+// weight slots; the radius is 2 when any distance-2 tap is present.
 abft_status map_taps(abft_ctx* c, const abft_problem* p)
 {
     c->st = Stencil{};
     c->st.bc = p->bc;
     c->st.g = round_to(p->dtype, p->bc_value);
+    c->st.rad = 1;
     for (int k = 0; k < p->ntaps; ++k) {
         const abft_tap& t = p->taps[k];
+        const int axes = (t.dx != 0) + (t.dy != 0) + (t.dz != 0);
         const int ad = std::abs(t.dx) + std::abs(t.dy) + std::abs(t.dz);
-        if (ad > 1)
+        if (axes > 1 || ad > 2)
             return fail(c, ABFT_E_UNSUPPORTED,
-                        "GPU kernels cover the radius-1 star (centre and six face neighbours)");
-        int slot;
-        if (t.dx == -1) slot = W_XM;
-        else if (t.dx == 1) slot = W_XP;
-        else if (t.dy == -1) slot = W_YM;
-        else if (t.dy == 1) slot = W_YP;
-        else if (t.dz == -1) slot = W_ZM;
-        else if (t.dz == 1) slot = W_ZP;
-        else slot = W_C;
+                        "GPU kernels cover star stencils of radius 1 or 2 (centre and points "
+                        "along one axis)");
+        int slot = W_C;
+        if (t.dx != 0) slot = w_slot(0, std::abs(t.dx), t.dx);
+        else if (t.dy != 0) slot = w_slot(1, std::abs(t.dy), t.dy);
+        else if (t.dz != 0) slot = w_slot(2, std::abs(t.dz), t.dz);
         if (c->st.mask & (1u << slot)) return fail(c, ABFT_E_INVAL, "duplicate tap offset");
         if (!std::isfinite(t.w)) return fail(c, ABFT_E_INVAL, "non-finite tap weight");
         c->st.mask |= 1u << slot;
         c->st.w[slot] = round_to(p->dtype, t.w);
+        if (ad == 2) c->st.rad = 2;
     }
     return ABFT_OK;
 }
@@ -182,10 +183,11 @@ abft_status map_taps(abft_ctx* c, const abft_problem* p)
 // block of 8 wavefronts per compute unit take that (the deeper block halves the share of halo
 // rows it loads and keeps more loads in flight per CU), cut into about that many z-slabs;
 // smaller grids take blocks of 4 wavefronts and enough z-slabs for ~1024 blocks.
-bool default_shape(int dtype, int nx, int ny, int nz, SweepShape* s)
+bool default_shape(int dtype, int nx, int ny, int nz, int rad, SweepShape* s)
 {
     const int vf = 16 / (int)esize(dtype);
     SweepShape r{};
+    r.rad = rad;
     if (nx % vf == 0) {
         r.vec = vf;
         if (nx <= 16 * vf * 4) {
@@ -223,8 +225,10 @@ bool default_shape(int dtype, int nx, int ny, int nz, SweepShape* s)
     return true;
 }
 
-abft_status apply_shape(abft_ctx* c, const SweepShape& s)
+abft_status apply_shape(abft_ctx* c, const SweepShape& shape)
 {
+    SweepShape s = shape;
+    s.rad = c->st.rad;  // the kernels are built per stencil radius
     if (!sweep_shape_supported(c->dtype, s)) return fail(c, ABFT_E_UNSUPPORTED, "launch shape");
     if ((int64_t)s.lpr * s.nch * s.vec < c->nx) return fail(c, ABFT_E_UNSUPPORTED, "row too long");
     if (s.vec > 1 && c->nx % s.vec) return fail(c, ABFT_E_UNSUPPORTED, "row not 16-byte multiple");
@@ -248,6 +252,7 @@ std::string cache_key(const abft_ctx* c)
     std::ostringstream o;
     o << c->dtype << ' ' << c->nx << ' ' << c->ny << ' ' << c->nz << ' ' << c->mode << ' '
       << c->csum;
+    if (c->st.rad != 1) o << " r" << c->st.rad;
     return o.str();
 }
 
@@ -350,12 +355,18 @@ SweepArgs base_args(const abft_ctx* c)
     return a;
 }
 
+// The x-boundary terms of Theorem 1 cancel in the weighted sum (and need not be recorded for
+// the offline interpolation) under the periodic rule, and under clamp for radius-1 x taps of
+// equal weight; clamp with distance-2 x taps, and the constant rule, leave them.
 bool need_boundary_terms(const abft_ctx* c)
 {
     if (c->bc == ABFT_BC_PERIODIC) return false;
-    const bool xm = c->st.mask & (1u << W_XM), xp = c->st.mask & (1u << W_XP);
-    if (c->bc == ABFT_BC_CLAMP) return (xm != xp) || (xm && c->st.w[W_XM] != c->st.w[W_XP]);
-    return xm || xp;
+    const uint32_t m = c->st.mask;
+    const bool xm = m & (1u << W_XM), xp = m & (1u << W_XP);
+    const bool x2 = m & ((1u << W_XM2) | (1u << W_XP2));
+    if (c->bc == ABFT_BC_CLAMP)
+        return x2 || (xm != xp) || (xm && c->st.w[W_XM] != c->st.w[W_XP]);
+    return xm || xp || x2;
 }
 
 int buf_of(const abft_ctx* c, int j) { return j == 0 ? c->ckpt : ((j & 1) ? c->wq : c->wr); }
@@ -431,8 +442,8 @@ abft_status offline_sweep(abft_ctx* c, int j, int k, int attempt, const uint32_t
 
 abft_status offline_check(abft_ctx* c, int k, int attempt, const uint32_t* guard)
 {
-    const int chunk = std::min(k, kCheckChunk);
-    check_shape(c, chunk);
+    const int chunk = std::min(k, kCheckChunk / c->st.rad);
+    check_shape(c, chunk * c->st.rad);  // the dependency cone: radius x steps
     CheckArgs a{};
     a.Bdir = c->B[c->bck ^ 1];
     a.cB = c->cB;
@@ -590,8 +601,8 @@ abft_status validate_problem(const abft_problem* p)
         return fail(nullptr, ABFT_E_INVAL, "dtype");
     if (p->bc < ABFT_BC_CLAMP || p->bc > ABFT_BC_CONSTANT)
         return fail(nullptr, ABFT_E_INVAL, "boundary rule");
-    if (p->ntaps < 1 || p->ntaps > 7 || !p->taps)
-        return fail(nullptr, ABFT_E_INVAL, "taps (1..7 required)");
+    if (p->ntaps < 1 || p->ntaps > W_COUNT || !p->taps)
+        return fail(nullptr, ABFT_E_INVAL, "taps (1..13 required)");
     if (!p->u0 || !p->u1 || p->u0 == p->u1)
         return fail(nullptr, ABFT_E_INVAL, "u0 and u1 must be distinct device buffers");
     if (!std::isfinite(p->bc_value) || !std::isfinite(p->cterm_scalar))
@@ -855,8 +866,21 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
     s = map_taps(c, p);
     if (s) return bail(s);
     SweepShape shape{};
-    if (!cache_lookup(c, &shape) || !sweep_shape_supported(c->dtype, shape)) {
-        if (!default_shape(c->dtype, c->nx, c->ny, c->nz, &shape))
+    if (c->st.rad == 2) {
+        // the shifted-line sums of Theorem 1 (and the periodic wrap) need every axis that
+        // carries a distance-2 tap to be at least 2 long
+        for (int ax = 0; ax < 3; ++ax) {
+            const int n = ax == 0 ? c->nx : ax == 1 ? c->ny : c->nz;
+            const uint32_t m2 = (1u << w_slot(ax, 2, -1)) | (1u << w_slot(ax, 2, 1));
+            if ((c->st.mask & m2) && n < 2)
+                return bail(fail(c, ABFT_E_UNSUPPORTED, "distance-2 taps along an axis of "
+                                                        "length 1"));
+        }
+    }
+    const bool cached = cache_lookup(c, &shape);
+    shape.rad = c->st.rad;
+    if (!cached || !sweep_shape_supported(c->dtype, shape)) {
+        if (!default_shape(c->dtype, c->nx, c->ny, c->nz, c->st.rad, &shape))
             return bail(fail(c, ABFT_E_UNSUPPORTED, "row length beyond the GPU kernels"));
     }
     s = apply_shape(c, shape);
@@ -864,7 +888,7 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
     if (fixup_lds_bytes(c->nx) > kLdsLimit || c->nx > 4 * kFixBlock)
         return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
     if (c->mode == ABFT_MODE_OFFLINE) {
-        check_shape(c, std::min(c->period, kCheckChunk));
+        check_shape(c, std::min(c->period, kCheckChunk / c->st.rad) * c->st.rad);
         if ((int64_t)c->ck.ry * c->ck.rz > (int64_t)kCheckCells * kCheckBlock)
             return bail(fail(c, ABFT_E_UNSUPPORTED, "offline period too long for this grid"));
     }
@@ -892,7 +916,7 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
         }
         if (need_boundary_terms(c) && (s = dalloc(c, &c->E, (size_t)c->period * nrows * 8)))
             return bail(s);
-        if (c->period > kCheckChunk &&
+        if (c->period > kCheckChunk / c->st.rad &&
             ((s = dalloc(c, &c->Btmp[0], nrows * 8)) || (s = dalloc(c, &c->Btmp[1], nrows * 8))))
             return bail(s);
     }
@@ -1201,7 +1225,7 @@ abft_status abft_stencil_autotune(abft_ctx* c)
             for (int nch : {1, 2, 4, 8, 16}) {
                 for (int pf : {1, 2})
                     for (int nw : {4, 8}) {
-                        SweepShape sh{lpr, nch, vec, 1, pf, nw};
+                        SweepShape sh{lpr, nch, vec, 1, pf, nw, c->st.rad};
                         if (!sweep_shape_supported(c->dtype, sh)) continue;
                         if ((int64_t)lpr * nch * vec < c->nx) continue;
                         if ((int64_t)lpr * (nch / 2) * vec >= c->nx && nch > 1) continue;  // minimal
@@ -1350,6 +1374,8 @@ abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft
         // per-grid stencil: reuse the single-grid tap mapping on a scratch context
         abft_ctx tmp;
         if ((s = map_taps(&tmp, &p[i]))) return bail(fail(c, s, tmp.err));
+        if (tmp.st.rad != 1)
+            return bail(fail(c, ABFT_E_UNSUPPORTED, "batched grids take radius-1 stars"));
         G.st = tmp.st;
         G.nx = p[i].nx;
         G.ny = p[i].ny;

@@ -1,15 +1,17 @@
-// The fused sweep kernel: Eq.(1) for a radius-1 star stencil, with the row checksum (Eq.(3)),
-// its prediction (Theorem 1, Eq.(5)) and the mismatch test (Section 3.4) in the same pass.
+// The fused sweep kernel: Eq.(1) for a star stencil of radius 1 or 2 (RAD), with the row
+// checksum (Eq.(3)), its prediction (Theorem 1, Eq.(5)) and the mismatch test (Section 3.4)
+// in the same pass.
 //
-// Work decomposition.  A block of NW wavefronts (4 or 8) owns TY whole rows (y0 .. y0+TY-1) of a slab of
-// planes z0 .. z0+tz-1 and marches along z.  Each row belongs to LPR lanes of one wavefront;
-// a lane holds NCH chunks of VEC consecutive x (16-byte accesses), so the row's checksum is a
-// reduction across the row's lanes (DPP) and never needs another pass over the data.  The
-// planes z-1, z, z+1 of the block's rows and the constant term of plane z are kept in
-// registers and rotated as the block advances one plane; the next plane is loaded while the
-// current one is computed.  The in-plane neighbours come from LDS: every plane step writes the
-// block's TY rows plus one halo row on each side (loaded cooperatively by the whole block)
-// into one of two LDS plane buffers, each row padded with its two x-ghost values.
+// Work decomposition.  A block of NW wavefronts (4 or 8) owns TY whole rows (y0 .. y0+TY-1)
+// of a slab of planes z0 .. z0+tz-1 and marches along z.  Each row belongs to LPR lanes of one
+// wavefront; a lane holds NCH chunks of VEC consecutive x (16-byte accesses), so the row's
+// checksum is a reduction across the row's lanes (DPP) and never needs another pass over the
+// data.  The planes z-RAD .. z+RAD of the block's rows and the constant term of plane z are
+// kept in registers and rotated as the block advances one plane; the next plane is loaded
+// while the current one is computed.  The in-plane neighbours come from LDS: every plane step
+// writes the block's TY rows plus RAD halo rows on each side (loaded cooperatively by the
+// whole block) into one of two LDS plane buffers, each row padded with its RAD x-ghost values
+// on each side.
 #pragma once
 
 #include <type_traits>
@@ -27,16 +29,20 @@ constexpr bool kStencilAccF64 = false;
 
 // One tile (TY rows x tz planes) of one sweep, run by one block.  smem_raw is the block's
 // dynamic LDS (sweep_lds_bytes).
-template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF, int NW>
+template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF, int NW, int RAD>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                                            unsigned char* smem_raw)
 {
+    static_assert(RAD == 1 || RAD == 2, "star stencils of radius 1 or 2");
     using V = VecOps<T, VEC>;
     constexpr int NT = NW * 64;       // threads per block
     constexpr int RPW = 64 / LPR;     // rows per wavefront
     constexpr int TY = NW * RPW;      // rows per block
     constexpr int SEGW = LPR * VEC;   // elements of one chunk of a row
     constexpr int HMAX = (NCH * SEGW + NT * VEC - 1) / (NT * VEC);
+    constexpr int PAD = VEC > RAD ? VEC : RAD;  // LDS row pad, ghosts x = -RAD..-1, nx..nx+RAD-1
+    constexpr int NP = 2 * RAD + 1;             // planes z-RAD .. z+RAD in registers
+    constexpr int NH = 2 * RAD;                 // halo rows per LDS plane
 
     T* lds = reinterpret_cast<T*>(smem_raw);
     const int64_t t = a.t_off + (a.t_base != nullptr ? *a.t_base : 0);
@@ -48,8 +54,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int seg = lane / LPR, sl = lane % LPR;
-    const int stride = nx + 2 * VEC;  // LDS row: VEC pad (ghost x=-1 at VEC-1), nx, VEC pad
-    const int plane_elems = (TY + 2) * stride;
+    const int stride = nx + 2 * PAD;  // LDS row: PAD ghosts/padding, nx values, PAD
+    const int plane_elems = (TY + NH) * stride;
 
     const int yb = tile % a.nyb, zb = tile / a.nyb;
     const int y0 = yb * TY, z0 = zb * a.tz;
@@ -67,10 +73,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
     const uint32_t mask = a.st.mask;
     // accumulation type of Eq.(1) (see kStencilAccF64)
     using Acc = typename std::conditional<sizeof(T) == 4 && kStencilAccF64, double, T>::type;
-    const Acc a_c = (Acc)a.st.w[W_C], a_xm = (Acc)a.st.w[W_XM], a_xp = (Acc)a.st.w[W_XP];
-    const Acc a_ym = (Acc)a.st.w[W_YM], a_yp = (Acc)a.st.w[W_YP];
-    const Acc a_zm = (Acc)a.st.w[W_ZM], a_zp = (Acc)a.st.w[W_ZP];
-    const bool full = mask == 0x7Fu;
+    const Acc a_c = (Acc)a.st.w[W_C];
+    Acc ax[RAD][2], ay[RAD][2], az[RAD][2];  // [distance - 1][minus, plus]
+#pragma unroll
+    for (int d = 0; d < RAD; ++d)
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            ax[d][sg] = (Acc)a.st.w[w_slot(0, d + 1, sg ? 1 : -1)];
+            ay[d][sg] = (Acc)a.st.w[w_slot(1, d + 1, sg ? 1 : -1)];
+            az[d][sg] = (Acc)a.st.w[w_slot(2, d + 1, sg ? 1 : -1)];
+        }
+    const uint32_t all = RAD == 1 ? 0x7Fu : 0x1FFFu;
+    const bool full = mask == all;
+    auto has = [&](int slot) { return (mask >> slot) & 1u; };
 
     int flo = 0, fhi = 0;
     if (a.faults != nullptr && t >= 0 && t < a.fault_tmax) {
@@ -78,14 +93,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
         fhi = a.fault_first[t + 1];
     }
 
-    // Halo rows of the block in LDS rows 0 and nrows + 1.
-    const int yh0 = map_coord(y0 - 1, ny, bc), yh1 = map_coord(y0 + nrows, ny, bc);
-    const int lh1 = nrows + 1;
+    // Halo rows of the block: LDS rows 0 .. RAD-1 hold y0-RAD .. y0-1, rows RAD+nrows ..
+    // RAD+nrows+RAD-1 hold y0+nrows .. y0+nrows+RAD-1 (mapped by the boundary rule).
+    int hy[NH], hl[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        hl[h] = h < RAD ? h : RAD + nrows + (h - RAD);
+        hy[h] = map_coord(h < RAD ? y0 - RAD + h : y0 + nrows + (h - RAD), ny, bc);
+    }
 
-    // planes z-1, z, z+1 and the constant term of z in use; planes ahead in flight (PF deep)
-    T dn[NCH][VEC], cu[NCH][VEC], up[NCH][VEC], cc[NCH][VEC], nu[NCH][VEC], nc[NCH][VEC];
-    T hc[2][HMAX][VEC], hn[2][HMAX][VEC];
-    T nu2[PF > 1 ? NCH : 1][VEC], nc2[PF > 1 ? NCH : 1][VEC], hn2[2][PF > 1 ? HMAX : 1][VEC];
+    // planes z-RAD .. z+RAD and the constant term of z in use; planes ahead in flight
+    T pl[NP][NCH][VEC], cc[NCH][VEC], nu[NCH][VEC], nc[NCH][VEC];
+    T hc[NH][HMAX][VEC], hn[NH][HMAX][VEC];
+    T nu2[PF > 1 ? NCH : 1][VEC], nc2[PF > 1 ? NCH : 1][VEC], hn2[NH][PF > 1 ? HMAX : 1][VEC];
 
     auto load_u = [&](T (&d)[NCH][VEC], int zz) {
 #pragma unroll
@@ -116,14 +136,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             }
         }
     };
-    auto load_halo = [&](T (&d)[2][HMAX][VEC], int zz) {
+    auto load_halo = [&](auto& d, int zz) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int yy = h ? yh1 : yh0;
+        for (int h = 0; h < NH; ++h) {
+            const int yy = hy[h];
 #pragma unroll
             for (int k = 0; k < HMAX; ++k) {
                 const int x = (tid + k * NT) * VEC;
-                if (x < nx && yy >= 0) {
+                if (x < nx && yy >= 0 && zz >= 0) {
                     V::load(uin + (size_t)zz * pstride + (size_t)yy * nx + x, d[h][k]);
                 } else {
 #pragma unroll
@@ -132,28 +152,43 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             }
         }
     };
-    // Ghost values of one LDS row from the thread holding x = 0 or x = nx - VEC.
+    // Ghost values of one LDS row from the threads holding its first and last RAD points:
+    // clamp repeats the edge value, periodic wraps, constant writes the ghost value.
     auto put_ghosts = [&](T* row, int x, const T (&d)[VEC]) {
-        if (x == 0) {
-            if (bc == ABFT_BC_CLAMP) row[-1] = d[0];
-            else if (bc == ABFT_BC_PERIODIC) row[nx] = d[0];
-            else { row[-1] = g; row[nx] = g; }
-        }
-        if (x + VEC == nx) {
-            if (bc == ABFT_BC_CLAMP) row[nx] = d[VEC - 1];
-            else if (bc == ABFT_BC_PERIODIC) row[-1] = d[VEC - 1];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const int xv = x + v;
+            if (bc == ABFT_BC_CLAMP) {
+                if (xv == 0)
+#pragma unroll
+                    for (int q = 1; q <= RAD; ++q) row[-q] = d[v];
+                if (xv == nx - 1)
+#pragma unroll
+                    for (int q = 0; q < RAD; ++q) row[nx + q] = d[v];
+            } else if (bc == ABFT_BC_PERIODIC) {
+                if (xv >= nx - RAD) row[xv - nx] = d[v];
+                if (xv < RAD) row[xv + nx] = d[v];
+            } else if (xv == 0) {
+#pragma unroll
+                for (int q = 1; q <= RAD; ++q) {
+                    row[-q] = g;
+                    row[nx - 1 + q] = g;
+                }
+            }
         }
     };
 
-    // The checksums the epilogue's prediction reads for this lane's first plane (its own row's,
-    // the four neighbouring rows' and the constant term's) are loaded now, so that their
+    // The checksums the epilogue's prediction reads for this lane's first plane (its own
+    // row's, the neighbouring rows' and the constant term's) are loaded now, so that their
     // latency hides behind the march instead of adding to the end of every tile.
     auto brow = [&](int z2, int y2) -> double {
         const int mz = map_coord(z2, nz, bc), my = map_coord(y2, ny, bc);
         if (mz < 0 || my < 0) return (double)nx * (double)g;
         return a.Bt[(size_t)mz * ny + my];
     };
-    double pb0 = 0.0, pcb = 0.0, pym = 0.0, pyp = 0.0, pzm = 0.0, pzp = 0.0;
+    double pb0 = 0.0, pcb = 0.0, pfy[RAD][2], pfz[RAD][2];
+#pragma unroll
+    for (int d = 0; d < RAD; ++d) pfy[d][0] = pfy[d][1] = pfz[d][0] = pfz[d][1] = 0.0;
     unsigned long long nknown = 0ull;
     if constexpr (MODE == MODE_PROT) {
         nknown = noise_known(a.cnt);
@@ -162,21 +197,23 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             const size_t l = (size_t)z * ny + y;
             pb0 = a.Bt[l];
             pcb = a.cB[l];
-            if (mask & 8u) pym = brow(z, y - 1);
-            if (mask & 16u) pyp = brow(z, y + 1);
-            if (mask & 32u) pzm = brow(z - 1, y);
-            if (mask & 64u) pzp = brow(z + 1, y);
+#pragma unroll
+            for (int d = 0; d < RAD; ++d) {
+                if (has(w_slot(1, d + 1, -1))) pfy[d][0] = brow(z, y - d - 1);
+                if (has(w_slot(1, d + 1, 1))) pfy[d][1] = brow(z, y + d + 1);
+                if (has(w_slot(2, d + 1, -1))) pfz[d][0] = brow(z - d - 1, y);
+                if (has(w_slot(2, d + 1, 1))) pfz[d][1] = brow(z + d + 1, y);
+            }
         }
     }
 
-    load_u(dn, map_coord(z0 - 1, nz, bc));
-    load_u(cu, z0);
-    load_u(up, map_coord(z0 + 1, nz, bc));
+#pragma unroll
+    for (int q = 0; q < NP; ++q) load_u(pl[q], map_coord(z0 - RAD + q, nz, bc));
     load_c(cc, z0);
     load_halo(hc, z0);
     if constexpr (PF > 1) {
         if (z0 + 1 < z1) {
-            load_u(nu, map_coord(z0 + 2, nz, bc));
+            load_u(nu, map_coord(z0 + RAD + 1, nz, bc));
             load_c(nc, z0 + 1);
             load_halo(hn, z0 + 1);
         }
@@ -190,13 +227,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
         // planes ahead in flight while this one is computed
         if constexpr (PF > 1) {
             if (z + 2 < z1) {
-                load_u(nu2, map_coord(z + 3, nz, bc));
+                load_u(nu2, map_coord(z + RAD + 2, nz, bc));
                 load_c(nc2, z + 2);
                 load_halo(hn2, z + 2);
             }
         } else {
             if (z + 1 < z1) {
-                load_u(nu, map_coord(z + 2, nz, bc));
+                load_u(nu, map_coord(z + RAD + 1, nz, bc));
                 load_c(nc, z + 1);
                 load_halo(hn, z + 1);
             }
@@ -204,19 +241,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
 
         T* buf = lds + ((z - z0) & 1) * plane_elems;
         if (row_ok) {
-            T* row = buf + (r + 1) * stride + VEC;
+            T* row = buf + (r + RAD) * stride + PAD;
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int x = c * SEGW + sl * VEC;
                 if (x < nx) {
-                    V::store(row + x, cu[c]);
-                    put_ghosts(row, x, cu[c]);
+                    V::store(row + x, pl[RAD][c]);
+                    put_ghosts(row, x, pl[RAD][c]);
                 }
             }
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            T* row = buf + (h ? lh1 : 0) * stride + VEC;
+        for (int h = 0; h < NH; ++h) {
+            T* row = buf + hl[h] * stride + PAD;
 #pragma unroll
             for (int k = 0; k < HMAX; ++k) {
                 const int x = (tid + k * NT) * VEC;
@@ -229,40 +266,52 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
         __syncthreads();
 
         // Eq.(1) on the block's rows of plane z.
-        const T* rowm = buf + r * stride + VEC;
-        const T* row0 = buf + (r + 1) * stride + VEC;
-        const T* rowp = buf + (r + 2) * stride + VEC;
+        const T* row0 = buf + (r + RAD) * stride + PAD;
         T o[NCH][VEC];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int x = c * SEGW + sl * VEC;
             if (row_ok && x < nx) {
-                T ym[VEC], yp[VEC];
-                V::load(rowm + x, ym);
-                V::load(rowp + x, yp);
-                const T xl = row0[x - 1], xr = row0[x + VEC];
+                T ym[RAD][VEC], yp[RAD][VEC], xlo[RAD], xhi[RAD];
+#pragma unroll
+                for (int d = 0; d < RAD; ++d) {
+                    V::load(row0 - (d + 1) * stride + x, ym[d]);
+                    V::load(row0 + (d + 1) * stride + x, yp[d]);
+                    xlo[d] = row0[x - 1 - d];    // x - 1 - d
+                    xhi[d] = row0[x + VEC + d];  // x + VEC + d
+                }
+                // the value at x + v + dx for |dx| <= RAD: this lane's chunk, else LDS
+                auto xval = [&](int v, int dx) -> T {
+                    const int idx = v + dx;
+                    if (idx >= 0 && idx < VEC) return pl[RAD][c][idx];
+                    return idx < 0 ? xlo[-idx - 1] : xhi[idx - VEC];
+                };
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
-                    const T xm = v > 0 ? cu[c][v - 1] : xl;
-                    const T xp = v < VEC - 1 ? cu[c][v + 1] : xr;
                     Acc acc = (Acc)cc[c][v];
                     if (full) {
-                        acc = fma(a_c, (Acc)cu[c][v], acc);
-                        acc = fma(a_xm, (Acc)xm, acc);
-                        acc = fma(a_xp, (Acc)xp, acc);
-                        acc = fma(a_ym, (Acc)ym[v], acc);
-                        acc = fma(a_yp, (Acc)yp[v], acc);
-                        acc = fma(a_zm, (Acc)dn[c][v], acc);
-                        acc = fma(a_zp, (Acc)up[c][v], acc);
+                        acc = fma(a_c, (Acc)pl[RAD][c][v], acc);
+#pragma unroll
+                        for (int d = 0; d < RAD; ++d) {
+                            acc = fma(ax[d][0], (Acc)xval(v, -d - 1), acc);
+                            acc = fma(ax[d][1], (Acc)xval(v, d + 1), acc);
+                            acc = fma(ay[d][0], (Acc)ym[d][v], acc);
+                            acc = fma(ay[d][1], (Acc)yp[d][v], acc);
+                            acc = fma(az[d][0], (Acc)pl[RAD - d - 1][c][v], acc);
+                            acc = fma(az[d][1], (Acc)pl[RAD + d + 1][c][v], acc);
+                        }
                     } else {
                         // absent taps contribute nothing, also next to non-finite values
-                        acc = fma(a_c, (mask & 1u) ? (Acc)cu[c][v] : Acc(0), acc);
-                        acc = fma(a_xm, (mask & 2u) ? (Acc)xm : Acc(0), acc);
-                        acc = fma(a_xp, (mask & 4u) ? (Acc)xp : Acc(0), acc);
-                        acc = fma(a_ym, (mask & 8u) ? (Acc)ym[v] : Acc(0), acc);
-                        acc = fma(a_yp, (mask & 16u) ? (Acc)yp[v] : Acc(0), acc);
-                        acc = fma(a_zm, (mask & 32u) ? (Acc)dn[c][v] : Acc(0), acc);
-                        acc = fma(a_zp, (mask & 64u) ? (Acc)up[c][v] : Acc(0), acc);
+                        acc = fma(a_c, has(W_C) ? (Acc)pl[RAD][c][v] : Acc(0), acc);
+#pragma unroll
+                        for (int d = 0; d < RAD; ++d) {
+                            acc = fma(ax[d][0], has(w_slot(0, d + 1, -1)) ? (Acc)xval(v, -d - 1) : Acc(0), acc);
+                            acc = fma(ax[d][1], has(w_slot(0, d + 1, 1)) ? (Acc)xval(v, d + 1) : Acc(0), acc);
+                            acc = fma(ay[d][0], has(w_slot(1, d + 1, -1)) ? (Acc)ym[d][v] : Acc(0), acc);
+                            acc = fma(ay[d][1], has(w_slot(1, d + 1, 1)) ? (Acc)yp[d][v] : Acc(0), acc);
+                            acc = fma(az[d][0], has(w_slot(2, d + 1, -1)) ? (Acc)pl[RAD - d - 1][c][v] : Acc(0), acc);
+                            acc = fma(az[d][1], has(w_slot(2, d + 1, 1)) ? (Acc)pl[RAD + d + 1][c][v] : Acc(0), acc);
+                        }
                     }
                     o[c][v] = (T)acc;
                 }
@@ -303,9 +352,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
         }
 
         // Row checksum of the output (Eq.(3)), reduced across the row's lanes, and the row's
-        // x-boundary term of Theorem 1 from the input row (its first and last points and the
-        // ghosts).  Both go to a small LDS table; the prediction and the comparison for all
-        // planes of the tile run after the march, so none of their loads sits in this loop.
+        // x-boundary term of Theorem 1 from the input row (its first and last RAD points and
+        // the ghosts).  Both go to a small LDS table; the prediction and the comparison for
+        // all planes of the tile run after the march, so none of their loads sits in this loop.
         if constexpr (MODE != MODE_PLAIN) {
             double S;
             if constexpr (CS == CS_F64) {
@@ -326,14 +375,22 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             if (row_ok && sl == 0) tabS[r * a.tz + (z - z0)] = S;
         }
         if (keep_e && row_ok && sl == 0) {
-            const double uf = (double)row0[0], ul = (double)row0[nx - 1];
-            double gl, gr;  // G(-1), G(nx)
-            if (bc == ABFT_BC_CLAMP) { gl = uf; gr = ul; }
-            else if (bc == ABFT_BC_PERIODIC) { gl = ul; gr = uf; }
-            else { gl = (double)g; gr = (double)g; }
+            // shift dx < 0 reads G(dx .. -1) and drops u(nx+dx .. nx-1); dx > 0 reads
+            // G(nx .. nx+dx-1) and drops u(0 .. dx-1)
             double e = 0.0;
-            if (mask & 2u) e += a.st.w[W_XM] * (gl - ul);
-            if (mask & 4u) e += a.st.w[W_XP] * (gr - uf);
+#pragma unroll
+            for (int d = 1; d <= RAD; ++d) {
+                if (has(w_slot(0, d, -1))) {
+                    double b = 0.0;
+                    for (int q = 1; q <= d; ++q) b += (double)row0[-q] - (double)row0[nx - q];
+                    e += a.st.w[w_slot(0, d, -1)] * b;
+                }
+                if (has(w_slot(0, d, 1))) {
+                    double b = 0.0;
+                    for (int q = 0; q < d; ++q) b += (double)row0[nx + q] - (double)row0[q];
+                    e += a.st.w[w_slot(0, d, 1)] * b;
+                }
+            }
             tabE[r * a.tz + (z - z0)] = e;
         }
 
@@ -342,9 +399,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
         for (int c = 0; c < NCH; ++c)
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
-                dn[c][v] = cu[c][v];
-                cu[c][v] = up[c][v];
-                up[c][v] = nu[c][v];
+#pragma unroll
+                for (int q = 0; q < NP - 1; ++q) pl[q][c][v] = pl[q + 1][c][v];
+                pl[NP - 1][c][v] = nu[c][v];
                 cc[c][v] = nc[c][v];
                 if constexpr (PF > 1) {
                     nu[c][v] = nu2[c][v];
@@ -352,7 +409,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                 }
             }
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < NH; ++h)
 #pragma unroll
             for (int k = 0; k < HMAX; ++k)
 #pragma unroll
@@ -385,17 +442,27 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                     const bool first = pz == sl;
                     const double b0 = first ? pb0 : a.Bt[l];
                     double bp = first ? pcb : a.cB[l];
-                    if (mask & 1u) bp += a.st.w[W_C] * b0;
-                    if (mask & 2u) bp += a.st.w[W_XM] * b0;
-                    if (mask & 4u) bp += a.st.w[W_XP] * b0;
+                    if (has(W_C)) bp += a.st.w[W_C] * b0;
+#pragma unroll
+                    for (int d = 1; d <= RAD; ++d) {
+                        if (has(w_slot(0, d, -1))) bp += a.st.w[w_slot(0, d, -1)] * b0;
+                        if (has(w_slot(0, d, 1))) bp += a.st.w[w_slot(0, d, 1)] * b0;
+                    }
                     bp += tabE[r * a.tz + pz];
-                    if (mask & 8u) bp += a.st.w[W_YM] * (first ? pym : brow(z, y - 1));
-                    if (mask & 16u) bp += a.st.w[W_YP] * (first ? pyp : brow(z, y + 1));
-                    if (mask & 32u) bp += a.st.w[W_ZM] * (first ? pzm : brow(z - 1, y));
-                    if (mask & 64u) bp += a.st.w[W_ZP] * (first ? pzp : brow(z + 1, y));
+#pragma unroll
+                    for (int d = 1; d <= RAD; ++d) {
+                        if (has(w_slot(1, d, -1)))
+                            bp += a.st.w[w_slot(1, d, -1)] * (first ? pfy[d - 1][0] : brow(z, y - d));
+                        if (has(w_slot(1, d, 1)))
+                            bp += a.st.w[w_slot(1, d, 1)] * (first ? pfy[d - 1][1] : brow(z, y + d));
+                        if (has(w_slot(2, d, -1)))
+                            bp += a.st.w[w_slot(2, d, -1)] * (first ? pfz[d - 1][0] : brow(z - d, y));
+                        if (has(w_slot(2, d, 1)))
+                            bp += a.st.w[w_slot(2, d, 1)] * (first ? pfz[d - 1][1] : brow(z + d, y));
+                    }
                     // Section 3.4, written so that NaN and Inf mismatches are flagged
-                    const double d = fabs(S - bp);
-                    if (!(d <= a.eps * fabs(bp))) {
+                    const double dlt = fabs(S - bp);
+                    if (!(dlt <= a.eps * fabs(bp))) {
                         const unsigned i = atomicAdd(&a.slot->count, 1u);
                         if (i < (unsigned)kMaxFlags) {
                             RowFlag rf;
@@ -411,7 +478,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                         emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_ROW_FLAG, z, y, -1, S, bp,
                                    a.grid);
                     } else if (bp != 0.0) {
-                        noise = fmax(noise, d / fabs(bp));
+                        noise = fmax(noise, dlt / fabs(bp));
                     }
                 }
             }
@@ -420,7 +487,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
     if constexpr (MODE == MODE_PROT) record_noise(a.cnt, noise, nknown);
 }
 
-template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF, int NW>
+template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF, int NW, int RAD>
 __global__ void __launch_bounds__(NW * 64) sweep_kernel(const SweepArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -432,16 +499,16 @@ __global__ void __launch_bounds__(NW * 64) sweep_kernel(const SweepArgs a)
     // that neighbouring row blocks (which share halo rows) meet in the same L2.
     const int per = nt >> 3, rem = nt & 7, xcd = bid & 7, q = bid >> 3;
     const int tile = xcd * per + (xcd < rem ? xcd : rem) + q;
-    sweep_tile<T, MODE, CS, LPR, NCH, VEC, PF, NW>(a, tile, smem_raw);
+    sweep_tile<T, MODE, CS, LPR, NCH, VEC, PF, NW, RAD>(a, tile, smem_raw);
 }
 
-// Table of instantiated variants.
-template <typename T, int MODE, int CS>
+// Table of instantiated variants (radius 2: prefetch depth 1 only).
+template <typename T, int MODE, int CS, int RAD>
 hipError_t launch_sweep_t(const SweepShape& s, const SweepArgs& a, hipStream_t st, size_t lds)
 {
 #define ABFT_SWEEP_CASE_NW(LPR_, NCH_, VEC_, PF_, NW_)                                        \
     if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_ && s.pf == PF_ && s.nw == NW_) {       \
-        auto kern = sweep_kernel<T, MODE, CS, LPR_, NCH_, VEC_, PF_, NW_>;                     \
+        auto kern = sweep_kernel<T, MODE, CS, LPR_, NCH_, VEC_, PF_, NW_, RAD>;                \
         static int lds_set = 0;                                                                \
         if (lds > 65536 && (int)lds > lds_set) {                                               \
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),             \
@@ -453,17 +520,20 @@ hipError_t launch_sweep_t(const SweepShape& s, const SweepArgs& a, hipStream_t s
         hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(NW_ * 64), lds, st, a);                  \
         return hipGetLastError();                                                              \
     }
-// Blocks of 8 wavefronts only where a lane's share of a row is at most 64 bytes: with more,
-// the planes held in registers exceed the 256 registers a lane may have at that block size.
+// Blocks of 8 wavefronts only where a lane's share of a row is at most 64 bytes (32 for
+// radius 2, which holds five planes): with more, the planes held in registers exceed the 256
+// registers a lane may have at that block size.
 #define ABFT_SWEEP_CASE_PF(LPR_, NCH_, VEC_, PF_)                                              \
     ABFT_SWEEP_CASE_NW(LPR_, NCH_, VEC_, PF_, 4)                                               \
-    if constexpr (NCH_ * VEC_ * sizeof(T) <= kWideBlockLaneBytes) {                            \
+    if constexpr (NCH_ * VEC_ * sizeof(T) * RAD <= kWideBlockLaneBytes) {                      \
         ABFT_SWEEP_CASE_NW(LPR_, NCH_, VEC_, PF_, 8)                                           \
     }
 #define ABFT_SWEEP_CASE(LPR_, NCH_, VEC_) ABFT_SWEEP_CASE_PF(LPR_, NCH_, VEC_, 1)
     constexpr int VF = 16 / (int)sizeof(T);
-    ABFT_SWEEP_CASE_PF(64, 2, VF, 2)
-    ABFT_SWEEP_CASE_PF(64, 4, VF, 2)
+    if constexpr (RAD == 1) {
+        ABFT_SWEEP_CASE_PF(64, 2, VF, 2)
+        ABFT_SWEEP_CASE_PF(64, 4, VF, 2)
+    }
     ABFT_SWEEP_CASE(16, 1, VF)
     ABFT_SWEEP_CASE(16, 2, VF)
     ABFT_SWEEP_CASE(16, 4, VF)

@@ -6,8 +6,8 @@ namespace abft {
 hipError_t launch_recover_f32(int csum, const SweepShape& s, const RecoverArgs& r, size_t lds,
                               int num_cus, hipStream_t st)
 {
-    if (csum == CS_F32C) return launch_recover_t<float, CS_F32C>(s, r, lds, num_cus, st);
-    return launch_recover_t<float, CS_F64>(s, r, lds, num_cus, st);
+    if (csum == CS_F32C) return launch_recover_t<float, CS_F32C, 1>(s, r, lds, num_cus, st);
+    return launch_recover_t<float, CS_F64, 1>(s, r, lds, num_cus, st);
 }
 
 }  // namespace abft

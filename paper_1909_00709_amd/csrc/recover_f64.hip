@@ -7,7 +7,7 @@ hipError_t launch_recover_f64(int csum, const SweepShape& s, const RecoverArgs& 
                               int num_cus, hipStream_t st)
 {
     (void)csum;
-    return launch_recover_t<double, CS_F64>(s, r, lds, num_cus, st);
+    return launch_recover_t<double, CS_F64, 1>(s, r, lds, num_cus, st);
 }
 
 }  // namespace abft

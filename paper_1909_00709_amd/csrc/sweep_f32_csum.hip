@@ -7,8 +7,8 @@ hipError_t launch_sweep_f32_csum(int csum, const SweepShape& s, const SweepArgs&
                               size_t lds)
 {
     (void)csum;
-    if (csum == CS_F64) return launch_sweep_t<float, MODE_CSUM, CS_F64>(s, a, st, lds);
-    if (csum == CS_F32C) return launch_sweep_t<float, MODE_CSUM, CS_F32C>(s, a, st, lds);
+    if (csum == CS_F64) return launch_sweep_t<float, MODE_CSUM, CS_F64, 1>(s, a, st, lds);
+    if (csum == CS_F32C) return launch_sweep_t<float, MODE_CSUM, CS_F32C, 1>(s, a, st, lds);
     return hipErrorInvalidValue;
 }
 

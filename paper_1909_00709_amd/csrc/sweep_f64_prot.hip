@@ -7,7 +7,7 @@ hipError_t launch_sweep_f64_prot(int csum, const SweepShape& s, const SweepArgs&
                               size_t lds)
 {
     (void)csum;
-    if (csum == CS_F64) return launch_sweep_t<double, MODE_PROT, CS_F64>(s, a, st, lds);
+    if (csum == CS_F64) return launch_sweep_t<double, MODE_PROT, CS_F64, 1>(s, a, st, lds);
     return hipErrorInvalidValue;
 }
 

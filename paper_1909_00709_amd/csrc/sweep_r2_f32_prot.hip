@@ -1,0 +1,13 @@
+// Instantiations of the sweep kernel for radius-2 stars: float grid, protected variant.
+#include "abft_sweep.h"
+
+namespace abft {
+
+hipError_t launch_sweep_r2_f32_prot(int csum, const SweepShape& s, const SweepArgs& a,
+                                    hipStream_t st, size_t lds)
+{
+    if (csum == CS_F32C) return launch_sweep_t<float, MODE_PROT, CS_F32C, 2>(s, a, st, lds);
+    return launch_sweep_t<float, MODE_PROT, CS_F64, 2>(s, a, st, lds);
+}
+
+}  // namespace abft
