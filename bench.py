@@ -250,6 +250,52 @@ def bench_periods(stream, timed, u0, C, tune=True, prerun=300, nsweeps=640):
     return out
 
 
+# Fourth-order diffusion: u + 0.05 * (-u[-2] + 16 u[-1] - 30 u + 16 u[+1] - u[+2]) / 12 along
+# each axis, a 13-point star of radius 2.
+DIFF4_TAPS = tuple([(0, 0, 0, 1 - 3 * 0.05 * 30 / 12)] + [
+    tuple(int(v) for v in off) + (w,)
+    for ax in range(3) for d, w in ((1, 0.05 * 16 / 12), (2, -0.05 / 12)) for sg in (-1, 1)
+    for off in [[sg * d if i == ax else 0 for i in range(3)]]])
+
+
+def bench_radius2(stream, timed, u0, C, tune=True, k=10, steps=10):
+    """The 13-point radius-2 star on the large grid: plain sweep, protected sweep kernel,
+    online ABFT (graph) and offline windows of k, each autotuned."""
+    import torch
+
+    from paper_1909_00709_amd import abft
+
+    npts = u0.numel()
+    res = {"workload": f"13-point radius-2 star (fourth-order diffusion), {tuple(u0.shape)} fp32"}
+    for name, mode, kw in (("plain", "none", {}),
+                           ("prot_kernel", "online", dict(threshold=2e-7, auto_correct=False)),
+                           ("online", "online", dict(threshold=2e-7)),
+                           ("offline", "offline", dict(threshold=2e-6, period=k))):
+        with torch.cuda.stream(stream):
+            S = abft.Stencil(u0.clone(), DIFF4_TAPS, C=C, mode=mode, stream=stream, **kw)
+            if tune:
+                S.autotune()
+            if name == "online":
+                S.step_graph(k)
+                ms = timed(lambda: S.step_graph(k), steps) / k
+            else:
+                S.step(k)
+                ms = timed(lambda: S.step(k), steps) / k
+            rep, _ = S.check()
+            assert rep["rows_flagged"] == 0 and rep["windows_flagged"] == 0, (name, rep)
+            res[f"{name}_gpts"] = round(npts / (ms * 1e-3) / 1e9, 3)
+            res[f"{name}_ms_per_sweep"] = round(ms, 5)
+            res[f"{name}_shape"] = S.launch_shape()
+            if name != "plain":
+                res[f"{name}_noise"] = rep["max_noise"]
+            S.close()
+    res["plain_GBs"] = round(12.0 * npts / (res["plain_ms_per_sweep"] * 1e-3) / 1e9, 1)
+    for name in ("prot_kernel", "online", "offline"):
+        res[f"overhead_{name}_pct"] = round(
+            (res[f"{name}_ms_per_sweep"] / res["plain_ms_per_sweep"] - 1) * 100, 2)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,7 +307,7 @@ def main():
     ap.add_argument("--period", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["plain", "prot", "offline", "online", "batch", "configs",
-                                       "periods"],
+                                       "periods", "radius2"],
                     default=None,
                     help="run one measurement only (for profiler runs)")
     ap.add_argument("--no-tune", action="store_true",
@@ -392,6 +438,11 @@ def main():
     batch = None
     if args.only in (None, "batch"):
         batch = bench_batch(stream, timed, tune=not args.no_tune)
+
+    if args.only == "radius2":
+        print(json.dumps({"only": "radius2", "radius2": bench_radius2(stream, timed, u0, C,
+                                                                      tune=not args.no_tune)}))
+        return
 
     if args.only == "periods":
         print(json.dumps({"only": "periods", "periods": bench_periods(stream, timed, u0, C,

@@ -143,7 +143,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
 #pragma unroll
             for (int k = 0; k < HMAX; ++k) {
                 const int x = (tid + k * NT) * VEC;
-                if (x < nx && yy >= 0 && zz >= 0) {
+                if (x < nx && yy >= 0) {
                     V::load(uin + (size_t)zz * pstride + (size_t)yy * nx + x, d[h][k]);
                 } else {
 #pragma unroll
@@ -155,6 +155,21 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
     // Ghost values of one LDS row from the threads holding its first and last RAD points:
     // clamp repeats the edge value, periodic wraps, constant writes the ghost value.
     auto put_ghosts = [&](T* row, int x, const T (&d)[VEC]) {
+        if constexpr (RAD == 1) {
+            // the row's first and last points sit at the ends of the first and last chunks
+            // (a per-point form costs the radius-1 march some 80 scalar registers in spills)
+            if (x == 0) {
+                if (bc == ABFT_BC_CLAMP) row[-1] = d[0];
+                else if (bc == ABFT_BC_PERIODIC) row[nx] = d[0];
+                else { row[-1] = g; row[nx] = g; }
+            }
+            if (x + VEC == nx) {
+                if (bc == ABFT_BC_CLAMP) row[nx] = d[VEC - 1];
+                else if (bc == ABFT_BC_PERIODIC) row[-1] = d[VEC - 1];
+            }
+            return;
+        }
+        if (x >= RAD && x + VEC <= nx - RAD) return;  // no edge point in this chunk
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
             const int xv = x + v;
@@ -180,7 +195,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
 
     // The checksums the epilogue's prediction reads for this lane's first plane (its own
     // row's, the neighbouring rows' and the constant term's) are loaded now, so that their
-    // latency hides behind the march instead of adding to the end of every tile.
+    // latency hides behind the march instead of adding to the end of every tile.  Radius 2
+    // skips this: its five register planes leave no room for the ten values across the march
+    // (they would halve the wavefronts a SIMD can hold).
+    constexpr bool kPrefetch = RAD == 1;
     auto brow = [&](int z2, int y2) -> double {
         const int mz = map_coord(z2, nz, bc), my = map_coord(y2, ny, bc);
         if (mz < 0 || my < 0) return (double)nx * (double)g;
@@ -192,7 +210,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
     unsigned long long nknown = 0ull;
     if constexpr (MODE == MODE_PROT) {
         nknown = noise_known(a.cnt);
-        if (row_ok && sl < z1 - z0) {
+        if (kPrefetch && row_ok && sl < z1 - z0) {
             const int z = z0 + sl;
             const size_t l = (size_t)z * ny + y;
             pb0 = a.Bt[l];
@@ -439,7 +457,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                     // boundary term e of the input row, the y and z shifts read the
                     // neighbouring rows' checksums (loaded before the march for the first
                     // plane of the lane).
-                    const bool first = pz == sl;
+                    const bool first = kPrefetch && pz == sl;
                     const double b0 = first ? pb0 : a.Bt[l];
                     double bp = first ? pcb : a.cB[l];
                     if (has(W_C)) bp += a.st.w[W_C] * b0;
