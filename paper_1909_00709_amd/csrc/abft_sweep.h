@@ -155,34 +155,47 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
     // Ghost values of one LDS row from the threads holding its first and last RAD points:
     // clamp repeats the edge value, periodic wraps, constant writes the ghost value.
     auto put_ghosts = [&](T* row, int x, const T (&d)[VEC]) {
-        if constexpr (RAD == 1) {
-            // the row's first and last points sit at the ends of the first and last chunks
-            // (a per-point form costs the radius-1 march some 80 scalar registers in spills)
+        if constexpr (VEC >= RAD) {
+            // the row's first and last RAD points sit in its first and last chunks (testing
+            // chunk ends only: a per-point form costs the march some 80 scalar registers in
+            // spills)
             if (x == 0) {
-                if (bc == ABFT_BC_CLAMP) row[-1] = d[0];
-                else if (bc == ABFT_BC_PERIODIC) row[nx] = d[0];
-                else { row[-1] = g; row[nx] = g; }
+                if (bc == ABFT_BC_CLAMP) {
+#pragma unroll
+                    for (int q = 1; q <= RAD; ++q) row[-q] = d[0];
+                } else if (bc == ABFT_BC_PERIODIC) {
+#pragma unroll
+                    for (int q = 0; q < RAD; ++q) row[nx + q] = d[q];
+                } else {
+#pragma unroll
+                    for (int q = 1; q <= RAD; ++q) {
+                        row[-q] = g;
+                        row[nx - 1 + q] = g;
+                    }
+                }
             }
             if (x + VEC == nx) {
-                if (bc == ABFT_BC_CLAMP) row[nx] = d[VEC - 1];
-                else if (bc == ABFT_BC_PERIODIC) row[-1] = d[VEC - 1];
-            }
-            return;
-        }
-        if (x >= RAD && x + VEC <= nx - RAD) return;  // no edge point in this chunk
+                if (bc == ABFT_BC_CLAMP) {
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-            const int xv = x + v;
+                    for (int q = 0; q < RAD; ++q) row[nx + q] = d[VEC - 1];
+                } else if (bc == ABFT_BC_PERIODIC) {
+#pragma unroll
+                    for (int q = 1; q <= RAD; ++q) row[-q] = d[VEC - q];
+                }
+            }
+        } else {
+            // one point per chunk (VEC == 1): the points 0 .. RAD-1 and nx-RAD .. nx-1
+            const int xv = x;
             if (bc == ABFT_BC_CLAMP) {
                 if (xv == 0)
 #pragma unroll
-                    for (int q = 1; q <= RAD; ++q) row[-q] = d[v];
+                    for (int q = 1; q <= RAD; ++q) row[-q] = d[0];
                 if (xv == nx - 1)
 #pragma unroll
-                    for (int q = 0; q < RAD; ++q) row[nx + q] = d[v];
+                    for (int q = 0; q < RAD; ++q) row[nx + q] = d[0];
             } else if (bc == ABFT_BC_PERIODIC) {
-                if (xv >= nx - RAD) row[xv - nx] = d[v];
-                if (xv < RAD) row[xv + nx] = d[v];
+                if (xv >= nx - RAD) row[xv - nx] = d[0];
+                if (xv < RAD) row[xv + nx] = d[0];
             } else if (xv == 0) {
 #pragma unroll
                 for (int q = 1; q <= RAD; ++q) {
