@@ -1,0 +1,415 @@
+// The fused sweep for 27-point box stencils (every tap (dx, dy, dz) with offsets in -1..1),
+// with the row checksum (Eq.(3)), its prediction (Theorem 1) and the mismatch test
+// (Section 3.4) in the same pass.
+//
+// The decomposition is that of the star sweep (abft_sweep.h): a block of 4 wavefronts owns TY
+// whole rows of a slab of planes and marches along z, each row held by LPR lanes.  A box tap
+// reads the in-plane neighbours of planes z-1 and z+1 as well, so the block keeps a ring of
+// four LDS plane buffers, each with the block's rows, one halo row above and below and the
+// x-ghosts: at step z the planes z-1, z, z+1 are in three of them while plane z+2 is written
+// into the fourth (the buffer of plane z-2, which no wavefront reads any more once all have
+// passed the previous step's barrier), so one barrier per plane suffices.
+//
+// Theorem 1 for a box stencil: the row sum of the output row (z, y) is the constant term's
+// row sum plus, for every (dy, dz), the weight sum over dx times the input row sum of row
+// (z+dz, y+dy), plus the x-boundary terms of those nine rows (their ghost values minus the
+// points a shift drops), weighted by the dx = -1 and dx = +1 taps.  The nine rows are in LDS
+// at step z, so the boundary terms are formed in the march; the row sums of the input come
+// from the previous sweep's checksum plane in the epilogue.
+#pragma once
+
+#include "abft_sweep.h"
+
+namespace abft {
+
+template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int NW>
+__device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int tile,
+                                               unsigned char* smem_raw)
+{
+    using V = VecOps<T, VEC>;
+    constexpr int NT = NW * 64;
+    constexpr int RPW = 64 / LPR;
+    constexpr int TY = NW * RPW;
+    constexpr int SEGW = LPR * VEC;
+    constexpr int HMAX = (NCH * SEGW + NT * VEC - 1) / (NT * VEC);
+    constexpr int NB = 4;  // LDS plane buffers in the ring
+
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const int64_t t = a.t_off + (a.t_base != nullptr ? *a.t_base : 0);
+    const int nx = a.nx, ny = a.ny, nz = a.nz, bc = a.st.bc;
+    const T g = (T)a.st.g;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int seg = lane / LPR, sl = lane % LPR;
+    const int stride = nx + 2 * VEC;
+    const int plane_elems = (TY + 2) * stride;
+
+    const int yb = tile % a.nyb, zb = tile / a.nyb;
+    const int y0 = yb * TY, z0 = zb * a.tz;
+    const int z1 = min(z0 + a.tz, nz);
+    const int nrows = min(TY, ny - y0);
+    const int r = wave * RPW + seg;
+    const int y = y0 + r;
+    const bool row_ok = r < nrows;
+
+    const T* uin = static_cast<const T*>(a.uin);
+    T* uout = static_cast<T*>(a.uout);
+    const T* Cp = static_cast<const T*>(a.C);
+    const T cs = (T)a.c_scalar;
+    const size_t pstride = (size_t)nx * (size_t)ny;
+    const uint32_t bmask = a.st.bmask;
+    auto has = [&](int slot) { return (bmask >> slot) & 1u; };
+
+    int flo = 0, fhi = 0;
+    if (a.faults != nullptr && t >= 0 && t < a.fault_tmax) {
+        flo = a.fault_first[t];
+        fhi = a.fault_first[t + 1];
+    }
+    const int yh0 = map_coord(y0 - 1, ny, bc), yh1 = map_coord(y0 + nrows, ny, bc);
+    const int lh1 = nrows + 1;
+
+    T nu[NCH][VEC], cc[NCH][VEC], nc[NCH][VEC];
+    T hn[2][HMAX][VEC];
+
+    auto load_u = [&](T (&d)[NCH][VEC], int zz) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int x = c * SEGW + sl * VEC;
+            if (row_ok && x < nx) {
+                if (zz >= 0) {
+                    V::load(uin + (size_t)zz * pstride + (size_t)y * nx + x, d[c]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) d[c][v] = g;
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) d[c][v] = T(0);
+            }
+        }
+    };
+    auto load_c = [&](T (&d)[NCH][VEC], int zz) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int x = c * SEGW + sl * VEC;
+            if (row_ok && x < nx && Cp != nullptr) {
+                V::load_nt(Cp + (size_t)zz * pstride + (size_t)y * nx + x, d[c]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) d[c][v] = cs;
+            }
+        }
+    };
+    auto load_halo = [&](T (&d)[2][HMAX][VEC], int zz) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int yy = h ? yh1 : yh0;
+#pragma unroll
+            for (int k = 0; k < HMAX; ++k) {
+                const int x = (tid + k * NT) * VEC;
+                if (x < nx && yy >= 0 && zz >= 0) {
+                    V::load(uin + (size_t)zz * pstride + (size_t)yy * nx + x, d[h][k]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) d[h][k][v] = g;
+                }
+            }
+        }
+    };
+    auto put_ghosts = [&](T* row, int x, const T (&d)[VEC]) {
+        if (x == 0) {
+            if (bc == ABFT_BC_CLAMP) row[-1] = d[0];
+            else if (bc == ABFT_BC_PERIODIC) row[nx] = d[0];
+            else { row[-1] = g; row[nx] = g; }
+        }
+        if (x + VEC == nx) {
+            if (bc == ABFT_BC_CLAMP) row[nx] = d[VEC - 1];
+            else if (bc == ABFT_BC_PERIODIC) row[-1] = d[VEC - 1];
+        }
+    };
+    // Plane zz (its mapped index mz, or -1 for a plane of constant ghosts) into its buffer.
+    auto buf_of = [&](int zz) { return lds + (zz & (NB - 1)) * plane_elems; };
+    auto put_plane = [&](int zz, const T (&own)[NCH][VEC], const T (&hal)[2][HMAX][VEC]) {
+        T* buf = buf_of(zz);
+        if (row_ok) {
+            T* row = buf + (r + 1) * stride + VEC;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int x = c * SEGW + sl * VEC;
+                if (x < nx) {
+                    V::store(row + x, own[c]);
+                    put_ghosts(row, x, own[c]);
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            T* row = buf + (h ? lh1 : 0) * stride + VEC;
+#pragma unroll
+            for (int k = 0; k < HMAX; ++k) {
+                const int x = (tid + k * NT) * VEC;
+                if (x < nx) {
+                    V::store(row + x, hal[h][k]);
+                    put_ghosts(row, x, hal[h][k]);
+                }
+            }
+        }
+    };
+
+    // prologue: planes z0-1 and z0 into the ring, z0+1 in flight
+    {
+        T pu[NCH][VEC], ph[2][HMAX][VEC];
+        load_u(pu, map_coord(z0 - 1, nz, bc));
+        load_halo(ph, map_coord(z0 - 1, nz, bc));
+        put_plane(z0 - 1, pu, ph);
+        load_u(pu, z0);
+        load_halo(ph, z0);
+        put_plane(z0, pu, ph);
+    }
+    load_u(nu, map_coord(z0 + 1, nz, bc));
+    load_halo(hn, map_coord(z0 + 1, nz, bc));
+    load_c(cc, z0);
+
+    double* tabS = reinterpret_cast<double*>(smem_raw + (size_t)NB * plane_elems * sizeof(T));
+    double* tabE = tabS + TY * a.tz;
+    const bool keep_e = MODE == MODE_PROT || a.E != nullptr;
+    using Acc = T;
+
+    for (int z = z0; z < z1; ++z) {
+        put_plane(z + 1, nu, hn);
+        if (z + 1 < z1) {
+            load_u(nu, map_coord(z + 2, nz, bc));
+            load_halo(hn, map_coord(z + 2, nz, bc));
+            load_c(nc, z + 1);
+        }
+        __syncthreads();
+
+        const T* rows[3][3];  // [dz + 1][dy + 1]: the input rows around (z, y) in LDS
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+                rows[dz + 1][dy + 1] = buf_of(z + dz) + (r + 1 + dy) * stride + VEC;
+
+        T o[NCH][VEC];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int x = c * SEGW + sl * VEC;
+            if (row_ok && x < nx) {
+                Acc acc[VEC];
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc[v] = (Acc)cc[c][v];
+                // taps in the order dz, dy, dx (absent taps contribute nothing, also next to
+                // non-finite values)
+#pragma unroll
+                for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+                    for (int dy = -1; dy <= 1; ++dy) {
+                        const T* rw = rows[dz + 1][dy + 1];
+                        T m[VEC];
+                        V::load(rw + x, m);
+                        const T xl = rw[x - 1], xr = rw[x + VEC];
+#pragma unroll
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int sl_ = box_slot(dx, dy, dz);
+                            const Acc wv = (Acc)a.st.wb[sl_];
+                            const bool on = has(sl_);
+#pragma unroll
+                            for (int v = 0; v < VEC; ++v) {
+                                const int idx = v + dx;
+                                const T val = idx < 0 ? xl : (idx >= VEC ? xr : m[idx]);
+                                acc[v] = fma(wv, on ? (Acc)val : Acc(0), acc[v]);
+                            }
+                        }
+                    }
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) o[c][v] = (T)acc[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) o[c][v] = T(0);
+            }
+        }
+
+        // Fault model of Section 5.1 (as in the star sweep).
+        for (int f = flo; f < fhi; ++f) {
+            const abft_fault F = a.faults[f];
+            if (F.attempt == a.attempt && F.grid == a.grid && F.z == z && F.y == y && row_ok) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v)
+                        if (c * SEGW + sl * VEC + v == F.x) {
+                            if constexpr (sizeof(T) == 4) {
+                                o[c][v] = __builtin_bit_cast(
+                                    T, __builtin_bit_cast(uint32_t, o[c][v]) ^ (1u << F.bit));
+                            } else {
+                                o[c][v] = __builtin_bit_cast(
+                                    T, __builtin_bit_cast(uint64_t, o[c][v]) ^ (1ull << F.bit));
+                            }
+                        }
+            }
+        }
+
+        if (row_ok) {
+            T* dst = uout + (size_t)z * pstride + (size_t)y * nx;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int x = c * SEGW + sl * VEC;
+                if (x < nx) V::store_nt(dst + x, o[c]);
+            }
+        }
+
+        if constexpr (MODE != MODE_PLAIN) {
+            double S;
+            if constexpr (CS == CS_F64) {
+                double p = 0.0;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) p += (double)o[c][v];
+                S = segment_total<LPR>(row16_sum(p));
+            } else {
+                CPair p{0.f, 0.f};
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) p = cpair_add1(p, (float)o[c][v]);
+                S = segment_total<LPR>(row16_pair(p));
+            }
+            if (row_ok && sl == 0) tabS[r * a.tz + (z - z0)] = S;
+        }
+        if (keep_e && row_ok && sl == 0) {
+            // x-boundary terms of the nine input rows around (z, y): a shift dx = -1 reads
+            // G(-1) and drops u(nx-1); dx = +1 reads G(nx) and drops u(0)
+            double e = 0.0;
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const T* rw = rows[dz + 1][dy + 1];
+                    const int sm = box_slot(-1, dy, dz), sp = box_slot(1, dy, dz);
+                    if (has(sm)) e += a.st.wb[sm] * ((double)rw[-1] - (double)rw[nx - 1]);
+                    if (has(sp)) e += a.st.wb[sp] * ((double)rw[nx] - (double)rw[0]);
+                }
+            tabE[r * a.tz + (z - z0)] = e;
+        }
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) cc[c][v] = nc[c][v];
+    }
+
+    if constexpr (MODE == MODE_PLAIN) {
+        if (a.E == nullptr) return;
+    }
+    __syncthreads();
+    auto brow = [&](int z2, int y2) -> double {
+        const int mz = map_coord(z2, nz, bc), my = map_coord(y2, ny, bc);
+        if (mz < 0 || my < 0) return (double)nx * (double)g;
+        return a.Bt[(size_t)mz * ny + my];
+    };
+    const int nzt = z1 - z0;
+    double noise = 0.0;
+    unsigned long long nknown = 0ull;
+    if constexpr (MODE == MODE_PROT) nknown = noise_known(a.cnt);
+    if (row_ok) {
+        for (int pz = sl; pz < nzt; pz += LPR) {
+            const int z = z0 + pz;
+            const size_t l = (size_t)z * ny + y;
+            if (a.E != nullptr) a.E[l] = tabE[r * a.tz + pz];
+            if constexpr (MODE != MODE_PLAIN) {
+                const double S = tabS[r * a.tz + pz];
+                a.Bn[l] = S;
+                if constexpr (MODE == MODE_PROT) {
+                    // Theorem 1 for the box: the weight sums over dx times the nine input
+                    // row sums, plus the boundary terms formed in the march
+                    double bp = a.cB[l] + tabE[r * a.tz + pz];
+#pragma unroll
+                    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+                        for (int dy = -1; dy <= 1; ++dy) {
+                            double wsum = 0.0;
+                            bool any = false;
+#pragma unroll
+                            for (int dx = -1; dx <= 1; ++dx) {
+                                const int sl_ = box_slot(dx, dy, dz);
+                                if (has(sl_)) {
+                                    wsum += a.st.wb[sl_];
+                                    any = true;
+                                }
+                            }
+                            if (any) bp += wsum * brow(z + dz, y + dy);
+                        }
+                    const double dlt = fabs(S - bp);
+                    if (!(dlt <= a.eps * fabs(bp))) {
+                        const unsigned i = atomicAdd(&a.slot->count, 1u);
+                        if (i < (unsigned)kMaxFlags) {
+                            RowFlag rf;
+                            rf.z = z;
+                            rf.y = y;
+                            rf.direct = S;
+                            rf.pred = bp;
+                            a.slot->rows[i] = rf;
+                        } else {
+                            atomicAdd(&a.cnt->overflow, 1ull);
+                        }
+                        atomicAdd(&a.cnt->rows_flagged, 1ull);
+                        emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_ROW_FLAG, z, y, -1, S, bp,
+                                   a.grid);
+                    } else if (bp != 0.0) {
+                        noise = fmax(noise, dlt / fabs(bp));
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (MODE == MODE_PROT) record_noise(a.cnt, noise, nknown);
+}
+
+template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int NW>
+__global__ void __launch_bounds__(NW * 64) sweep_box_kernel(const SweepArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    if (a.guard != nullptr && *a.guard == 0u) return;
+    const int nt = a.ntiles, bid = blockIdx.x;
+    if (a.zero_ptr != nullptr && bid == 0 && (int)threadIdx.x < a.zero_n)
+        a.zero_ptr[threadIdx.x] = 0u;
+    const int per = nt >> 3, rem = nt & 7, xcd = bid & 7, q = bid >> 3;
+    const int tile = xcd * per + (xcd < rem ? xcd : rem) + q;
+    sweep_box_tile<T, MODE, CS, LPR, NCH, VEC, NW>(a, tile, smem_raw);
+}
+
+// Table of instantiated box variants (blocks of 4 wavefronts, prefetch depth 1).
+template <typename T, int MODE, int CS>
+hipError_t launch_sweep_box_t(const SweepShape& s, const SweepArgs& a, hipStream_t st,
+                              size_t lds)
+{
+#define ABFT_BOX_CASE(LPR_, NCH_, VEC_)                                                        \
+    if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_ && s.nw == 4) {                        \
+        auto kern = sweep_box_kernel<T, MODE, CS, LPR_, NCH_, VEC_, 4>;                        \
+        static int lds_set = 0;                                                                \
+        if (lds > 65536 && (int)lds > lds_set) {                                               \
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),             \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,      \
+                                               (int)lds);                                      \
+            if (e != hipSuccess) return e;                                                     \
+            lds_set = (int)lds;                                                                \
+        }                                                                                      \
+        hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(256), lds, st, a);                       \
+        return hipGetLastError();                                                              \
+    }
+    constexpr int VF = 16 / (int)sizeof(T);
+    ABFT_BOX_CASE(16, 1, VF)
+    ABFT_BOX_CASE(16, 2, VF)
+    ABFT_BOX_CASE(16, 4, VF)
+    ABFT_BOX_CASE(64, 1, VF)
+    ABFT_BOX_CASE(64, 2, VF)
+    ABFT_BOX_CASE(64, 4, VF)
+    ABFT_BOX_CASE(64, 8, VF)
+    ABFT_BOX_CASE(64, 4, 1)
+    ABFT_BOX_CASE(64, 16, 1)
+#undef ABFT_BOX_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace abft

@@ -33,12 +33,21 @@ __host__ __device__ constexpr int w_slot(int axis, int d, int sign)
     return (d == 1 ? W_XM : W_XM2) + 2 * axis + (sign > 0 ? 1 : 0);
 }
 
+// Slot of tap (dx, dy, dz), each in -1..1, of a 27-point box stencil.
+__host__ __device__ constexpr int box_slot(int dx, int dy, int dz)
+{
+    return (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+}
+
 struct Stencil {
-    double w[W_COUNT];  // weights rounded to the grid dtype, held as double
+    double w[W_COUNT];  // star weights rounded to the grid dtype, held as double
     uint32_t mask;      // bit k set when slot k is a tap of the stencil
     int32_t bc;         // abft_bc
     double g;           // constant ghost value (rounded to the grid dtype)
     int32_t rad;        // 1, or 2 when a distance-2 tap is present
+    int32_t box;        // 1: a 27-point box stencil (taps off the axes); weights in wb
+    double wb[27];      // box weights by box_slot (box stencils only)
+    uint32_t bmask;     // bit box_slot set for each box tap
     int32_t pad;
 };
 
@@ -199,6 +208,7 @@ struct SweepShape {
     int32_t pf;    // planes loaded ahead of the one computed: 1 or 2
     int32_t nw = 4;  // wavefronts per block: 4 or 8 (each holds 64 / lpr rows)
     int32_t rad = 1; // stencil radius the kernel is built for: 1 or 2
+    int32_t box = 0; // 1: the 27-point box kernel (radius 1, blocks of 4 wavefronts)
 };
 
 bool sweep_shape_supported(int dtype, const SweepShape& s);
@@ -214,7 +224,7 @@ hipError_t launch_sweep_batch(int dtype, int mode, int csum, const SweepShape& s
                               const BatchArgs& b, int nblocks, size_t lds, hipStream_t st);
 size_t batch_lds_bytes(int dtype, int maxnx, int maxtz, const SweepShape& s);
 int batch_blocks_per_cu(int dtype, int mode, int csum, const SweepShape& s, size_t lds);
-size_t fixup_lds_bytes(int nx);
+size_t fixup_lds_bytes(int nx, bool box);
 hipError_t launch_check(const CheckArgs& a, hipStream_t st);
 size_t check_lds_bytes(int ry, int rz);
 hipError_t launch_row_sums(int dtype, const void* u, double cs, int nx, int64_t nrows,
@@ -237,6 +247,16 @@ hipError_t launch_recover_r2_f32(int csum, const SweepShape& s, const RecoverArg
                                  int num_cus, hipStream_t st);
 hipError_t launch_recover_r2_f64(int csum, const SweepShape& s, const RecoverArgs& r, size_t lds,
                                  int num_cus, hipStream_t st);
+hipError_t launch_recover_box_f32(int csum, const SweepShape& s, const RecoverArgs& r,
+                                  size_t lds, int num_cus, hipStream_t st);
+hipError_t launch_recover_box_f64(int csum, const SweepShape& s, const RecoverArgs& r,
+                                  size_t lds, int num_cus, hipStream_t st);
+
+// Box (27-point) sweep launchers (blocks of 4 wavefronts, prefetch depth 1).
+hipError_t launch_sweep_box_f32(int mode, int csum, const SweepShape& s, const SweepArgs& a,
+                                hipStream_t st, size_t lds);
+hipError_t launch_sweep_box_f64(int mode, int csum, const SweepShape& s, const SweepArgs& a,
+                                hipStream_t st, size_t lds);
 
 // Radius-2 sweep launchers (prefetch depth 1).
 hipError_t launch_sweep_r2_f32_pc(int mode, int csum, const SweepShape& s, const SweepArgs& a,

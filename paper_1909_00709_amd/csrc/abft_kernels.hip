@@ -28,7 +28,7 @@ __device__ double block_sum(double v, double* red)
 // correction of the intersections (Eq.(10), with the partial sum over the other points taken
 // directly).  Exits at once when nothing was flagged.
 // ------------------------------------------------------------------------------------------
-template <typename T, int RAD>
+template <typename T, int RAD, int BOX>
 __device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* red, int& sh_K)
 {
     FlagSlot* slot = a.slot;
@@ -41,6 +41,10 @@ __device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* re
     double* An = Ap + nx;
     int* cflag = reinterpret_cast<int*>(An + nx);
     int* xs = cflag + nx;
+    // box stencils: column sums and first / last points of the input layers z-1, z, z+1
+    double* A3 = reinterpret_cast<double*>(xs + nx);  // [3][nx]
+    double* F3 = A3 + 3 * nx;
+    double* L3 = F3 + 3 * nx;
 
     const int tid = threadIdx.x;
     const int64_t t = a.t_off + (a.t_base != nullptr ? *a.t_base : 0);
@@ -81,95 +85,156 @@ __device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* re
         int j = i;
         while (j < n && slot->rows[j].z == z) ++j;
         const int R = j - i;
-        // layers z - d and z + d for d = 1 .. RAD (mapped by the boundary rule)
-        int zl[RAD][2];
+        if constexpr (BOX) {
+            // column sums and end points of the input layers z-1, z, z+1 (mapped), and the
+            // output layer's column sums
+            for (int x = tid; x < nx; x += kFixBlock) {
 #pragma unroll
-        for (int d = 0; d < RAD; ++d) {
-            zl[d][0] = map_coord(z - d - 1, nz, bc);
-            zl[d][1] = map_coord(z + d + 1, nz, bc);
-        }
-
-        // column checksums of the layer (input: z and its z-neighbours; output: z), and the
-        // first and last RAD points of each input column (the y-boundary terms)
-        double s_z[RAD][2][kFixXPT], u_f[RAD][kFixXPT], u_l[RAD][kFixXPT];
-#pragma unroll
-        for (int k = 0; k < kFixXPT; ++k) {
-            const int x = tid + k * kFixBlock;
-#pragma unroll
-            for (int d = 0; d < RAD; ++d) s_z[d][0][k] = s_z[d][1][k] = u_f[d][k] = u_l[d][k] = 0.0;
-            if (x < nx) {
-                double sz = 0.0, sn = 0.0, sl[RAD][2];
-#pragma unroll
-                for (int d = 0; d < RAD; ++d) sl[d][0] = sl[d][1] = 0.0;
-#pragma unroll 4
-                for (int yy = 0; yy < ny; ++yy) {
-                    const size_t o = (size_t)yy * nx + x;
-                    sz += (double)uin[(size_t)z * ps + o];
-#pragma unroll
-                    for (int d = 0; d < RAD; ++d)
-#pragma unroll
-                        for (int sg = 0; sg < 2; ++sg)
-                            if (zl[d][sg] >= 0) sl[d][sg] += (double)uin[(size_t)zl[d][sg] * ps + o];
-                    sn += (double)uout[(size_t)z * ps + o];
+                for (int dz = -1; dz <= 1; ++dz) {
+                    const int mz = map_coord(z + dz, nz, bc);
+                    double sacc = 0.0, f = gd, l = gd;
+                    if (mz >= 0) {
+                        const T* col = uin + (size_t)mz * ps + x;
+                        for (int yy = 0; yy < ny; ++yy) sacc += (double)col[(size_t)yy * nx];
+                        f = (double)col[0];
+                        l = (double)col[(size_t)(ny - 1) * nx];
+                    } else {
+                        sacc = (double)ny * gd;
+                    }
+                    A3[(dz + 1) * nx + x] = sacc;
+                    F3[(dz + 1) * nx + x] = f;
+                    L3[(dz + 1) * nx + x] = l;
                 }
-                At[x] = sz;
+                double sn = 0.0;
+                for (int yy = 0; yy < ny; ++yy) sn += (double)uout[(size_t)z * ps + (size_t)yy * nx + x];
                 An[x] = sn;
-#pragma unroll
-                for (int d = 0; d < RAD; ++d) {
-#pragma unroll
-                    for (int sg = 0; sg < 2; ++sg)
-                        s_z[d][sg][k] = zl[d][sg] >= 0 ? sl[d][sg] : (double)ny * gd;
-                    const int yf = d < ny ? d : ny - 1, yl = ny - 1 - d >= 0 ? ny - 1 - d : 0;
-                    u_f[d][k] = (double)uin[(size_t)z * ps + (size_t)yf * nx + x];
-                    u_l[d][k] = (double)uin[(size_t)z * ps + (size_t)yl * nx + x];
-                }
             }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kFixXPT; ++k) {
-            const int x = tid + k * kFixBlock;
-            if (x < nx) {
-                const double a0 = At[x];
-                // G of the column at y = -q and y = ny - 1 + q (q = 1 .. RAD)
-                auto g_lo = [&](int q) -> double {
-                    if (bc == ABFT_BC_CLAMP) return u_f[0][k];
-                    if (bc == ABFT_BC_PERIODIC) return u_l[q - 1][k];
-                    return gd;
-                };
-                auto g_hi = [&](int q) -> double {
-                    if (bc == ABFT_BC_CLAMP) return u_l[0][k];
-                    if (bc == ABFT_BC_PERIODIC) return u_f[q - 1][k];
-                    return gd;
-                };
-                auto acol = [&](int xx) -> double {
-                    const int mx = map_coord(xx, nx, bc);
-                    return mx < 0 ? (double)ny * gd : At[mx];
-                };
+            __syncthreads();
+            for (int x = tid; x < nx; x += kFixBlock) {
                 double ap = a.cA[(size_t)z * nx + x];
-                if (mask & (1u << W_C)) ap += a.st.w[W_C] * a0;
 #pragma unroll
-                for (int d = 1; d <= RAD; ++d) {
-                    if (mask & (1u << w_slot(0, d, -1))) ap += a.st.w[w_slot(0, d, -1)] * acol(x - d);
-                    if (mask & (1u << w_slot(0, d, 1))) ap += a.st.w[w_slot(0, d, 1)] * acol(x + d);
-                    // shift dy = -d reads G(-d .. -1) and drops the last d points; dy = +d
-                    // reads G(ny .. ny+d-1) and drops the first d points
-                    if (mask & (1u << w_slot(1, d, -1))) {
-                        double b = 0.0;
-                        for (int q = 1; q <= d; ++q) b += g_lo(q) - u_l[q - 1][k];
-                        ap += a.st.w[w_slot(1, d, -1)] * (a0 + b);
+                for (int dz = -1; dz <= 1; ++dz) {
+                    const bool zin = map_coord(z + dz, nz, bc) >= 0;
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int mx = map_coord(x + dx, nx, bc);
+                        const bool in = zin && mx >= 0;
+                        const double acol = in ? A3[(dz + 1) * nx + mx] : (double)ny * gd;
+                        // y-boundary terms of the column: dy = -1 reads G(-1) and drops
+                        // u(ny-1), dy = +1 reads G(ny) and drops u(0); a column of constant
+                        // ghosts has none
+                        double gm = 0.0, gp = 0.0;
+                        if (in) {
+                            const double f = F3[(dz + 1) * nx + mx], l = L3[(dz + 1) * nx + mx];
+                            const double glo = bc == ABFT_BC_CLAMP ? f : (bc == ABFT_BC_PERIODIC ? l : gd);
+                            const double ghi = bc == ABFT_BC_CLAMP ? l : (bc == ABFT_BC_PERIODIC ? f : gd);
+                            gm = glo - l;
+                            gp = ghi - f;
+                        }
+#pragma unroll
+                        for (int dy = -1; dy <= 1; ++dy) {
+                            const int sl_ = box_slot(dx, dy, dz);
+                            if (!((a.st.bmask >> sl_) & 1u)) continue;
+                            const double w = a.st.wb[sl_];
+                            ap += w * (acol + (dy < 0 ? gm : (dy > 0 ? gp : 0.0)));
+                        }
                     }
-                    if (mask & (1u << w_slot(1, d, 1))) {
-                        double b = 0.0;
-                        for (int q = 1; q <= d; ++q) b += g_hi(q) - u_f[q - 1][k];
-                        ap += a.st.w[w_slot(1, d, 1)] * (a0 + b);
-                    }
-                    if (mask & (1u << w_slot(2, d, -1))) ap += a.st.w[w_slot(2, d, -1)] * s_z[d - 1][0][k];
-                    if (mask & (1u << w_slot(2, d, 1))) ap += a.st.w[w_slot(2, d, 1)] * s_z[d - 1][1][k];
                 }
                 Ap[x] = ap;
                 const double dd = fabs(An[x] - ap);
                 cflag[x] = !(dd <= a.eps * fabs(ap));
+            }
+        } else {
+            // layers z - d and z + d for d = 1 .. RAD (mapped by the boundary rule)
+            int zl[RAD][2];
+    #pragma unroll
+            for (int d = 0; d < RAD; ++d) {
+                zl[d][0] = map_coord(z - d - 1, nz, bc);
+                zl[d][1] = map_coord(z + d + 1, nz, bc);
+            }
+
+            // column checksums of the layer (input: z and its z-neighbours; output: z), and the
+            // first and last RAD points of each input column (the y-boundary terms)
+            double s_z[RAD][2][kFixXPT], u_f[RAD][kFixXPT], u_l[RAD][kFixXPT];
+    #pragma unroll
+            for (int k = 0; k < kFixXPT; ++k) {
+                const int x = tid + k * kFixBlock;
+    #pragma unroll
+                for (int d = 0; d < RAD; ++d) s_z[d][0][k] = s_z[d][1][k] = u_f[d][k] = u_l[d][k] = 0.0;
+                if (x < nx) {
+                    double sz = 0.0, sn = 0.0, sl[RAD][2];
+    #pragma unroll
+                    for (int d = 0; d < RAD; ++d) sl[d][0] = sl[d][1] = 0.0;
+    #pragma unroll 4
+                    for (int yy = 0; yy < ny; ++yy) {
+                        const size_t o = (size_t)yy * nx + x;
+                        sz += (double)uin[(size_t)z * ps + o];
+    #pragma unroll
+                        for (int d = 0; d < RAD; ++d)
+    #pragma unroll
+                            for (int sg = 0; sg < 2; ++sg)
+                                if (zl[d][sg] >= 0) sl[d][sg] += (double)uin[(size_t)zl[d][sg] * ps + o];
+                        sn += (double)uout[(size_t)z * ps + o];
+                    }
+                    At[x] = sz;
+                    An[x] = sn;
+    #pragma unroll
+                    for (int d = 0; d < RAD; ++d) {
+    #pragma unroll
+                        for (int sg = 0; sg < 2; ++sg)
+                            s_z[d][sg][k] = zl[d][sg] >= 0 ? sl[d][sg] : (double)ny * gd;
+                        const int yf = d < ny ? d : ny - 1, yl = ny - 1 - d >= 0 ? ny - 1 - d : 0;
+                        u_f[d][k] = (double)uin[(size_t)z * ps + (size_t)yf * nx + x];
+                        u_l[d][k] = (double)uin[(size_t)z * ps + (size_t)yl * nx + x];
+                    }
+                }
+            }
+            __syncthreads();
+    #pragma unroll
+            for (int k = 0; k < kFixXPT; ++k) {
+                const int x = tid + k * kFixBlock;
+                if (x < nx) {
+                    const double a0 = At[x];
+                    // G of the column at y = -q and y = ny - 1 + q (q = 1 .. RAD)
+                    auto g_lo = [&](int q) -> double {
+                        if (bc == ABFT_BC_CLAMP) return u_f[0][k];
+                        if (bc == ABFT_BC_PERIODIC) return u_l[q - 1][k];
+                        return gd;
+                    };
+                    auto g_hi = [&](int q) -> double {
+                        if (bc == ABFT_BC_CLAMP) return u_l[0][k];
+                        if (bc == ABFT_BC_PERIODIC) return u_f[q - 1][k];
+                        return gd;
+                    };
+                    auto acol = [&](int xx) -> double {
+                        const int mx = map_coord(xx, nx, bc);
+                        return mx < 0 ? (double)ny * gd : At[mx];
+                    };
+                    double ap = a.cA[(size_t)z * nx + x];
+                    if (mask & (1u << W_C)) ap += a.st.w[W_C] * a0;
+    #pragma unroll
+                    for (int d = 1; d <= RAD; ++d) {
+                        if (mask & (1u << w_slot(0, d, -1))) ap += a.st.w[w_slot(0, d, -1)] * acol(x - d);
+                        if (mask & (1u << w_slot(0, d, 1))) ap += a.st.w[w_slot(0, d, 1)] * acol(x + d);
+                        // shift dy = -d reads G(-d .. -1) and drops the last d points; dy = +d
+                        // reads G(ny .. ny+d-1) and drops the first d points
+                        if (mask & (1u << w_slot(1, d, -1))) {
+                            double b = 0.0;
+                            for (int q = 1; q <= d; ++q) b += g_lo(q) - u_l[q - 1][k];
+                            ap += a.st.w[w_slot(1, d, -1)] * (a0 + b);
+                        }
+                        if (mask & (1u << w_slot(1, d, 1))) {
+                            double b = 0.0;
+                            for (int q = 1; q <= d; ++q) b += g_hi(q) - u_f[q - 1][k];
+                            ap += a.st.w[w_slot(1, d, 1)] * (a0 + b);
+                        }
+                        if (mask & (1u << w_slot(2, d, -1))) ap += a.st.w[w_slot(2, d, -1)] * s_z[d - 1][0][k];
+                        if (mask & (1u << w_slot(2, d, 1))) ap += a.st.w[w_slot(2, d, 1)] * s_z[d - 1][1][k];
+                    }
+                    Ap[x] = ap;
+                    const double dd = fabs(An[x] - ap);
+                    cflag[x] = !(dd <= a.eps * fabs(ap));
+                }
             }
         }
         __syncthreads();
@@ -245,13 +310,13 @@ __device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* re
     if (tid == 0) slot->count = 0u;
 }
 
-template <typename T, int RAD>
+template <typename T, int RAD, int BOX>
 __global__ void __launch_bounds__(kFixBlock) fixup_kernel(const FixArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ double red[kFixBlock / 64];
     __shared__ int sh_K;
-    fixup_body<T, RAD>(a, smem_raw, red, sh_K);
+    fixup_body<T, RAD, BOX>(a, smem_raw, red, sh_K);
 }
 
 // One block per grid of a batch; each exits at once unless its grid flagged a row.
@@ -282,7 +347,7 @@ __global__ void __launch_bounds__(kFixBlock) fixup_batch_kernel(const BatchArgs 
     a.grid = g;
     a.t_base = b.t_base;
     a.t_off = b.t_off;
-    fixup_body<T, 1>(a, smem_raw, red, sh_K);
+    fixup_body<T, 1, 0>(a, smem_raw, red, sh_K);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -293,11 +358,24 @@ __global__ void __launch_bounds__(kFixBlock) fixup_batch_kernel(const BatchArgs 
 // steps: all k of a window up to kCheckChunk, else the window's steps in chunks, each but the
 // last writing its tiles' interiors to an intermediate plane.
 // ------------------------------------------------------------------------------------------
-template <int RAD>
+// Neighbours of a checksum-plane cell under the collapsed stencil: (dy, dz) offsets of the
+// k-th neighbour, for a star of radius RAD (4 * RAD neighbours) or a box (8).
+__device__ constexpr int nb_count(int rad, int box) { return box ? 8 : 4 * rad; }
+__device__ constexpr int nb_dy(int k, int box)
+{
+    return box ? ((k < 4 ? k : k + 1) % 3) - 1 : ((k & 3) == 0 ? -(k / 4 + 1) : (k & 3) == 1 ? k / 4 + 1 : 0);
+}
+__device__ constexpr int nb_dz(int k, int box)
+{
+    return box ? ((k < 4 ? k : k + 1) / 3) - 1 : ((k & 3) == 2 ? -(k / 4 + 1) : (k & 3) == 3 ? k / 4 + 1 : 0);
+}
+
+template <int RAD, int BOX>
 __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     if (a.guard != nullptr && *a.guard == 0u) return;
+    constexpr int NN = nb_count(RAD, BOX);
 
     const int nx = a.nx, ny = a.ny, nz = a.nz, bc = a.st.bc, k = a.ns, hal = RAD * a.ns;
     const bool per = bc == ABFT_BC_PERIODIC;
@@ -320,16 +398,29 @@ __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
 
     auto wrap = [](int c, int n) { const int m = c % n; return m < 0 ? m + n : m; };
     auto wt = [&](int slot) { return ((mask >> slot) & 1u) ? a.st.w[slot] : 0.0; };
+    auto wbox = [&](int dy, int dz) {  // the box weights of a (dy, dz) row, summed over dx
+        double s = 0.0;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int sl = box_slot(dx, dy, dz);
+            if ((a.st.bmask >> sl) & 1u) s += a.st.wb[sl];
+        }
+        return s;
+    };
     // the x taps collapse onto the row itself (their boundary terms come from E)
-    double wx = wt(W_C);
-    double wy[RAD][2], wz[RAD][2];
+    double wx, wn[NN];
+    if constexpr (BOX) {
+        wx = wbox(0, 0);
 #pragma unroll
-    for (int d = 0; d < RAD; ++d) {
-        wx += wt(w_slot(0, d + 1, -1)) + wt(w_slot(0, d + 1, 1));
+        for (int n = 0; n < NN; ++n) wn[n] = wbox(nb_dy(n, 1), nb_dz(n, 1));
+    } else {
+        wx = wt(W_C);
 #pragma unroll
-        for (int sg = 0; sg < 2; ++sg) {
-            wy[d][sg] = wt(w_slot(1, d + 1, sg ? 1 : -1));
-            wz[d][sg] = wt(w_slot(2, d + 1, sg ? 1 : -1));
+        for (int d = 0; d < RAD; ++d) {
+            wx += wt(w_slot(0, d + 1, -1)) + wt(w_slot(0, d + 1, 1));
+            wn[4 * d + 0] = wt(w_slot(1, d + 1, -1));
+            wn[4 * d + 1] = wt(w_slot(1, d + 1, 1));
+            wn[4 * d + 2] = wt(w_slot(2, d + 1, -1));
+            wn[4 * d + 3] = wt(w_slot(2, d + 1, 1));
         }
     }
 
@@ -338,16 +429,14 @@ __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
     // of constant ghosts (sum nx * g); a neighbour outside the loaded region points at the
     // cell itself (its value only reaches cells outside the tile).
     double cbv[kCheckCells];
-    int gl[kCheckCells], nby[kCheckCells][RAD][2], nbz[kCheckCells][RAD][2];
+    int gl[kCheckCells], nb[kCheckCells][NN];
 #pragma unroll
     for (int q = 0; q < kCheckCells; ++q) {
         const int i = tid + q * kCheckBlock;
         cbv[q] = 0.0;
         gl[q] = 0;
 #pragma unroll
-        for (int d = 0; d < RAD; ++d)
-#pragma unroll
-            for (int sg = 0; sg < 2; ++sg) nby[q][d][sg] = nbz[q][d][sg] = i < NC ? i : 0;
+        for (int n = 0; n < NN; ++n) nb[q][n] = i < NC ? i : 0;
         if (i < NC) {
             const int yy = ry0 + i % RY, zz = rz0 + i / RY;
             const int gy = per ? wrap(yy, ny) : yy, gz = per ? wrap(zz, nz) : zz;
@@ -365,12 +454,7 @@ __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
                 return (z2 - rz0) * RY + (y2 - ry0);
             };
 #pragma unroll
-            for (int d = 0; d < RAD; ++d) {
-                nby[q][d][0] = nbi(0, -d - 1);
-                nby[q][d][1] = nbi(0, d + 1);
-                nbz[q][d][0] = nbi(-d - 1, 0);
-                nbz[q][d][1] = nbi(d + 1, 0);
-            }
+            for (int n = 0; n < NN; ++n) nb[q][n] = nbi(nb_dz(n, BOX), nb_dy(n, BOX));
         }
     }
     __syncthreads();
@@ -386,12 +470,7 @@ __global__ void __launch_bounds__(kCheckBlock) check_kernel(const CheckArgs a)
                 double v = cbv[q] + wx * cur[i];
                 if (Es != nullptr) v += Es[gl[q]];
 #pragma unroll
-                for (int d = 0; d < RAD; ++d) {
-                    v += wy[d][0] * val(nby[q][d][0]);
-                    v += wy[d][1] * val(nby[q][d][1]);
-                    v += wz[d][0] * val(nbz[q][d][0]);
-                    v += wz[d][1] * val(nbz[q][d][1]);
-                }
+                for (int n = 0; n < NN; ++n) v += wn[n] * val(nb[q][n]);
                 nxt[i] = v;
             }
         }
@@ -511,6 +590,7 @@ bool sweep_shape_supported(int dtype, const SweepShape& s)
 {
     const int vf = dtype == ABFT_F32 ? 4 : 2;
     if (s.tz < 1 || (s.nw != 4 && s.nw != 8) || (s.rad != 1 && s.rad != 2)) return false;
+    if (s.box && (s.rad != 1 || s.nw != 4 || s.pf != 1)) return false;
     if (s.nw == 8 && s.nch * s.vec * (vf == 4 ? 4 : 8) * s.rad > kWideBlockLaneBytes)
         return false;
     if (s.pf == 2)
@@ -532,8 +612,9 @@ size_t sweep_lds_bytes(int dtype, int nx, const SweepShape& s)
     const size_t es = dtype == ABFT_F32 ? 4 : 8;
     const size_t ty = (size_t)sweep_rows_per_block(s);
     const size_t pad = (size_t)std::max(s.vec, s.rad);
-    return 2 * (ty + 2 * s.rad) * (nx + 2 * pad) * es   // two plane buffers with halo rows
-           + 2 * ty * (size_t)s.tz * sizeof(double);     // checksum and boundary tables
+    const size_t planes = s.box ? 4 : 2;  // the box sweep keeps a ring of four planes
+    return planes * (ty + 2 * s.rad) * (nx + 2 * pad) * es  // plane buffers with halo rows
+           + 2 * ty * (size_t)s.tz * sizeof(double);         // checksum and boundary tables
 }
 
 hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, const SweepArgs& a,
@@ -542,6 +623,10 @@ hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, cons
     if (!sweep_shape_supported(dtype, s)) return hipErrorInvalidValue;
     const size_t lds = sweep_lds_bytes(dtype, a.nx, s);
     if (mode == MODE_PLAIN) csum = CS_F64;  // no checksum in the plain variant
+    if (s.box) {
+        if (dtype == ABFT_F32) return launch_sweep_box_f32(mode, csum, s, a, st, lds);
+        return launch_sweep_box_f64(mode, csum, s, a, st, lds);
+    }
     if (s.rad == 2) {
         if (dtype == ABFT_F32) {
             if (mode == MODE_PROT) return launch_sweep_r2_f32_prot(csum, s, a, st, lds);
@@ -574,6 +659,10 @@ hipError_t launch_recover(int dtype, int csum, const SweepShape& s, const Recove
     if (!recover_shape_supported(dtype, s) || r.k < 1 || r.k > kMaxPeriod || num_cus < 1)
         return hipErrorInvalidValue;
     const size_t lds = sweep_lds_bytes(dtype, r.a.nx, s);
+    if (s.box) {
+        if (dtype == ABFT_F32) return launch_recover_box_f32(csum, s, r, lds, num_cus, st);
+        return launch_recover_box_f64(csum, s, r, lds, num_cus, st);
+    }
     if (s.rad == 2) {
         if (dtype == ABFT_F32) return launch_recover_r2_f32(csum, s, r, lds, num_cus, st);
         return launch_recover_r2_f64(csum, s, r, lds, num_cus, st);
@@ -582,11 +671,14 @@ hipError_t launch_recover(int dtype, int csum, const SweepShape& s, const Recove
     return launch_recover_f64(csum, s, r, lds, num_cus, st);
 }
 
-size_t fixup_lds_bytes(int nx) { return (size_t)nx * (3 * sizeof(double) + 2 * sizeof(int)); }
+size_t fixup_lds_bytes(int nx, bool box)
+{
+    return (size_t)nx * ((box ? 12 : 3) * sizeof(double) + 2 * sizeof(int));
+}
 
 hipError_t launch_fixup_batch(int dtype, const BatchArgs& b, int maxnx, hipStream_t st)
 {
-    const size_t lds = fixup_lds_bytes(maxnx);
+    const size_t lds = fixup_lds_bytes(maxnx, false);
     if (dtype == ABFT_F32)
         hipLaunchKernelGGL(fixup_batch_kernel<float>, dim3(b.ngrids), dim3(kFixBlock), lds, st,
                            b);
@@ -598,16 +690,27 @@ hipError_t launch_fixup_batch(int dtype, const BatchArgs& b, int maxnx, hipStrea
 
 hipError_t launch_fixup(int dtype, const FixArgs& a, hipStream_t st)
 {
-    const size_t lds = fixup_lds_bytes(a.nx);
+    const bool box = a.st.box != 0;
+    const size_t lds = fixup_lds_bytes(a.nx, box);
     const bool r2 = a.st.rad == 2;
+    auto go = [&](auto kern) -> hipError_t {
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(kern, dim3(1), dim3(kFixBlock), lds, st, a);
+        return hipGetLastError();
+    };
     if (dtype == ABFT_F32) {
-        if (r2) hipLaunchKernelGGL((fixup_kernel<float, 2>), dim3(1), dim3(kFixBlock), lds, st, a);
-        else hipLaunchKernelGGL((fixup_kernel<float, 1>), dim3(1), dim3(kFixBlock), lds, st, a);
-    } else {
-        if (r2) hipLaunchKernelGGL((fixup_kernel<double, 2>), dim3(1), dim3(kFixBlock), lds, st, a);
-        else hipLaunchKernelGGL((fixup_kernel<double, 1>), dim3(1), dim3(kFixBlock), lds, st, a);
+        if (box) return go(fixup_kernel<float, 1, 1>);
+        if (r2) return go(fixup_kernel<float, 2, 0>);
+        return go(fixup_kernel<float, 1, 0>);
     }
-    return hipGetLastError();
+    if (box) return go(fixup_kernel<double, 1, 1>);
+    if (r2) return go(fixup_kernel<double, 2, 0>);
+    return go(fixup_kernel<double, 1, 0>);
 }
 
 size_t check_lds_bytes(int ry, int rz) { return (size_t)2 * ry * rz * sizeof(double); }
@@ -615,10 +718,12 @@ size_t check_lds_bytes(int ry, int rz) { return (size_t)2 * ry * rz * sizeof(dou
 hipError_t launch_check(const CheckArgs& a, hipStream_t st)
 {
     const size_t lds = check_lds_bytes(a.ry_max, a.rz_max);
-    if (a.st.rad == 2)
-        hipLaunchKernelGGL(check_kernel<2>, dim3(a.nyt * a.nzt), dim3(kCheckBlock), lds, st, a);
+    if (a.st.box)
+        hipLaunchKernelGGL((check_kernel<1, 1>), dim3(a.nyt * a.nzt), dim3(kCheckBlock), lds, st, a);
+    else if (a.st.rad == 2)
+        hipLaunchKernelGGL((check_kernel<2, 0>), dim3(a.nyt * a.nzt), dim3(kCheckBlock), lds, st, a);
     else
-        hipLaunchKernelGGL(check_kernel<1>, dim3(a.nyt * a.nzt), dim3(kCheckBlock), lds, st, a);
+        hipLaunchKernelGGL((check_kernel<1, 0>), dim3(a.nyt * a.nzt), dim3(kCheckBlock), lds, st, a);
     return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@
 // drains, and the next check reports the failure.
 #pragma once
 
-#include "abft_sweep.h"
+#include "abft_box.h"
 
 namespace abft {
 
@@ -47,7 +47,7 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* bar, unsigned target,
     return ok != 0;
 }
 
-template <typename T, int CS, int LPR, int NCH, int VEC, int NW, int RAD>
+template <typename T, int CS, int LPR, int NCH, int VEC, int NW, int RAD, int BOX>
 __global__ void __launch_bounds__(NW * 64) recover_kernel(const RecoverArgs r)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -66,10 +66,17 @@ __global__ void __launch_bounds__(NW * 64) recover_kernel(const RecoverArgs r)
         a.t_off = r.t_first + j;
         a.E = r.E != nullptr ? r.E + (size_t)j * a.nz * a.ny : nullptr;
         for (int tile = blockIdx.x; tile < a.ntiles; tile += (int)nb) {
-            if (j == r.k - 1)
-                sweep_tile<T, MODE_CSUM, CS, LPR, NCH, VEC, 1, NW, RAD>(a, tile, smem_raw);
-            else
-                sweep_tile<T, MODE_PLAIN, CS, LPR, NCH, VEC, 1, NW, RAD>(a, tile, smem_raw);
+            if constexpr (BOX) {
+                if (j == r.k - 1)
+                    sweep_box_tile<T, MODE_CSUM, CS, LPR, NCH, VEC, NW>(a, tile, smem_raw);
+                else
+                    sweep_box_tile<T, MODE_PLAIN, CS, LPR, NCH, VEC, NW>(a, tile, smem_raw);
+            } else {
+                if (j == r.k - 1)
+                    sweep_tile<T, MODE_CSUM, CS, LPR, NCH, VEC, 1, NW, RAD>(a, tile, smem_raw);
+                else
+                    sweep_tile<T, MODE_PLAIN, CS, LPR, NCH, VEC, 1, NW, RAD>(a, tile, smem_raw);
+            }
             __syncthreads();  // the tile's LDS use is over
         }
         if (j + 1 < r.k && !grid_barrier(r.bar, (unsigned)(j + 1) * nb, &cnt->barrier_timeouts))
@@ -82,13 +89,13 @@ __global__ void __launch_bounds__(NW * 64) recover_kernel(const RecoverArgs r)
     }
 }
 
-template <typename T, int CS, int RAD>
+template <typename T, int CS, int RAD, int BOX = 0>
 hipError_t launch_recover_t(const SweepShape& s, const RecoverArgs& r, size_t lds, int num_cus,
                             hipStream_t st)
 {
 #define ABFT_RECOVER_CASE_NW(LPR_, NCH_, VEC_, NW_)                                            \
     if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_ && s.nw == NW_) {                      \
-        auto kern = recover_kernel<T, CS, LPR_, NCH_, VEC_, NW_, RAD>;                         \
+        auto kern = recover_kernel<T, CS, LPR_, NCH_, VEC_, NW_, RAD, BOX>;                    \
         static int lds_set = 0;                                                                \
         static size_t occ_lds = 0;                                                             \
         static int occ = 0;                                                                    \
@@ -113,7 +120,7 @@ hipError_t launch_recover_t(const SweepShape& s, const RecoverArgs& r, size_t ld
     }
 #define ABFT_RECOVER_CASE(LPR_, NCH_, VEC_)                                                    \
     ABFT_RECOVER_CASE_NW(LPR_, NCH_, VEC_, 4)                                                  \
-    if constexpr (NCH_ * VEC_ * sizeof(T) * RAD <= kWideBlockLaneBytes) {                      \
+    if constexpr (!BOX && NCH_ * VEC_ * sizeof(T) * RAD <= kWideBlockLaneBytes) {              \
         ABFT_RECOVER_CASE_NW(LPR_, NCH_, VEC_, 8)                                              \
     }
     constexpr int VF = 16 / (int)sizeof(T);

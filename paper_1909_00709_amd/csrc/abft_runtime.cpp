@@ -157,6 +157,29 @@ abft_status map_taps(abft_ctx* c, const abft_problem* p)
     c->st.bc = p->bc;
     c->st.g = round_to(p->dtype, p->bc_value);
     c->st.rad = 1;
+    // A tap off the axes (two or three offsets non-zero, each within -1..1) makes the
+    // stencil a 27-point box: every tap then goes to the box weights.
+    bool box = false;
+    for (int k = 0; k < p->ntaps; ++k) {
+        const abft_tap& t = p->taps[k];
+        const int axes = (t.dx != 0) + (t.dy != 0) + (t.dz != 0);
+        if (axes > 1) box = true;
+    }
+    if (box) {
+        c->st.box = 1;
+        for (int k = 0; k < p->ntaps; ++k) {
+            const abft_tap& t = p->taps[k];
+            if (std::abs(t.dx) > 1 || std::abs(t.dy) > 1 || std::abs(t.dz) > 1)
+                return fail(c, ABFT_E_UNSUPPORTED,
+                            "GPU box stencils take offsets within -1..1 on every axis");
+            const int slot = box_slot(t.dx, t.dy, t.dz);
+            if (c->st.bmask & (1u << slot)) return fail(c, ABFT_E_INVAL, "duplicate tap offset");
+            if (!std::isfinite(t.w)) return fail(c, ABFT_E_INVAL, "non-finite tap weight");
+            c->st.bmask |= 1u << slot;
+            c->st.wb[slot] = round_to(p->dtype, t.w);
+        }
+        return ABFT_OK;
+    }
     for (int k = 0; k < p->ntaps; ++k) {
         const abft_tap& t = p->taps[k];
         const int axes = (t.dx != 0) + (t.dy != 0) + (t.dz != 0);
@@ -183,11 +206,12 @@ abft_status map_taps(abft_ctx* c, const abft_problem* p)
 // block of 8 wavefronts per compute unit take that (the deeper block halves the share of halo
 // rows it loads and keeps more loads in flight per CU), cut into about that many z-slabs;
 // smaller grids take blocks of 4 wavefronts and enough z-slabs for ~1024 blocks.
-bool default_shape(int dtype, int nx, int ny, int nz, int rad, SweepShape* s)
+bool default_shape(int dtype, int nx, int ny, int nz, int rad, int box, SweepShape* s)
 {
     const int vf = 16 / (int)esize(dtype);
     SweepShape r{};
     r.rad = rad;
+    r.box = box;
     if (nx % vf == 0) {
         r.vec = vf;
         if (nx <= 16 * vf * 4) {
@@ -228,7 +252,8 @@ bool default_shape(int dtype, int nx, int ny, int nz, int rad, SweepShape* s)
 abft_status apply_shape(abft_ctx* c, const SweepShape& shape)
 {
     SweepShape s = shape;
-    s.rad = c->st.rad;  // the kernels are built per stencil radius
+    s.rad = c->st.rad;  // the kernels are built per stencil radius and form
+    s.box = c->st.box;
     if (!sweep_shape_supported(c->dtype, s)) return fail(c, ABFT_E_UNSUPPORTED, "launch shape");
     if ((int64_t)s.lpr * s.nch * s.vec < c->nx) return fail(c, ABFT_E_UNSUPPORTED, "row too long");
     if (s.vec > 1 && c->nx % s.vec) return fail(c, ABFT_E_UNSUPPORTED, "row not 16-byte multiple");
@@ -253,6 +278,7 @@ std::string cache_key(const abft_ctx* c)
     o << c->dtype << ' ' << c->nx << ' ' << c->ny << ' ' << c->nz << ' ' << c->mode << ' '
       << c->csum;
     if (c->st.rad != 1) o << " r" << c->st.rad;
+    if (c->st.box) o << " box";
     return o.str();
 }
 
@@ -361,6 +387,18 @@ SweepArgs base_args(const abft_ctx* c)
 bool need_boundary_terms(const abft_ctx* c)
 {
     if (c->bc == ABFT_BC_PERIODIC) return false;
+    if (c->st.box) {
+        // per (dy, dz) the dx = -1 and dx = +1 terms of a row cancel under clamp only with
+        // equal weights
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int sm = box_slot(-1, dy, dz), sp = box_slot(1, dy, dz);
+                const bool hm = c->st.bmask & (1u << sm), hp = c->st.bmask & (1u << sp);
+                if (c->bc != ABFT_BC_CLAMP && (hm || hp)) return true;
+                if (hm != hp || (hm && c->st.wb[sm] != c->st.wb[sp])) return true;
+            }
+        return false;
+    }
     const uint32_t m = c->st.mask;
     const bool xm = m & (1u << W_XM), xp = m & (1u << W_XP);
     const bool x2 = m & ((1u << W_XM2) | (1u << W_XP2));
@@ -601,8 +639,8 @@ abft_status validate_problem(const abft_problem* p)
         return fail(nullptr, ABFT_E_INVAL, "dtype");
     if (p->bc < ABFT_BC_CLAMP || p->bc > ABFT_BC_CONSTANT)
         return fail(nullptr, ABFT_E_INVAL, "boundary rule");
-    if (p->ntaps < 1 || p->ntaps > W_COUNT || !p->taps)
-        return fail(nullptr, ABFT_E_INVAL, "taps (1..13 required)");
+    if (p->ntaps < 1 || p->ntaps > 27 || !p->taps)
+        return fail(nullptr, ABFT_E_INVAL, "taps (1..27 required)");
     if (!p->u0 || !p->u1 || p->u0 == p->u1)
         return fail(nullptr, ABFT_E_INVAL, "u0 and u1 must be distinct device buffers");
     if (!std::isfinite(p->bc_value) || !std::isfinite(p->cterm_scalar))
@@ -879,13 +917,15 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
     }
     const bool cached = cache_lookup(c, &shape);
     shape.rad = c->st.rad;
+    shape.box = c->st.box;
     if (!cached || !sweep_shape_supported(c->dtype, shape)) {
-        if (!default_shape(c->dtype, c->nx, c->ny, c->nz, c->st.rad, &shape))
+        if (!default_shape(c->dtype, c->nx, c->ny, c->nz, c->st.rad, c->st.box, &shape))
             return bail(fail(c, ABFT_E_UNSUPPORTED, "row length beyond the GPU kernels"));
     }
     s = apply_shape(c, shape);
     if (s) return bail(s);
-    if (fixup_lds_bytes(c->nx) > kLdsLimit || c->nx > 4 * kFixBlock)
+    if (fixup_lds_bytes(c->nx, c->st.box) > (c->st.box ? kSweepLdsLimit : kLdsLimit) ||
+        c->nx > 4 * kFixBlock)
         return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
     if (c->mode == ABFT_MODE_OFFLINE) {
         check_shape(c, std::min(c->period, kCheckChunk / c->st.rad) * c->st.rad);
@@ -1225,7 +1265,7 @@ abft_status abft_stencil_autotune(abft_ctx* c)
             for (int nch : {1, 2, 4, 8, 16}) {
                 for (int pf : {1, 2})
                     for (int nw : {4, 8}) {
-                        SweepShape sh{lpr, nch, vec, 1, pf, nw, c->st.rad};
+                        SweepShape sh{lpr, nch, vec, 1, pf, nw, c->st.rad, c->st.box};
                         if (!sweep_shape_supported(c->dtype, sh)) continue;
                         if ((int64_t)lpr * nch * vec < c->nx) continue;
                         if ((int64_t)lpr * (nch / 2) * vec >= c->nx && nch > 1) continue;  // minimal
@@ -1365,7 +1405,7 @@ abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft
     else if (c->maxnx <= 64 * 16) sh = SweepShape{64, 16, 1, 1, 1};
     else return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the batched kernel"));
     c->shape = sh;
-    if (fixup_lds_bytes(c->maxnx) > kLdsLimit || c->maxnx > 4 * kFixBlock)
+    if (fixup_lds_bytes(c->maxnx, false) > kLdsLimit || c->maxnx > 4 * kFixBlock)
         return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
 
     c->grids.resize(n);
@@ -1374,7 +1414,7 @@ abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft
         // per-grid stencil: reuse the single-grid tap mapping on a scratch context
         abft_ctx tmp;
         if ((s = map_taps(&tmp, &p[i]))) return bail(fail(c, s, tmp.err));
-        if (tmp.st.rad != 1)
+        if (tmp.st.rad != 1 || tmp.st.box)
             return bail(fail(c, ABFT_E_UNSUPPORTED, "batched grids take radius-1 stars"));
         G.st = tmp.st;
         G.nx = p[i].nx;
