@@ -258,21 +258,28 @@ DIFF4_TAPS = tuple([(0, 0, 0, 1 - 3 * 0.05 * 30 / 12)] + [
     for off in [[sg * d if i == ax else 0 for i in range(3)]]])
 
 
-def bench_radius2(stream, timed, u0, C, tune=True, k=10, steps=10):
-    """The 13-point radius-2 star on the large grid: plain sweep, protected sweep kernel,
-    online ABFT (graph) and offline windows of k, each autotuned."""
+# A 27-point box smoother: centre 0.4, faces 0.05, edges 0.015, corners 0.005 (sum 0.92).
+BOX27_TAPS = tuple((dx, dy, dz, (0.4, 0.05, 0.015, 0.005)[abs(dx) + abs(dy) + abs(dz)])
+                   for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1))
+
+
+def bench_radius2(stream, timed, u0, C, tune=True, k=10, steps=10, taps=DIFF4_TAPS,
+                  name="13-point radius-2 star (fourth-order diffusion)"):
+    """A stencil other than the 7-point star on the large grid (the 13-point radius-2 star
+    by default): plain sweep, protected sweep kernel, online ABFT (graph) and offline windows
+    of k, each autotuned."""
     import torch
 
     from paper_1909_00709_amd import abft
 
     npts = u0.numel()
-    res = {"workload": f"13-point radius-2 star (fourth-order diffusion), {tuple(u0.shape)} fp32"}
+    res = {"workload": f"{name}, {tuple(u0.shape)} fp32"}
     for name, mode, kw in (("plain", "none", {}),
                            ("prot_kernel", "online", dict(threshold=2e-7, auto_correct=False)),
                            ("online", "online", dict(threshold=2e-7)),
                            ("offline", "offline", dict(threshold=2e-6, period=k))):
         with torch.cuda.stream(stream):
-            S = abft.Stencil(u0.clone(), DIFF4_TAPS, C=C, mode=mode, stream=stream, **kw)
+            S = abft.Stencil(u0.clone(), taps, C=C, mode=mode, stream=stream, **kw)
             if tune:
                 S.autotune()
             if name == "online":
@@ -307,7 +314,7 @@ def main():
     ap.add_argument("--period", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["plain", "prot", "offline", "online", "batch", "configs",
-                                       "periods", "radius2"],
+                                       "periods", "radius2", "box27"],
                     default=None,
                     help="run one measurement only (for profiler runs)")
     ap.add_argument("--no-tune", action="store_true",
@@ -442,6 +449,12 @@ def main():
     if args.only == "radius2":
         print(json.dumps({"only": "radius2", "radius2": bench_radius2(stream, timed, u0, C,
                                                                       tune=not args.no_tune)}))
+        return
+
+    if args.only == "box27":
+        print(json.dumps({"only": "box27", "box27": bench_radius2(
+            stream, timed, u0, C, tune=not args.no_tune, taps=BOX27_TAPS,
+            name="27-point box smoother")}))
         return
 
     if args.only == "periods":

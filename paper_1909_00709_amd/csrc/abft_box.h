@@ -2,13 +2,13 @@
 // with the row checksum (Eq.(3)), its prediction (Theorem 1) and the mismatch test
 // (Section 3.4) in the same pass.
 //
-// The decomposition is that of the star sweep (abft_sweep.h): a block of 4 wavefronts owns TY
-// whole rows of a slab of planes and marches along z, each row held by LPR lanes.  A box tap
-// reads the in-plane neighbours of planes z-1 and z+1 as well, so the block keeps a ring of
-// four LDS plane buffers, each with the block's rows, one halo row above and below and the
-// x-ghosts: at step z the planes z-1, z, z+1 are in three of them while plane z+2 is written
-// into the fourth (the buffer of plane z-2, which no wavefront reads any more once all have
-// passed the previous step's barrier), so one barrier per plane suffices.
+// The decomposition is that of the star sweep (abft_sweep.h): a block of NW wavefronts owns
+// TY whole rows of a slab of planes and marches along z, each row held by LPR lanes.  A box
+// tap reads the in-plane neighbours of planes z-1 and z+1 as well, so the block keeps a ring
+// of three LDS plane buffers, each with the block's rows, one halo row above and below and
+// the x-ghosts: at step z they hold the planes z-1, z, z+1; plane z+1 is written into the
+// buffer of plane z-2 at the start of the step, after a barrier that ends the previous step's
+// reads (a fourth buffer would save that barrier but halves the blocks a CU can hold).
 //
 // Theorem 1 for a box stencil: the row sum of the output row (z, y) is the constant term's
 // row sum plus, for every (dy, dz), the weight sum over dx times the input row sum of row
@@ -32,7 +32,7 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
     constexpr int TY = NW * RPW;
     constexpr int SEGW = LPR * VEC;
     constexpr int HMAX = (NCH * SEGW + NT * VEC - 1) / (NT * VEC);
-    constexpr int NB = 4;  // LDS plane buffers in the ring
+    constexpr int NB = 3;  // LDS plane buffers in the ring
 
     T* lds = reinterpret_cast<T*>(smem_raw);
     const int64_t t = a.t_off + (a.t_base != nullptr ? *a.t_base : 0);
@@ -128,7 +128,7 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
         }
     };
     // Plane zz (its mapped index mz, or -1 for a plane of constant ghosts) into its buffer.
-    auto buf_of = [&](int zz) { return lds + (zz & (NB - 1)) * plane_elems; };
+    auto buf_of = [&](int zz) { return lds + ((zz % NB + NB) % NB) * plane_elems; };
     auto put_plane = [&](int zz, const T (&own)[NCH][VEC], const T (&hal)[2][HMAX][VEC]) {
         T* buf = buf_of(zz);
         if (row_ok) {
@@ -156,6 +156,32 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
         }
     };
 
+    // The input row sums the epilogue's prediction reads for this lane's first plane (the
+    // nine rows around it) and its constant-term sum, loaded now so that their latency hides
+    // behind the march.
+    auto brow = [&](int z2, int y2) -> double {
+        const int mz = map_coord(z2, nz, bc), my = map_coord(y2, ny, bc);
+        if (mz < 0 || my < 0) return (double)nx * (double)g;
+        return a.Bt[(size_t)mz * ny + my];
+    };
+    double pre[3][3], pcb = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) pre[dz][dy] = 0.0;
+    unsigned long long nknown = 0ull;
+    if constexpr (MODE == MODE_PROT) {
+        nknown = noise_known(a.cnt);
+        if (row_ok && sl < z1 - z0) {
+            const int z = z0 + sl;
+            pcb = a.cB[(size_t)z * ny + y];
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy) pre[dz + 1][dy + 1] = brow(z + dz, y + dy);
+        }
+    }
+
     // prologue: planes z0-1 and z0 into the ring, z0+1 in flight
     {
         T pu[NCH][VEC], ph[2][HMAX][VEC];
@@ -170,12 +196,25 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
     load_halo(hn, map_coord(z0 + 1, nz, bc));
     load_c(cc, z0);
 
+    // this lane's neighbour row for the boundary terms (lanes 0..8 of a row), its weights
+    const int ldz = sl / 3 - 1, ldy = sl % 3 - 1;
+    double lwm = 0.0, lwp = 0.0;
+    bool lhm = false, lhp = false;
+    if (sl < 9) {
+        const int sm = box_slot(-1, ldy, ldz), sp = box_slot(1, ldy, ldz);
+        lhm = has(sm);
+        lhp = has(sp);
+        lwm = a.st.wb[sm];
+        lwp = a.st.wb[sp];
+    }
+
     double* tabS = reinterpret_cast<double*>(smem_raw + (size_t)NB * plane_elems * sizeof(T));
     double* tabE = tabS + TY * a.tz;
     const bool keep_e = MODE == MODE_PROT || a.E != nullptr;
     using Acc = T;
 
     for (int z = z0; z < z1; ++z) {
+        if (z > z0) __syncthreads();  // the previous step's reads of plane z-2 are over
         put_plane(z + 1, nu, hn);
         if (z + 1 < z1) {
             load_u(nu, map_coord(z + 2, nz, bc));
@@ -278,20 +317,18 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
             }
             if (row_ok && sl == 0) tabS[r * a.tz + (z - z0)] = S;
         }
-        if (keep_e && row_ok && sl == 0) {
+        if (keep_e) {
             // x-boundary terms of the nine input rows around (z, y): a shift dx = -1 reads
-            // G(-1) and drops u(nx-1); dx = +1 reads G(nx) and drops u(0)
-            double e = 0.0;
-#pragma unroll
-            for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-                for (int dy = -1; dy <= 1; ++dy) {
-                    const T* rw = rows[dz + 1][dy + 1];
-                    const int sm = box_slot(-1, dy, dz), sp = box_slot(1, dy, dz);
-                    if (has(sm)) e += a.st.wb[sm] * ((double)rw[-1] - (double)rw[nx - 1]);
-                    if (has(sp)) e += a.st.wb[sp] * ((double)rw[nx] - (double)rw[0]);
-                }
-            tabE[r * a.tz + (z - z0)] = e;
+            // G(-1) and drops u(nx-1); dx = +1 reads G(nx) and drops u(0).  Lane j < 9 of
+            // the row takes neighbour row j, and a 16-lane reduction sums them.
+            double part = 0.0;
+            if (row_ok && sl < 9) {
+                const T* rw = buf_of(z + ldz) + (r + 1 + ldy) * stride + VEC;
+                if (lhm) part += lwm * ((double)rw[-1] - (double)rw[nx - 1]);
+                if (lhp) part += lwp * ((double)rw[nx] - (double)rw[0]);
+            }
+            const double e = row16_sum(part);
+            if (row_ok && sl == 0) tabE[r * a.tz + (z - z0)] = e;
         }
 #pragma unroll
         for (int c = 0; c < NCH; ++c)
@@ -303,15 +340,8 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
         if (a.E == nullptr) return;
     }
     __syncthreads();
-    auto brow = [&](int z2, int y2) -> double {
-        const int mz = map_coord(z2, nz, bc), my = map_coord(y2, ny, bc);
-        if (mz < 0 || my < 0) return (double)nx * (double)g;
-        return a.Bt[(size_t)mz * ny + my];
-    };
     const int nzt = z1 - z0;
     double noise = 0.0;
-    unsigned long long nknown = 0ull;
-    if constexpr (MODE == MODE_PROT) nknown = noise_known(a.cnt);
     if (row_ok) {
         for (int pz = sl; pz < nzt; pz += LPR) {
             const int z = z0 + pz;
@@ -323,7 +353,8 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
                 if constexpr (MODE == MODE_PROT) {
                     // Theorem 1 for the box: the weight sums over dx times the nine input
                     // row sums, plus the boundary terms formed in the march
-                    double bp = a.cB[l] + tabE[r * a.tz + pz];
+                    const bool first = pz == sl;
+                    double bp = (first ? pcb : a.cB[l]) + tabE[r * a.tz + pz];
 #pragma unroll
                     for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
@@ -338,7 +369,8 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
                                     any = true;
                                 }
                             }
-                            if (any) bp += wsum * brow(z + dz, y + dy);
+                            if (any)
+                                bp += wsum * (first ? pre[dz + 1][dy + 1] : brow(z + dz, y + dy));
                         }
                     const double dlt = fabs(S - bp);
                     if (!(dlt <= a.eps * fabs(bp))) {
@@ -379,14 +411,14 @@ __global__ void __launch_bounds__(NW * 64) sweep_box_kernel(const SweepArgs a)
     sweep_box_tile<T, MODE, CS, LPR, NCH, VEC, NW>(a, tile, smem_raw);
 }
 
-// Table of instantiated box variants (blocks of 4 wavefronts, prefetch depth 1).
+// Table of instantiated box variants (prefetch depth 1).
 template <typename T, int MODE, int CS>
 hipError_t launch_sweep_box_t(const SweepShape& s, const SweepArgs& a, hipStream_t st,
                               size_t lds)
 {
-#define ABFT_BOX_CASE(LPR_, NCH_, VEC_)                                                        \
-    if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_ && s.nw == 4) {                        \
-        auto kern = sweep_box_kernel<T, MODE, CS, LPR_, NCH_, VEC_, 4>;                        \
+#define ABFT_BOX_CASE_NW(LPR_, NCH_, VEC_, NW_)                                               \
+    if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_ && s.nw == NW_) {                      \
+        auto kern = sweep_box_kernel<T, MODE, CS, LPR_, NCH_, VEC_, NW_>;                      \
         static int lds_set = 0;                                                                \
         if (lds > 65536 && (int)lds > lds_set) {                                               \
             hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),             \
@@ -395,8 +427,13 @@ hipError_t launch_sweep_box_t(const SweepShape& s, const SweepArgs& a, hipStream
             if (e != hipSuccess) return e;                                                     \
             lds_set = (int)lds;                                                                \
         }                                                                                      \
-        hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(256), lds, st, a);                       \
+        hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(NW_ * 64), lds, st, a);                  \
         return hipGetLastError();                                                              \
+    }
+#define ABFT_BOX_CASE(LPR_, NCH_, VEC_)                                                        \
+    ABFT_BOX_CASE_NW(LPR_, NCH_, VEC_, 4)                                                      \
+    if constexpr (NCH_ * VEC_ * sizeof(T) <= kWideBlockLaneBytes) {                            \
+        ABFT_BOX_CASE_NW(LPR_, NCH_, VEC_, 8)                                                  \
     }
     constexpr int VF = 16 / (int)sizeof(T);
     ABFT_BOX_CASE(16, 1, VF)
@@ -409,6 +446,7 @@ hipError_t launch_sweep_box_t(const SweepShape& s, const SweepArgs& a, hipStream
     ABFT_BOX_CASE(64, 4, 1)
     ABFT_BOX_CASE(64, 16, 1)
 #undef ABFT_BOX_CASE
+#undef ABFT_BOX_CASE_NW
     return hipErrorInvalidValue;
 }
 

@@ -208,7 +208,7 @@ struct SweepShape {
     int32_t pf;    // planes loaded ahead of the one computed: 1 or 2
     int32_t nw = 4;  // wavefronts per block: 4 or 8 (each holds 64 / lpr rows)
     int32_t rad = 1; // stencil radius the kernel is built for: 1 or 2
-    int32_t box = 0; // 1: the 27-point box kernel (radius 1, blocks of 4 wavefronts)
+    int32_t box = 0; // 1: the 27-point box kernel (radius 1, prefetch depth 1)
 };
 
 bool sweep_shape_supported(int dtype, const SweepShape& s);
@@ -252,7 +252,7 @@ hipError_t launch_recover_box_f32(int csum, const SweepShape& s, const RecoverAr
 hipError_t launch_recover_box_f64(int csum, const SweepShape& s, const RecoverArgs& r,
                                   size_t lds, int num_cus, hipStream_t st);
 
-// Box (27-point) sweep launchers (blocks of 4 wavefronts, prefetch depth 1).
+// Box (27-point) sweep launchers (prefetch depth 1).
 hipError_t launch_sweep_box_f32(int mode, int csum, const SweepShape& s, const SweepArgs& a,
                                 hipStream_t st, size_t lds);
 hipError_t launch_sweep_box_f64(int mode, int csum, const SweepShape& s, const SweepArgs& a,

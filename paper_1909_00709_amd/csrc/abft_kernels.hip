@@ -590,7 +590,7 @@ bool sweep_shape_supported(int dtype, const SweepShape& s)
 {
     const int vf = dtype == ABFT_F32 ? 4 : 2;
     if (s.tz < 1 || (s.nw != 4 && s.nw != 8) || (s.rad != 1 && s.rad != 2)) return false;
-    if (s.box && (s.rad != 1 || s.nw != 4 || s.pf != 1)) return false;
+    if (s.box && (s.rad != 1 || s.pf != 1)) return false;
     if (s.nw == 8 && s.nch * s.vec * (vf == 4 ? 4 : 8) * s.rad > kWideBlockLaneBytes)
         return false;
     if (s.pf == 2)
@@ -612,7 +612,7 @@ size_t sweep_lds_bytes(int dtype, int nx, const SweepShape& s)
     const size_t es = dtype == ABFT_F32 ? 4 : 8;
     const size_t ty = (size_t)sweep_rows_per_block(s);
     const size_t pad = (size_t)std::max(s.vec, s.rad);
-    const size_t planes = s.box ? 4 : 2;  // the box sweep keeps a ring of four planes
+    const size_t planes = s.box ? 3 : 2;  // the box sweep keeps a ring of three planes
     return planes * (ty + 2 * s.rad) * (nx + 2 * pad) * es  // plane buffers with halo rows
            + 2 * ty * (size_t)s.tz * sizeof(double);         // checksum and boundary tables
 }

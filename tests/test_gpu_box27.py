@@ -26,7 +26,7 @@ def box27(wc, wface, wedge, wcorner, asym=1.0):
 
 
 DYADIC27 = box27(0.25, 0.0625, 0.015625, 0.0078125)
-SMOOTH27 = box27(0.4, 0.05, 0.015, 0.005)       # weights sum to 1.0
+SMOOTH27 = box27(0.4, 0.05, 0.015, 0.005)       # weights sum to 0.92
 ASYM27 = box27(0.3, 0.06, 0.012, 0.004, asym=1.7)
 
 
