@@ -76,13 +76,15 @@ typedef struct {
 typedef struct {
     int32_t nx, ny, nz;         /* grid extents, >= 1 each; nz = 1 for a 2D grid */
     int32_t dtype;              /* abft_dtype of u0, u1 and cterm */
-    int32_t ntaps;              /* number of taps, 1..13 on the GPU */
+    int32_t ntaps;              /* number of taps, 1..27 on the GPU */
     int32_t bc;                 /* abft_bc */
     const abft_tap* taps;       /* host array of ntaps taps, copied by init.  GPU support:
-                                   offsets in the star of radius 2 (the centre and points at
-                                   distance 1 or 2 along one axis), each at most once; an
-                                   axis carrying a distance-2 tap must be at least 2 long.
-                                   Batches (abft_stencil_init_batch) take radius 1 only. */
+                                   each offset at most once, either in the star of radius 2
+                                   (the centre and points at distance 1 or 2 along one axis;
+                                   an axis carrying a distance-2 tap must be at least 2 long)
+                                   or in the 3 x 3 x 3 box (every offset in -1..1 per axis,
+                                   diagonal taps included).  Batches
+                                   (abft_stencil_init_batch) take radius-1 stars only. */
     double bc_value;            /* ghost value for ABFT_BC_CONSTANT, rounded to dtype */
     const void* cterm;          /* device [nz][ny][nx] constant term C of Eq.(1), or NULL */
     double cterm_scalar;        /* constant term used when cterm is NULL, rounded to dtype */
