@@ -121,7 +121,16 @@ enum {
     ABFT_EV_ROLLBACK = 6,       /* offline rollback: sweep = first sweep of the window,
                                    x = window length */
     ABFT_EV_PERSISTENT = 7,     /* offline recompute mismatched again: sweep = window end */
-    ABFT_EV_COL_FLAG = 8        /* column mismatch found while locating: sweep, z, x */
+    ABFT_EV_COL_FLAG = 8,       /* column mismatch found while locating: sweep, z, x */
+    ABFT_EV_MEM_FLAG = 9,       /* online: an input row of the sweep differs from the checksum
+                                   stored when it was written: sweep, z, y; a = the row's sum
+                                   as read, b = the stored B */
+    ABFT_EV_MEM_CORRECTED = 10, /* input point repaired in place: sweep, z, y, x; a = old
+                                   value, b = new; the sweep's outputs that read it are
+                                   evaluated again */
+    ABFT_EV_MEM_UNLOCATED = 11  /* input row mismatch that the weighted row sums do not place
+                                   on one point: sweep, z, y; a = change of the row sum,
+                                   b = implied position + 1 */
 };
 
 typedef struct {
@@ -132,14 +141,27 @@ typedef struct {
     int32_t pad;
 } abft_event;
 
-/* A bit flip for the fault plan (Section 5.1 fault model): XOR (1 << bit) into the value
- * sweep `sweep` stores at (x, y, z), after the update and before the store, so the stored
- * value and its checksum both see it.  It fires only on the given attempt (0 = first run,
- * 1 = offline recompute after a rollback). */
+/* Fault kinds. */
+enum {
+    ABFT_FAULT_STORE = 0,       /* the value sweep `sweep` stores (Section 5.1 fault model) */
+    ABFT_FAULT_MEMORY = 1       /* the input grid of sweep `sweep`, in memory, after its
+                                   checksums were taken and before the sweep reads it (the
+                                   first case in the proof of Theorem 2) */
+};
+
+/* A bit flip for the fault plan: XOR (1 << bit) into the word at (x, y, z).  STORE: into the
+ * value sweep `sweep` stores, after the update and before the store, so the stored value and
+ * its checksum both see it; it fires on the given attempt (0 = first run, 1 = offline
+ * recompute after a rollback).  MEMORY: into u^sweep before sweep `sweep` reads it, on the
+ * first attempt only (attempt must be 0); single-grid contexts only.  In offline mode the
+ * checkpoint is the window's first input in place, so a MEMORY flip on a window's first sweep
+ * also corrupts the checkpoint. */
 typedef struct {
     int64_t sweep;
     int32_t z, y, x, bit, attempt;
     int32_t grid;               /* grid index in a batch context, 0 otherwise */
+    int32_t kind;               /* ABFT_FAULT_* */
+    int32_t pad;
 } abft_fault;
 
 typedef struct {
@@ -157,6 +179,9 @@ typedef struct {
     int64_t pending;            /* detections waiting for abft_stencil_correct */
     int64_t sweeps_skipped;     /* offline without auto-correct: sweeps not run after a
                                    flagged window (re-issue them after correct) */
+    int64_t mem_flagged;        /* online: input rows that differed from their checksums */
+    int64_t mem_corrected;      /* online: input points repaired in place */
+    int64_t mem_unlocated;      /* online: input row mismatches not placed on one point */
     double max_noise;           /* largest |B - B'| / |B'| over unflagged rows so far */
     int32_t nevents;            /* events copied into `events` by check() */
     int32_t events_cap;         /* capacity of `events` (set by the caller) */

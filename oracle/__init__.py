@@ -21,12 +21,15 @@ BC_CLAMP, BC_PERIODIC, BC_CONSTANT = 0, 1, 2
 MODE_NONE, MODE_ONLINE, MODE_OFFLINE = 0, 1, 2
 EV_ROW_FLAG, EV_CORRECTED, EV_CHECKSUM_FAULT, EV_UNCORRECTABLE = 1, 2, 3, 4
 EV_WINDOW_FLAG, EV_ROLLBACK, EV_PERSISTENT, EV_COL_FLAG = 5, 6, 7, 8
+EV_MEM_FLAG, EV_MEM_CORRECTED, EV_MEM_UNLOCATED = 9, 10, 11
+FAULT_STORE, FAULT_MEMORY = 0, 1
 
 EVENT_DTYPE = np.dtype([("sweep", "<i8"), ("kind", "<i4"), ("z", "<i4"), ("y", "<i4"),
                         ("x", "<i4"), ("a", "<f8"), ("b", "<f8")])
 COUNTER_FIELDS = ("sweeps_done", "rows_flagged", "cols_flagged", "corrected",
                   "checksum_faults", "uncorrectable", "windows_checked", "windows_flagged",
-                  "rollbacks", "persistent", "events_total")
+                  "rollbacks", "persistent", "events_total", "mem_flagged", "mem_corrected",
+                  "mem_unlocated")
 
 
 def build(force: bool = True) -> str:
@@ -71,6 +74,7 @@ def lib():
         L.orc_sweep.argtypes = [P, vp, vp, vp]
         L.orc_row_checksums.argtypes = [P, vp, dp]
         L.orc_col_checksums.argtypes = [P, vp, dp]
+        L.orc_weighted_row_checksums.argtypes = [P, vp, dp]
         L.orc_const_row_checksums.argtypes = [P, vp, dp]
         L.orc_const_col_checksums.argtypes = [P, vp, dp]
         L.orc_strip_width.argtypes = [P, ctypes.c_int]
@@ -139,6 +143,12 @@ class Problem:
         B = np.empty((nz, ny))
         lib().orc_row_checksums(self.ref, _ptr(self._grid(u)), _ptr(B))
         return B
+
+    def weighted_row_checksums(self, u):
+        nz, ny, nx = self.shape
+        W = np.empty((nz, ny))
+        lib().orc_weighted_row_checksums(self.ref, _ptr(self._grid(u)), _ptr(W))
+        return W
 
     def col_checksums(self, u):
         nz, ny, nx = self.shape

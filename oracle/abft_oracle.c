@@ -122,6 +122,17 @@ static double* rounded_weights(const orc_problem* p)
     return w;
 }
 
+/* Eq.(1) at one point, before the rounding to the storage type: w are the rounded weights,
+ * cs the rounded scalar constant term. */
+static double point(const orc_problem* p, const double* w, double cs, const void* C,
+                    const void* uin, int64_t x, int64_t y, int64_t z)
+{
+    double acc = C ? ld(p->dtype, C, idx(p, x, y, z)) : cs;
+    for (int k = 0; k < p->ntaps; k++)
+        acc += w[k] * ghost(p, uin, x + p->taps[k].dx, y + p->taps[k].dy, z + p->taps[k].dz);
+    return acc;
+}
+
 /* Eq.(1), Section 3.1: out-of-place sweep. */
 void orc_sweep(const orc_problem* p, const void* C, const void* uin, void* uout)
 {
@@ -130,14 +141,8 @@ void orc_sweep(const orc_problem* p, const void* C, const void* uin, void* uout)
 #pragma omp parallel for collapse(2) schedule(static)
     for (int64_t z = 0; z < p->nz; z++)
         for (int64_t y = 0; y < p->ny; y++)
-            for (int64_t x = 0; x < p->nx; x++) {
-                const int64_t i = idx(p, x, y, z);
-                double acc = C ? ld(p->dtype, C, i) : cs;
-                for (int k = 0; k < p->ntaps; k++)
-                    acc += w[k] * ghost(p, uin, x + p->taps[k].dx, y + p->taps[k].dy,
-                                        z + p->taps[k].dz);
-                st(p->dtype, uout, i, acc);
-            }
+            for (int64_t x = 0; x < p->nx; x++)
+                st(p->dtype, uout, idx(p, x, y, z), point(p, w, cs, C, uin, x, y, z));
     free(w);
 }
 
@@ -162,6 +167,20 @@ void orc_col_checksums(const orc_problem* p, const void* u, double* A)
             csum s = {0.0, 0.0};
             for (int64_t y = 0; y < p->ny; y++) cs_add(&s, ld(p->dtype, u, idx(p, x, y, z)));
             A[z * p->nx + x] = cs_val(s);
+        }
+}
+
+/* The index-weighted row sums (a location aid for changes of the stored grid; not part of
+ * the paper's scheme). */
+void orc_weighted_row_checksums(const orc_problem* p, const void* u, double* W)
+{
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < p->nz; z++)
+        for (int64_t y = 0; y < p->ny; y++) {
+            csum s = {0.0, 0.0};
+            for (int64_t x = 0; x < p->nx; x++)
+                cs_add(&s, (double)(x + 1) * ld(p->dtype, u, idx(p, x, y, z)));
+            W[z * p->ny + y] = cs_val(s);
         }
 }
 
@@ -363,6 +382,12 @@ typedef struct {
     /* work arrays */
     double *B, *Bn, *Bp, *cB, *cA, *At, *An, *Ap, *rs, *cs;
     uint8_t *rflag, *cflag;
+    /* input-side check: weighted sums of u^t and u^{t+1}, sums of the input rows as read */
+    double *W, *Wn, *Bi;
+    uint8_t* mflag;
+    double* w;       /* rounded weights */
+    double c_scalar; /* rounded scalar constant term */
+    int reach;       /* largest |offset| of any tap along any axis */
 } run_state;
 
 static void emit(run_state* S, int64_t sweep, int kind, int z, int y, int x, double a, double b)
@@ -380,13 +405,15 @@ static void emit(run_state* S, int64_t sweep, int kind, int z, int y, int x, dou
     S->cnt->events_total++;
 }
 
-/* Section 5.1 fault model: flip one bit of the value the sweep stores, after the update. */
-static void inject(run_state* S, void* uout, int64_t sweep, int attempt)
+/* Section 5.1 fault model: flip one bit of the value the sweep stores, after the update
+ * (kind STORE, applied to uout), or of the sweep's input before it is read (kind MEMORY,
+ * applied to uin). */
+static void inject(run_state* S, void* uout, int64_t sweep, int attempt, int kind)
 {
     const orc_problem* p = S->p;
     for (int64_t f = 0; f < S->nfaults; f++) {
         const orc_fault* F = &S->faults[f];
-        if (F->sweep != sweep || F->attempt != attempt) continue;
+        if (F->sweep != sweep || F->attempt != attempt || F->kind != kind) continue;
         const int64_t i = idx(p, F->x, F->y, F->z);
         if (p->dtype == ORC_F32) {
             uint32_t v;
@@ -486,8 +513,70 @@ static void locate_correct_layer(run_state* S, int64_t sweep, const void* uin, v
     free(xs);
 }
 
-/* Online ABFT after sweep t (Figure 1 steps 2-3, then Section 3.5). */
-static void online_check(run_state* S, int64_t sweep, const void* uin, void* uout)
+/* Boundary rule for the outputs around a repaired input point: periodic wraps, the other
+ * rules have no outputs outside the grid (a clamped read of an edge point comes from an output
+ * inside the grid, which the window already holds). */
+static int64_t window_coord(int bc, int64_t c, int64_t n)
+{
+    if (c >= 0 && c < n) return c;
+    return bc == ORC_BC_PERIODIC ? map_coord(bc, c, n) : -1;
+}
+
+/* A memory-resident change of input row (z, y) of sweep t, found because the row's sum as
+ * read differs from the checksum B^t stored when the row was written (Theorem 2, first case):
+ * the change d = sum - B^t moves the weighted sum by (x + 1) d, which places the point; its
+ * value is recovered from B^t and the other points of the row (the partial-sum form used for
+ * Eq.(10)); the outputs of sweep t that read it (the window of the stencil's reach around it)
+ * are evaluated again, and the row checksums of the output rows in that window recomputed.
+ * Returns 1 when the point was repaired. */
+static int repair_input_row(run_state* S, int64_t sweep, void* uin, void* uout, int z, int y)
+{
+    const orc_problem* p = S->p;
+    const int64_t l = (int64_t)z * p->ny + y;
+    csum ws = {0.0, 0.0};
+    for (int64_t q = 0; q < p->nx; q++)
+        cs_add(&ws, (double)(q + 1) * ld(p->dtype, uin, idx(p, q, y, z)));
+    const double d = S->Bi[l] - S->B[l];
+    const double ratio = (cs_val(ws) - S->W[l]) / d;
+    const double pos = nearbyint(ratio);
+    if (!isfinite(ratio) || fabs(ratio - pos) > 0.25 || pos < 1.0 || pos > (double)p->nx) {
+        S->cnt->mem_unlocated++;
+        emit(S, sweep, ORC_EV_MEM_UNLOCATED, z, y, -1, d, ratio);
+        return 0;
+    }
+    const int x = (int)pos - 1;
+    const int64_t c = idx(p, x, y, z);
+    const double old = ld(p->dtype, uin, c);
+    csum rest = {0.0, 0.0};
+    for (int64_t q = 0; q < p->nx; q++)
+        if (q != x) cs_add(&rest, ld(p->dtype, uin, idx(p, q, y, z)));
+    st(p->dtype, uin, c, S->B[l] - cs_val(rest));
+    S->cnt->mem_corrected++;
+    emit(S, sweep, ORC_EV_MEM_CORRECTED, z, y, x, old, ld(p->dtype, uin, c));
+    const int R = S->reach;
+    for (int oz = -R; oz <= R; oz++)
+        for (int oy = -R; oy <= R; oy++) {
+            const int64_t zz = window_coord(p->bc, z + oz, p->nz);
+            const int64_t yy = window_coord(p->bc, y + oy, p->ny);
+            if (zz < 0 || yy < 0) continue;
+            for (int ox = -R; ox <= R; ox++) {
+                const int64_t xx = window_coord(p->bc, x + ox, p->nx);
+                if (xx < 0) continue;
+                st(p->dtype, uout, idx(p, xx, yy, zz),
+                   point(p, S->w, S->c_scalar, S->C, uin, xx, yy, zz));
+            }
+            recompute_row(S, uout, (int)zz, (int)yy, S->Bn);
+        }
+    return 1;
+}
+
+/* Online ABFT after sweep t (Figure 1 steps 2-3, then Section 3.5), with the input-side check:
+ *   1. the output's row checksums, their prediction from B^t and the input's boundary strips,
+ *      and the row flags (as the sweep reports them);
+ *   2. the input rows as read against B^t; each mismatched row is repaired (repair_input_row);
+ *   3. after a repair, the flagged rows are tested again against predictions from the repaired
+ *      input, and only those still mismatched go on to location and correction. */
+static void online_check(run_state* S, int64_t sweep, void* uin, void* uout)
 {
     const orc_problem* p = S->p;
     const int64_t nrows = (int64_t)p->nz * p->ny;
@@ -495,14 +584,39 @@ static void online_check(run_state* S, int64_t sweep, const void* uin, void* uou
     orc_row_strips(p, uin, S->rs);
     orc_predict_rows(p, S->cB, S->B, S->rs, S->Bp);
     int64_t nf = orc_detect(nrows, S->Bn, S->Bp, S->eps, S->rflag);
-    if (nf == 0) return;
     for (int64_t l = 0; l < nrows; l++)
         if (S->rflag[l]) {
             S->cnt->rows_flagged++;
             emit(S, sweep, ORC_EV_ROW_FLAG, (int)(l / p->ny), (int)(l % p->ny), -1, S->Bn[l],
                  S->Bp[l]);
         }
+    orc_row_checksums(p, uin, S->Bi);
+    const int64_t nm = orc_detect(nrows, S->Bi, S->B, S->eps, S->mflag);
+    for (int64_t l = 0; l < nrows; l++)
+        if (S->mflag[l]) {
+            S->cnt->mem_flagged++;
+            emit(S, sweep, ORC_EV_MEM_FLAG, (int)(l / p->ny), (int)(l % p->ny), -1, S->Bi[l],
+                 S->B[l]);
+        }
     if (!S->auto_correct) return;
+    if (nm > 0) {
+        int repaired = 0;
+        for (int64_t l = 0; l < nrows; l++)
+            if (S->mflag[l])
+                repaired += repair_input_row(S, sweep, uin, uout, (int)(l / p->ny),
+                                             (int)(l % p->ny));
+        if (repaired) {
+            orc_row_strips(p, uin, S->rs);
+            orc_predict_rows(p, S->cB, S->B, S->rs, S->Bp);
+            nf = 0;
+            for (int64_t l = 0; l < nrows; l++) {
+                if (!S->rflag[l]) continue;
+                S->rflag[l] = !(fabs(S->Bn[l] - S->Bp[l]) <= S->eps * fabs(S->Bp[l]));
+                nf += S->rflag[l];
+            }
+        }
+    }
+    if (nf == 0) return;
     /* the second checksum direction, only now that a mismatch was seen */
     orc_col_checksums(p, uin, S->At);
     orc_col_strips(p, uin, S->cs);
@@ -529,7 +643,8 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
     for (int64_t f = 0; f < nfaults; f++) {
         const orc_fault* F = &faults[f];
         if (F->x < 0 || F->x >= p->nx || F->y < 0 || F->y >= p->ny || F->z < 0 ||
-            F->z >= p->nz || F->bit < 0 || F->bit >= bits)
+            F->z >= p->nz || F->bit < 0 || F->bit >= bits ||
+            (F->kind != ORC_FAULT_STORE && F->kind != ORC_FAULT_MEMORY))
             return -3;
     }
     memset(counters, 0, sizeof(*counters));
@@ -562,6 +677,18 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
     S.cs = (double*)calloc((size_t)ncols * 2 * (ry ? ry : 1), sizeof(double));
     S.rflag = (uint8_t*)calloc((size_t)nrows, 1);
     S.cflag = (uint8_t*)calloc((size_t)ncols, 1);
+    S.W = (double*)calloc((size_t)nrows, sizeof(double));
+    S.Wn = (double*)calloc((size_t)nrows, sizeof(double));
+    S.Bi = (double*)calloc((size_t)nrows, sizeof(double));
+    S.mflag = (uint8_t*)calloc((size_t)nrows, 1);
+    S.w = rounded_weights(p);
+    S.c_scalar = round_to(p->dtype, p->c_scalar);
+    for (int k = 0; k < p->ntaps; k++) {
+        const int m = abs(p->taps[k].dx) > abs(p->taps[k].dy) ? abs(p->taps[k].dx)
+                                                               : abs(p->taps[k].dy);
+        if (m > S.reach) S.reach = m;
+        if (abs(p->taps[k].dz) > S.reach) S.reach = abs(p->taps[k].dz);
+    }
     orc_const_row_checksums(p, C, S.cB);
     orc_const_col_checksums(p, C, S.cA);
 
@@ -569,15 +696,24 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
     void* uout = u_b;
 
     if (mode != ORC_MODE_OFFLINE) {
-        if (mode == ORC_MODE_ONLINE) orc_row_checksums(p, uin, S.B);
+        if (mode == ORC_MODE_ONLINE) {
+            orc_row_checksums(p, uin, S.B);
+            orc_weighted_row_checksums(p, uin, S.W);
+        }
         for (int64_t t = 0; t < nsweeps; t++) {
+            inject(&S, uin, t, 0, ORC_FAULT_MEMORY);
             orc_sweep(p, C, uin, uout);
-            inject(&S, uout, t, 0);
+            inject(&S, uout, t, 0, ORC_FAULT_STORE);
             if (mode == ORC_MODE_ONLINE) {
                 online_check(&S, t, uin, uout);
+                /* the checksums of the output as it stands after any repair */
+                orc_weighted_row_checksums(p, uout, S.Wn);
                 double* tmp = S.B;
                 S.B = S.Bn;
                 S.Bn = tmp;
+                tmp = S.W;
+                S.W = S.Wn;
+                S.Wn = tmp;
             }
             void* tu = uin;
             uin = uout;
@@ -603,9 +739,12 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
                 uin = u_a;
                 uout = u_b;
                 for (int64_t j = 0; j < k; j++) {
+                    inject(&S, uin, t0 + j, attempt, ORC_FAULT_MEMORY);
+                    /* the checkpoint is the window's first input in place */
+                    if (j == 0) inject(&S, ckpt, t0, attempt, ORC_FAULT_MEMORY);
                     orc_row_strips(p, uin, hist + j * nrows * 2 * rx);
                     orc_sweep(p, C, uin, uout);
-                    inject(&S, uout, t0 + j, attempt);
+                    inject(&S, uout, t0 + j, attempt, ORC_FAULT_STORE);
                     void* tu = uin;
                     uin = uout;
                     uout = tu;
@@ -664,6 +803,11 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
     free(S.cs);
     free(S.rflag);
     free(S.cflag);
+    free(S.W);
+    free(S.Wn);
+    free(S.Bi);
+    free(S.mflag);
+    free(S.w);
     return 0;
 }
 

@@ -33,14 +33,27 @@ enum {
     ORC_EV_WINDOW_FLAG = 5,    /* offline row mismatch at window end: sweep, z, y, x = attempt */
     ORC_EV_ROLLBACK = 6,       /* offline rollback: sweep = window start, x = window length */
     ORC_EV_PERSISTENT = 7,     /* offline recompute still mismatched: sweep = window end */
-    ORC_EV_COL_FLAG = 8        /* column mismatch during location: sweep, z, x; a, b as above */
+    ORC_EV_COL_FLAG = 8,       /* column mismatch during location: sweep, z, x; a, b as above */
+    ORC_EV_MEM_FLAG = 9,       /* input row of a sweep differs from its stored checksum:
+                                  sweep, z, y; a = sum of the row as read, b = stored B */
+    ORC_EV_MEM_CORRECTED = 10, /* input point repaired: sweep, z, y, x; a = old, b = new */
+    ORC_EV_MEM_UNLOCATED = 11  /* input row mismatch that the weighted sums do not place:
+                                  sweep, z, y; a = row sum difference, b = position ratio */
 };
+
+/* Fault kinds: a flip of the value a sweep stores (Section 5.1), or a flip of the sweep's
+ * input grid in memory, after its checksums were taken and before the sweep reads it (the
+ * first case of Theorem 2's proof). */
+enum { ORC_FAULT_STORE = 0, ORC_FAULT_MEMORY = 1 };
 
 typedef struct { int32_t dx, dy, dz, pad; double w; } orc_tap;
 
 typedef struct {
-    int64_t sweep;              /* sweep t whose stored output u^{t+1} is hit */
+    int64_t sweep;              /* STORE: sweep t whose stored output u^{t+1} is hit;
+                                   MEMORY: sweep t whose input u^t is hit before it is read */
     int32_t z, y, x, bit, attempt, pad;
+    int32_t kind;               /* ORC_FAULT_* */
+    int32_t pad2;
 } orc_fault;
 
 typedef struct {
@@ -71,6 +84,9 @@ typedef struct {
     int64_t rollbacks;
     int64_t persistent;
     int64_t events_total;       /* may exceed the event capacity */
+    int64_t mem_flagged;        /* input rows that differed from their stored checksums */
+    int64_t mem_corrected;
+    int64_t mem_unlocated;
 } orc_counters;
 
 /* Returns 0 when the problem is valid, a negative code otherwise. */
@@ -83,6 +99,11 @@ void orc_sweep(const orc_problem* p, const void* C, const void* uin, void* uout)
 /* Eq.(3) / Eq.(2), per layer, compensated double sums. */
 void orc_row_checksums(const orc_problem* p, const void* u, double* B);
 void orc_col_checksums(const orc_problem* p, const void* u, double* A);
+
+/* Index-weighted row sums W[z][y] = sum_x (x + 1) u[z][y][x], compensated.  Together with
+ * B they place a single changed point of a row: the change d moves B by d and W by
+ * (x + 1) d. */
+void orc_weighted_row_checksums(const orc_problem* p, const void* u, double* W);
 
 /* The constant-term checksums c_y and c_x of Theorem 1. */
 void orc_const_row_checksums(const orc_problem* p, const void* C, double* cB);
@@ -106,10 +127,15 @@ int64_t orc_detect(int64_t n, const double* direct, const double* pred, double e
                    uint8_t* flags);
 
 /* Whole run: nsweeps sweeps from u_a (u_b is scratch of the same size), protected in the given
- * mode (ORC_MODE_*), with the fault plan applied to stored values.  The final grid is left in
- * u_a.  period is the offline window length.  With auto_correct == 0 in offline mode the run
- * stops after the first flagged window (the checkpoint is still valid) and sweeps_done tells
- * where.  Events are written up to max_events.  Returns 0 or a negative code. */
+ * mode (ORC_MODE_*), with the fault plan applied (STORE faults to stored values, MEMORY faults
+ * to a sweep's input grid before it is read).  The final grid is left in u_a.  period is the
+ * offline window length.  With auto_correct == 0 in offline mode the run stops after the first
+ * flagged window (the checkpoint is still valid) and sweeps_done tells where.  Online, each
+ * sweep also compares the sums of its input rows with the stored checksums; a mismatched row
+ * is repaired before the sweep's own flags are examined (see online_check).  Offline, the
+ * checkpoint is the window's first input in place, so a MEMORY fault on a window's first
+ * sweep corrupts the checkpoint too.  Events are written up to max_events.  Returns 0 or a
+ * negative code. */
 int orc_run(const orc_problem* p, const void* C, int mode, int period, double eps,
             int auto_correct, void* u_a, void* u_b, int64_t nsweeps,
             const orc_fault* faults, int64_t nfaults,

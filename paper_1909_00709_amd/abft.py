@@ -26,6 +26,8 @@ ABFT_MODE_NONE, ABFT_MODE_ONLINE, ABFT_MODE_OFFLINE = 0, 1, 2
 ABFT_CSUM_F64, ABFT_CSUM_F32_COMP = 0, 1
 ABFT_EV_ROW_FLAG, ABFT_EV_CORRECTED, ABFT_EV_CHECKSUM_FAULT, ABFT_EV_UNCORRECTABLE = 1, 2, 3, 4
 ABFT_EV_WINDOW_FLAG, ABFT_EV_ROLLBACK, ABFT_EV_PERSISTENT, ABFT_EV_COL_FLAG = 5, 6, 7, 8
+ABFT_EV_MEM_FLAG, ABFT_EV_MEM_CORRECTED, ABFT_EV_MEM_UNLOCATED = 9, 10, 11
+ABFT_FAULT_STORE, ABFT_FAULT_MEMORY = 0, 1
 
 EXPORTED = (
     "abft_stencil_init", "abft_stencil_init_batch", "abft_stencil_step",
@@ -65,12 +67,13 @@ class AbftEvent(ctypes.Structure):
 class AbftFault(ctypes.Structure):
     _fields_ = [("sweep", ctypes.c_int64), ("z", ctypes.c_int32), ("y", ctypes.c_int32),
                 ("x", ctypes.c_int32), ("bit", ctypes.c_int32), ("attempt", ctypes.c_int32),
-                ("grid", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("kind", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 REPORT_COUNTERS = ("sweeps_done", "rows_flagged", "cols_flagged", "corrected",
                    "checksum_faults", "uncorrectable", "windows_checked", "windows_flagged",
-                   "rollbacks", "persistent", "events_total", "pending", "sweeps_skipped")
+                   "rollbacks", "persistent", "events_total", "pending", "sweeps_skipped",
+                   "mem_flagged", "mem_corrected", "mem_unlocated")
 
 
 class AbftReport(ctypes.Structure):
@@ -83,7 +86,7 @@ EVENT_DTYPE = np.dtype([("sweep", "<i8"), ("kind", "<i4"), ("z", "<i4"), ("y", "
                         ("x", "<i4"), ("a", "<f8"), ("b", "<f8"), ("grid", "<i4"),
                         ("pad", "<i4")])
 assert EVENT_DTYPE.itemsize == ctypes.sizeof(AbftEvent)
-assert ctypes.sizeof(AbftFault) == 32
+assert ctypes.sizeof(AbftFault) == 40
 
 _ctx_p = ctypes.c_void_p
 
@@ -188,11 +191,11 @@ def abft_stencil_checksums(ctx, grid: int = 0):
 
 
 def abft_stencil_inject(ctx, plan) -> int:
-    """plan: numpy structured array with the abft_fault layout (32-byte records)."""
+    """plan: numpy structured array with the abft_fault layout (40-byte records)."""
     if plan is None or len(plan) == 0:
         return LIB.abft_stencil_inject(ctx, None, 0)
     plan = np.ascontiguousarray(plan)
-    assert plan.dtype.itemsize == 32
+    assert plan.dtype.itemsize == ctypes.sizeof(AbftFault)
     return LIB.abft_stencil_inject(ctx, plan.ctypes.data_as(ctypes.c_void_p), len(plan))
 
 

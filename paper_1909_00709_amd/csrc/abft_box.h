@@ -272,7 +272,8 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
         // Fault model of Section 5.1 (as in the star sweep).
         for (int f = flo; f < fhi; ++f) {
             const abft_fault F = a.faults[f];
-            if (F.attempt == a.attempt && F.grid == a.grid && F.z == z && F.y == y && row_ok) {
+            if (F.kind == ABFT_FAULT_STORE && F.attempt == a.attempt && F.grid == a.grid &&
+                F.z == z && F.y == y && row_ok) {
 #pragma unroll
                 for (int c = 0; c < NCH; ++c)
 #pragma unroll

@@ -1197,8 +1197,11 @@ abft_status abft_stencil_inject(abft_ctx* c, const abft_fault* f, int32_t n)
             return fail(c, ABFT_E_INVAL, "fault grid index");
         }
         if (x.sweep < 0 || x.z < 0 || x.z >= nz || x.y < 0 || x.y >= ny || x.x < 0 ||
-            x.x >= nx || x.bit < 0 || x.bit >= bits || x.attempt < 0 || x.attempt > 1)
+            x.x >= nx || x.bit < 0 || x.bit >= bits || x.attempt < 0 || x.attempt > 1 ||
+            (x.kind != ABFT_FAULT_STORE && x.kind != ABFT_FAULT_MEMORY))
             return fail(c, ABFT_E_INVAL, "fault outside the grid or word");
+        if (x.kind == ABFT_FAULT_MEMORY && (c->batch || x.attempt != 0))
+            return fail(c, ABFT_E_UNSUPPORTED, "memory faults: single grids, first attempt");
     }
     std::stable_sort(v.begin(), v.end(),
                      [](const abft_fault& a, const abft_fault& b) { return a.sweep < b.sweep; });

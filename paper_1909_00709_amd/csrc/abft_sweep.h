@@ -356,7 +356,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
         // store; the checksum below sees the stored value.
         for (int f = flo; f < fhi; ++f) {
             const abft_fault F = a.faults[f];
-            if (F.attempt == a.attempt && F.grid == a.grid && F.z == z && F.y == y && row_ok) {
+            if (F.kind == ABFT_FAULT_STORE && F.attempt == a.attempt && F.grid == a.grid &&
+                F.z == z && F.y == y && row_ok) {
 #pragma unroll
                 for (int c = 0; c < NCH; ++c)
 #pragma unroll

@@ -19,15 +19,19 @@ from dataclasses import dataclass, field
 import numpy as np
 
 # --------------------------------------------------------------------------------------
-# Fault plan record: one bit flip, applied to the value a sweep stores (Section 5.1).
-# Layout (32 bytes) is part of the C interface of both the library and the oracle.
+# Fault plan record: one bit flip, applied to the value a sweep stores (Section 5.1), or to
+# a sweep's input grid in memory before the sweep reads it.
+# Layout (40 bytes) is part of the C interface of both the library and the oracle.
 # --------------------------------------------------------------------------------------
+FAULT_STORE, FAULT_MEMORY = 0, 1
 FAULT_DTYPE = np.dtype([
-    ("sweep", "<i8"),    # 0-based sweep index t; the flip hits u^{t+1}
+    ("sweep", "<i8"),    # 0-based sweep index t; STORE hits u^{t+1}, MEMORY hits u^t
     ("z", "<i4"), ("y", "<i4"), ("x", "<i4"),
     ("bit", "<i4"),      # bit position in the stored word (0 = LSB)
     ("attempt", "<i4"),  # fires only on this attempt (0 = first run, 1 = offline recompute)
     ("grid", "<i4"),     # grid index in a batch of grids (0 for a single grid)
+    ("kind", "<i4"),     # FAULT_STORE or FAULT_MEMORY
+    ("pad", "<i4"),
 ])
 
 # --------------------------------------------------------------------------------------
@@ -81,12 +85,13 @@ def empty_plan(n: int = 0) -> np.ndarray:
 
 
 def make_plan(rows) -> np.ndarray:
-    """rows: iterable of (sweep, z, y, x, bit[, attempt])."""
+    """rows: iterable of (sweep, z, y, x, bit[, attempt[, kind]])."""
     rows = list(rows)
     plan = empty_plan(len(rows))
     for i, r in enumerate(rows):
         plan[i]["sweep"], plan[i]["z"], plan[i]["y"], plan[i]["x"], plan[i]["bit"] = r[:5]
         plan[i]["attempt"] = r[5] if len(r) > 5 else 0
+        plan[i]["kind"] = r[6] if len(r) > 6 else FAULT_STORE
     plan.sort(order="sweep", kind="stable")
     return plan
 
