@@ -210,7 +210,10 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
 
     double* tabS = reinterpret_cast<double*>(smem_raw + (size_t)NB * plane_elems * sizeof(T));
     double* tabE = tabS + TY * a.tz;
+    double* tabI = tabE + TY * a.tz;
+    double* tabW = tabI + TY * a.tz;
     const bool keep_e = MODE == MODE_PROT || a.E != nullptr;
+    const bool memchk = MODE == MODE_PROT && a.Wn != nullptr;
     using Acc = T;
 
     for (int z = z0; z < z1; ++z) {
@@ -300,23 +303,29 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
         }
 
         if constexpr (MODE != MODE_PLAIN) {
-            double S;
-            if constexpr (CS == CS_F64) {
-                double p = 0.0;
-#pragma unroll
-                for (int c = 0; c < NCH; ++c)
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) p += (double)o[c][v];
-                S = segment_total<LPR>(row16_sum(p));
-            } else {
-                CPair p{0.f, 0.f};
-#pragma unroll
-                for (int c = 0; c < NCH; ++c)
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) p = cpair_add1(p, (float)o[c][v]);
-                S = segment_total<LPR>(row16_pair(p));
-            }
+            const double S = row_sum<CS, LPR, NCH, VEC>(o);
             if (row_ok && sl == 0) tabS[r * a.tz + (z - z0)] = S;
+        }
+        if (memchk) {
+            // the input row as read (from the ring) and the output's index-weighted sum, as in
+            // the star sweep
+            T ci[NCH][VEC];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int x = c * SEGW + sl * VEC;
+                if (row_ok && x < nx) {
+                    V::load(rows[1][1] + x, ci[c]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) ci[c][v] = T(0);
+                }
+            }
+            const double Si = row_sum<CS, LPR, NCH, VEC>(ci);
+            const double Sw = weighted_row_sum<LPR, NCH, VEC>(o, sl);
+            if (row_ok && sl == 0) {
+                tabI[r * a.tz + (z - z0)] = Si;
+                tabW[r * a.tz + (z - z0)] = Sw;
+            }
         }
         if (keep_e) {
             // x-boundary terms of the nine input rows around (z, y): a shift dx = -1 reads
@@ -373,6 +382,11 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
                             if (any)
                                 bp += wsum * (first ? pre[dz + 1][dy + 1] : brow(z + dz, y + dy));
                         }
+                    if (memchk) {
+                        a.Wn[l] = tabW[r * a.tz + pz];
+                        check_input_row(a, t, z, y, tabI[r * a.tz + pz],
+                                        first ? pre[1][1] : a.Bt[l]);
+                    }
                     const double dlt = fabs(S - bp);
                     if (!(dlt <= a.eps * fabs(bp))) {
                         const unsigned i = atomicAdd(&a.slot->count, 1u);

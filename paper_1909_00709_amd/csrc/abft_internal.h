@@ -10,6 +10,7 @@
 namespace abft {
 
 constexpr int kMaxFlags = 1024;   // flagged rows remembered per sweep for location
+constexpr int kMaxMemFlags = 64;  // mismatched input rows remembered per sweep for repair
 constexpr int kSweepBlock = 256;  // threads per block of the batched sweep (4 wavefronts)
 constexpr int kWideBlockLaneBytes = 64;  // most row bytes per lane for 8-wavefront sweep blocks
 constexpr int kFixBlock = 512;    // threads of the single locate/correct block
@@ -56,10 +57,17 @@ struct RowFlag {
     double direct, pred;
 };
 
+// An input row whose sum as the sweep read it differs from the checksum stored with it.
+struct MemFlag {
+    int32_t z, y;
+};
+
+// Both counts are cleared together by the sweep before the one that fills the slot.
 struct FlagSlot {
-    uint32_t count;
-    uint32_t pad;
+    uint32_t count;               // rows flagged by the output check
+    uint32_t mcount;              // input rows flagged by the input check
     RowFlag rows[kMaxFlags];
+    MemFlag mrows[kMaxMemFlags];
 };
 
 // Device counters; 64-bit so they can be updated with atomicAdd.
@@ -70,6 +78,7 @@ struct Counters {
     unsigned long long noise_bits;  // bit pattern of the largest non-negative noise (double)
     unsigned long long overflow;    // sweeps whose flagged rows exceeded kMaxFlags
     unsigned long long barrier_timeouts;  // recovery grid barriers that gave up waiting
+    unsigned long long mem_flagged, mem_corrected, mem_unlocated;  // input-side check
 };
 
 // Sweep kernel variants.
@@ -91,6 +100,8 @@ struct SweepArgs {
     // checksums
     const double* Bt;       // row checksums of uin (prediction input)
     double* Bn;             // row checksums of uout (written)
+    double* Wn;             // index-weighted row sums of uout (written), or null; when set,
+                            // the protected sweep also checks its input rows against Bt
     const double* cB;       // constant-term row checksums
     double eps;
     FlagSlot* slot;         // flagged rows of this sweep
@@ -110,10 +121,18 @@ struct SweepArgs {
 };
 
 struct FixArgs {
-    const void* uin;
+    const void* uin;        // written only by the repair of input points
     void* uout;
     double* Bn;
     const double* cA;
+    // input-side repair (null Wt: none): the input's checksums and weighted sums, the output's
+    // weighted sums, and what evaluating an output point again needs
+    const double* Bt;
+    const double* Wt;
+    double* Wn;
+    const double* cB;
+    const void* C;
+    double c_scalar;
     Stencil st;
     int32_t nx, ny, nz;
     double eps;
@@ -229,6 +248,13 @@ hipError_t launch_check(const CheckArgs& a, hipStream_t st);
 size_t check_lds_bytes(int ry, int rz);
 hipError_t launch_row_sums(int dtype, const void* u, double cs, int nx, int64_t nrows,
                            double* out, hipStream_t st);
+hipError_t launch_weighted_row_sums(int dtype, const void* u, int nx, int64_t nrows, double* out,
+                                    hipStream_t st);
+// Memory-resident faults of the plan for sweep t (kind MEMORY, first attempt): flip them in
+// the sweep's input grid u before the sweep reads it.
+hipError_t launch_mem_flip(int dtype, void* u, int nx, int ny, const abft_fault* faults,
+                           const int32_t* fault_first, int64_t fault_tmax, const int64_t* t_base,
+                           int64_t t_off, hipStream_t st);
 hipError_t launch_col_sums(int dtype, const void* u, double cs, int nx, int ny, int nz,
                            double* out, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);

@@ -22,6 +22,254 @@ __device__ double block_sum(double v, double* red)
 }
 
 // ------------------------------------------------------------------------------------------
+// Repair of input points changed in memory (found by the sweep's input-side check).
+// ------------------------------------------------------------------------------------------
+
+// G(u, x, y, z): the grid extended by the boundary rule (constant ghosts outside).
+template <typename T>
+__device__ __forceinline__ T ghost_value(const FixArgs& a, const T* u, int x, int y, int z)
+{
+    const int bc = a.st.bc;
+    const int mx = map_coord(x, a.nx, bc), my = map_coord(y, a.ny, bc), mz = map_coord(z, a.nz, bc);
+    if (mx < 0 || my < 0 || mz < 0) return (T)a.st.g;
+    return u[((size_t)mz * a.ny + my) * a.nx + mx];
+}
+
+// Eq.(1) at one point with the operations of the sweep kernels in their order (the constant
+// term, then one fused multiply-add per tap, absent taps adding zero), so that the value is
+// the one the sweep stores for the same input.
+template <typename T, int RAD, int BOX>
+__device__ T point_value(const FixArgs& a, const T* u, int x, int y, int z)
+{
+    const size_t i = ((size_t)z * a.ny + y) * a.nx + x;
+    T acc = a.C != nullptr ? static_cast<const T*>(a.C)[i] : (T)a.c_scalar;
+    if constexpr (BOX) {
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int sl = box_slot(dx, dy, dz);
+                    const bool on = (a.st.bmask >> sl) & 1u;
+                    acc = fma((T)a.st.wb[sl], on ? ghost_value(a, u, x + dx, y + dy, z + dz) : T(0),
+                              acc);
+                }
+    } else {
+        auto tap = [&](int slot, int dx, int dy, int dz) {
+            const bool on = (a.st.mask >> slot) & 1u;
+            acc = fma((T)a.st.w[slot], on ? ghost_value(a, u, x + dx, y + dy, z + dz) : T(0), acc);
+        };
+        tap(W_C, 0, 0, 0);
+        for (int d = 1; d <= RAD; ++d) {
+            tap(w_slot(0, d, -1), -d, 0, 0);
+            tap(w_slot(0, d, 1), d, 0, 0);
+            tap(w_slot(1, d, -1), 0, -d, 0);
+            tap(w_slot(1, d, 1), 0, d, 0);
+            tap(w_slot(2, d, -1), 0, 0, -d);
+            tap(w_slot(2, d, 1), 0, 0, d);
+        }
+    }
+    return acc;
+}
+
+// x-boundary term of Theorem 1 for a shift dx (|dx| <= 2) of input row (z, y), which may lie
+// outside the grid (a row of constant ghosts has none): dx < 0 reads G(dx .. -1) and drops
+// u(nx+dx .. nx-1); dx > 0 reads G(nx .. nx+dx-1) and drops u(0 .. dx-1).
+template <typename T>
+__device__ double row_boundary_term(const FixArgs& a, const T* u, int z, int y, int dx)
+{
+    if (map_coord(z, a.nz, a.st.bc) < 0 || map_coord(y, a.ny, a.st.bc) < 0) return 0.0;
+    double b = 0.0;
+    if (dx < 0)
+        for (int q = 1; q <= -dx; ++q)
+            b += (double)ghost_value(a, u, -q, y, z) - (double)ghost_value(a, u, a.nx - q, y, z);
+    else
+        for (int q = 0; q < dx; ++q)
+            b += (double)ghost_value(a, u, a.nx + q, y, z) - (double)ghost_value(a, u, q, y, z);
+    return b;
+}
+
+// Theorem 1's prediction of output row (z, y) from the input's checksums and boundary values,
+// as the sweep forms it.
+template <typename T, int RAD, int BOX>
+__device__ double predict_row(const FixArgs& a, const T* u, int z, int y)
+{
+    const int bc = a.st.bc, nx = a.nx;
+    auto brow = [&](int z2, int y2) -> double {
+        const int mz = map_coord(z2, a.nz, bc), my = map_coord(y2, a.ny, bc);
+        if (mz < 0 || my < 0) return (double)nx * a.st.g;
+        return a.Bt[(size_t)mz * a.ny + my];
+    };
+    const size_t l = (size_t)z * a.ny + y;
+    double bp = a.cB[l];
+    if constexpr (BOX) {
+        double e = 0.0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int sm = box_slot(-1, dy, dz), sp = box_slot(1, dy, dz);
+                if ((a.st.bmask >> sm) & 1u) e += a.st.wb[sm] * row_boundary_term(a, u, z + dz, y + dy, -1);
+                if ((a.st.bmask >> sp) & 1u) e += a.st.wb[sp] * row_boundary_term(a, u, z + dz, y + dy, 1);
+            }
+        bp += e;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy) {
+                double wsum = 0.0;
+                bool any = false;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int sl = box_slot(dx, dy, dz);
+                    if ((a.st.bmask >> sl) & 1u) {
+                        wsum += a.st.wb[sl];
+                        any = true;
+                    }
+                }
+                if (any) bp += wsum * brow(z + dz, y + dy);
+            }
+    } else {
+        const uint32_t m = a.st.mask;
+        const double b0 = a.Bt[l];
+        if (m & (1u << W_C)) bp += a.st.w[W_C] * b0;
+        double e = 0.0;
+        for (int d = 1; d <= RAD; ++d) {
+            if (m & (1u << w_slot(0, d, -1))) {
+                bp += a.st.w[w_slot(0, d, -1)] * b0;
+                e += a.st.w[w_slot(0, d, -1)] * row_boundary_term(a, u, z, y, -d);
+            }
+            if (m & (1u << w_slot(0, d, 1))) {
+                bp += a.st.w[w_slot(0, d, 1)] * b0;
+                e += a.st.w[w_slot(0, d, 1)] * row_boundary_term(a, u, z, y, d);
+            }
+        }
+        bp += e;
+        for (int d = 1; d <= RAD; ++d) {
+            if (m & (1u << w_slot(1, d, -1))) bp += a.st.w[w_slot(1, d, -1)] * brow(z, y - d);
+            if (m & (1u << w_slot(1, d, 1))) bp += a.st.w[w_slot(1, d, 1)] * brow(z, y + d);
+            if (m & (1u << w_slot(2, d, -1))) bp += a.st.w[w_slot(2, d, -1)] * brow(z - d, y);
+            if (m & (1u << w_slot(2, d, 1))) bp += a.st.w[w_slot(2, d, 1)] * brow(z + d, y);
+        }
+    }
+    return bp;
+}
+
+// Output coordinate of the repair window: periodic wraps; the other rules have no outputs
+// outside the grid (an output that reads a clamped edge point lies inside the window).
+__device__ __forceinline__ int window_coord(int c, int n, int bc)
+{
+    if (c >= 0 && c < n) return c;
+    return bc == ABFT_BC_PERIODIC ? map_coord(c, n, bc) : -1;
+}
+
+// Sum and index-weighted sum of one row, by the whole block (fixed order).
+template <typename T>
+__device__ void block_row_sums(const T* row, int nx, double* red, double* s, double* w)
+{
+    double ps = 0.0, pw = 0.0;
+    for (int x = threadIdx.x; x < nx; x += kFixBlock) {
+        const double v = (double)row[x];
+        ps += v;
+        pw = fma((double)(x + 1), v, pw);
+    }
+    *s = block_sum(ps, red);
+    *w = block_sum(pw, red);
+}
+
+// The sweep's input-side check flagged input rows: the row's sum changed by d = S - B^t, its
+// index-weighted sum by (x + 1) d for a single changed point, which places it; the value comes
+// back from B^t and the other points of the row (the partial-sum form used for Eq.(10)); the
+// outputs of the sweep in the window of the stencil's reach around the point are evaluated
+// again, and the checksums of the output rows in the window recomputed.  Returns the number of
+// points repaired (the same in every thread).
+template <typename T, int RAD, int BOX>
+__device__ int repair_inputs(const FixArgs& a, double* red, int64_t t)
+{
+    FlagSlot* slot = a.slot;
+    const unsigned m_all = slot->mcount;
+    if (m_all == 0u || a.Wt == nullptr) return 0;
+    const int tid = threadIdx.x;
+    if (m_all > (unsigned)kMaxMemFlags) {
+        if (tid == 0) {
+            atomicAdd(&a.cnt->uncorrectable, 1ull);
+            emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_UNCORRECTABLE, -1, -1, -1,
+                       (double)m_all, 1.0, a.grid);
+        }
+        return 0;
+    }
+    const int m = (int)m_all;
+    if (tid == 0) {  // order by (z, y)
+        for (int i = 1; i < m; ++i) {
+            const MemFlag key = slot->mrows[i];
+            int j = i - 1;
+            while (j >= 0 && (slot->mrows[j].z > key.z ||
+                              (slot->mrows[j].z == key.z && slot->mrows[j].y > key.y))) {
+                slot->mrows[j + 1] = slot->mrows[j];
+                --j;
+            }
+            slot->mrows[j + 1] = key;
+        }
+    }
+    __syncthreads();
+    T* uin = static_cast<T*>(const_cast<void*>(a.uin));
+    T* uout = static_cast<T*>(a.uout);
+    const int nx = a.nx, ny = a.ny, nz = a.nz, bc = a.st.bc;
+    constexpr int R = BOX ? 1 : RAD;
+    constexpr int NWIN = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
+    static_assert(NWIN <= kFixBlock, "one thread per point of the repair window");
+    int nrep = 0;
+    for (int i = 0; i < m; ++i) {
+        const int z = slot->mrows[i].z, y = slot->mrows[i].y;
+        const size_t l = (size_t)z * ny + y;
+        T* row = uin + l * nx;
+        double S, Wr;
+        block_row_sums(row, nx, red, &S, &Wr);
+        const double d = S - a.Bt[l];
+        const double ratio = (Wr - a.Wt[l]) / d;
+        const double pos = rint(ratio);
+        if (!isfinite(ratio) || fabs(ratio - pos) > 0.25 || pos < 1.0 || pos > (double)nx) {
+            if (tid == 0) {
+                atomicAdd(&a.cnt->mem_unlocated, 1ull);
+                emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_MEM_UNLOCATED, z, y, -1, d, ratio,
+                           a.grid);
+            }
+            continue;
+        }
+        const int x = (int)pos - 1;
+        double p = 0.0;
+        for (int q = tid; q < nx; q += kFixBlock)
+            if (q != x) p += (double)row[q];
+        const double rest = block_sum(p, red);
+        if (tid == 0) {
+            const T old = row[x];
+            row[x] = (T)(a.Bt[l] - rest);
+            atomicAdd(&a.cnt->mem_corrected, 1ull);
+            emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_MEM_CORRECTED, z, y, x, (double)old,
+                       (double)row[x], a.grid);
+        }
+        __syncthreads();
+        if (tid < NWIN) {
+            const int ox = tid % (2 * R + 1) - R, oy = (tid / (2 * R + 1)) % (2 * R + 1) - R,
+                      oz = tid / ((2 * R + 1) * (2 * R + 1)) - R;
+            const int xx = window_coord(x + ox, nx, bc), yy = window_coord(y + oy, ny, bc),
+                      zz = window_coord(z + oz, nz, bc);
+            if (xx >= 0 && yy >= 0 && zz >= 0)
+                uout[((size_t)zz * ny + yy) * nx + xx] = point_value<T, RAD, BOX>(a, uin, xx, yy, zz);
+        }
+        __syncthreads();
+        for (int oz = -R; oz <= R; ++oz)
+            for (int oy = -R; oy <= R; ++oy) {
+                const int yy = window_coord(y + oy, ny, bc), zz = window_coord(z + oz, nz, bc);
+                if (yy < 0 || zz < 0) continue;
+                const size_t lo = (size_t)zz * ny + yy;
+                double So, Wo;
+                block_row_sums(uout + lo * nx, nx, red, &So, &Wo);
+                if (tid == 0) {
+                    a.Bn[lo] = So;
+                    a.Wn[lo] = Wo;
+                }
+            }
+        __syncthreads();
+        ++nrep;
+    }
+    return nrep;
+}
+
+// ------------------------------------------------------------------------------------------
 // Locate and correct after a sweep whose row checks flagged something (Sections 3.4-3.5).
 // One block.  For each layer with flagged rows: the column checksums of the layer (Eq.(2)),
 // their prediction from the input grid (Theorem 1, Eq.(4)), the flagged columns, and the
@@ -32,7 +280,33 @@ template <typename T, int RAD, int BOX>
 __device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* red, int& sh_K)
 {
     FlagSlot* slot = a.slot;
+    if (slot->count == 0u && slot->mcount == 0u) return;  // nothing flagged: the usual case
+    const int64_t t0 = a.t_off + (a.t_base != nullptr ? *a.t_base : 0);
+    // input points changed in memory first: the output rows they reached are then tested
+    // again against predictions from the repaired input, and only rows still mismatched go on
+    const int nrep = repair_inputs<T, RAD, BOX>(a, red, t0);
+    if (nrep > 0 && slot->count > 0u && slot->count <= (unsigned)kMaxFlags) {
+        const int nf = (int)slot->count;
+        int* keep = reinterpret_cast<int*>(smem_raw);  // [kMaxFlags]
+        for (int i = threadIdx.x; i < nf; i += kFixBlock) {
+            RowFlag rf = slot->rows[i];
+            rf.direct = a.Bn[(size_t)rf.z * a.ny + rf.y];
+            rf.pred = predict_row<T, RAD, BOX>(a, static_cast<const T*>(a.uin), rf.z, rf.y);
+            slot->rows[i] = rf;
+            keep[i] = !(fabs(rf.direct - rf.pred) <= a.eps * fabs(rf.pred));
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned k = 0;
+            for (int i = 0; i < nf; ++i)
+                if (keep[i]) slot->rows[k++] = slot->rows[i];
+            slot->count = k;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) slot->mcount = 0u;
     const unsigned n_all = slot->count;
+    __syncthreads();
     if (n_all == 0u) return;
 
     const int nx = a.nx, ny = a.ny, nz = a.nz, bc = a.st.bc;
@@ -296,12 +570,15 @@ __device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* re
                     }
                     __syncthreads();
                 }
-                // checksum update after the correction: the row's direct sum
+                // checksum update after the correction: the row's direct sum (and its
+                // index-weighted sum when the input-side check is on)
                 const T* rowc = uout + (size_t)z * ps + (size_t)y * nx;
-                double p = 0.0;
-                for (int xx = tid; xx < nx; xx += kFixBlock) p += (double)rowc[xx];
-                const double S = block_sum(p, red);
-                if (tid == 0) a.Bn[(size_t)z * ny + y] = S;
+                double S, Wr;
+                block_row_sums(rowc, nx, red, &S, &Wr);
+                if (tid == 0) {
+                    a.Bn[(size_t)z * ny + y] = S;
+                    if (a.Wn != nullptr) a.Wn[(size_t)z * ny + y] = Wr;
+                }
             }
         }
         __syncthreads();
@@ -560,6 +837,41 @@ __global__ void __launch_bounds__(256) row_sums_kernel(const T* u, double cs, in
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256) weighted_row_sums_kernel(const T* u, int nx,
+                                                                 int64_t nrows, double* out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= nrows) return;
+    double p = 0.0;
+    for (int x = lane; x < nx; x += 64) p = fma((double)(x + 1), (double)u[row * nx + x], p);
+    const double s = wave_sum(p);
+    if (lane == 0) out[row] = s;
+}
+
+// Memory-resident faults of the plan for one sweep: XOR the bit into the sweep's input grid
+// before the sweep reads it (kind MEMORY, first attempt, grid 0).  One wavefront walks the
+// sweep's entries.
+template <typename T>
+__global__ void __launch_bounds__(64) mem_flip_kernel(T* u, int nx, int ny,
+                                                       const abft_fault* faults,
+                                                       const int32_t* first, int64_t tmax,
+                                                       const int64_t* t_base, int64_t t_off)
+{
+    const int64_t t = t_off + (t_base != nullptr ? *t_base : 0);
+    if (t < 0 || t >= tmax) return;
+    for (int f = first[t] + (int)threadIdx.x; f < first[t + 1]; f += 64) {
+        const abft_fault F = faults[f];
+        if (F.kind != ABFT_FAULT_MEMORY || F.attempt != 0 || F.grid != 0) continue;
+        T* p = u + ((size_t)F.z * ny + F.y) * nx + F.x;
+        if constexpr (sizeof(T) == 4)
+            *p = __builtin_bit_cast(T, __builtin_bit_cast(uint32_t, *p) ^ (1u << F.bit));
+        else
+            *p = __builtin_bit_cast(T, __builtin_bit_cast(uint64_t, *p) ^ (1ull << F.bit));
+    }
+}
+
+template <typename T>
 __global__ void __launch_bounds__(256) col_sums_kernel(const T* u, double cs, int nx, int ny,
                                                         int nz, double* out)
 {
@@ -614,7 +926,7 @@ size_t sweep_lds_bytes(int dtype, int nx, const SweepShape& s)
     const size_t pad = (size_t)std::max(s.vec, s.rad);
     const size_t planes = s.box ? 3 : 2;  // the box sweep keeps a ring of three planes
     return planes * (ty + 2 * s.rad) * (nx + 2 * pad) * es  // plane buffers with halo rows
-           + 2 * ty * (size_t)s.tz * sizeof(double);         // checksum and boundary tables
+           + 4 * ty * (size_t)s.tz * sizeof(double);  // checksum, boundary, input, weighted
 }
 
 hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, const SweepArgs& a,
@@ -673,7 +985,9 @@ hipError_t launch_recover(int dtype, int csum, const SweepShape& s, const Recove
 
 size_t fixup_lds_bytes(int nx, bool box)
 {
-    return (size_t)nx * ((box ? 12 : 3) * sizeof(double) + 2 * sizeof(int));
+    // the column tables of the layer, or the keep flags of the re-test after an input repair
+    return std::max((size_t)nx * ((box ? 12 : 3) * sizeof(double) + 2 * sizeof(int)),
+                    (size_t)kMaxFlags * sizeof(int));
 }
 
 hipError_t launch_fixup_batch(int dtype, const BatchArgs& b, int maxnx, hipStream_t st)
@@ -745,6 +1059,35 @@ hipError_t launch_row_sums(int dtype, const void* u, double cs, int nx, int64_t 
     else
         hipLaunchKernelGGL(row_sums_kernel<double>, grid, dim3(256), 0, st,
                            static_cast<const double*>(u), cs, nx, nrows, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_weighted_row_sums(int dtype, const void* u, int nx, int64_t nrows, double* out,
+                                    hipStream_t st)
+{
+    const dim3 grid((unsigned)((nrows + 3) / 4));
+    if (dtype == ABFT_F32)
+        hipLaunchKernelGGL(weighted_row_sums_kernel<float>, grid, dim3(256), 0, st,
+                           static_cast<const float*>(u), nx, nrows, out);
+    else
+        hipLaunchKernelGGL(weighted_row_sums_kernel<double>, grid, dim3(256), 0, st,
+                           static_cast<const double*>(u), nx, nrows, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mem_flip(int dtype, void* u, int nx, int ny, const abft_fault* faults,
+                           const int32_t* fault_first, int64_t fault_tmax, const int64_t* t_base,
+                           int64_t t_off, hipStream_t st)
+{
+    if (faults == nullptr || fault_first == nullptr || fault_tmax <= 0) return hipSuccess;
+    if (dtype == ABFT_F32)
+        hipLaunchKernelGGL(mem_flip_kernel<float>, dim3(1), dim3(64), 0, st,
+                           static_cast<float*>(u), nx, ny, faults, fault_first, fault_tmax,
+                           t_base, t_off);
+    else
+        hipLaunchKernelGGL(mem_flip_kernel<double>, dim3(1), dim3(64), 0, st,
+                           static_cast<double*>(u), nx, ny, faults, fault_first, fault_tmax,
+                           t_base, t_off);
     return hipGetLastError();
 }
 

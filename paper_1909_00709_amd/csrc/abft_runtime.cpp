@@ -53,6 +53,7 @@ struct abft_ctx {
     // workspace
     std::vector<void*> allocs;
     double* B[2] = {nullptr, nullptr};
+    double* W[2] = {nullptr, nullptr};  // online: index-weighted row sums beside B
     double* cB = nullptr;
     double* cA = nullptr;
     FlagSlot* slot[2] = {nullptr, nullptr};
@@ -68,6 +69,7 @@ struct abft_ctx {
     int32_t* fault_first = nullptr;
     int64_t fault_tmax = 0;
     int nfaults = 0;
+    bool mem_faults = false;     // the plan holds memory-resident flips
     // launch shapes
     SweepShape shape{};
     int nyb = 0, nzb = 0, ntiles = 0;
@@ -410,6 +412,36 @@ bool need_boundary_terms(const abft_ctx* c)
 int buf_of(const abft_ctx* c, int j) { return j == 0 ? c->ckpt : ((j & 1) ? c->wq : c->wr); }
 
 // ---- online / plain ------------------------------------------------------------------------
+// Locate/correct and input repair after online sweep t, whose input is u[in] with checksums
+// B[bin] and whose output is u[in ^ 1] with checksums B[bin ^ 1].
+FixArgs online_fix_args(const abft_ctx* c, int in, int bin, int64_t t, const int64_t* tbase,
+                        int64_t t_off)
+{
+    FixArgs f{};
+    f.uin = c->u[in];
+    f.uout = c->u[in ^ 1];
+    f.Bn = c->B[bin ^ 1];
+    f.cA = c->cA;
+    f.Bt = c->B[bin];
+    f.Wt = c->W[bin];
+    f.Wn = c->W[bin ^ 1];
+    f.cB = c->cB;
+    f.C = c->C;
+    f.c_scalar = c->cs;
+    f.st = c->st;
+    f.nx = c->nx;
+    f.ny = c->ny;
+    f.nz = c->nz;
+    f.eps = c->eps;
+    f.slot = c->slot[t & 1];
+    f.cnt = c->cnt;
+    f.ev = c->ev;
+    f.ev_cap = c->ev_cap;
+    f.t_base = tbase;
+    f.t_off = t_off;
+    return f;
+}
+
 abft_status enqueue_online(abft_ctx* c, int64_t n, const int64_t* tbase, int64_t t0)
 {
     for (int64_t i = 0; i < n; ++i) {
@@ -424,29 +456,21 @@ abft_status enqueue_online(abft_ctx* c, int64_t n, const int64_t* tbase, int64_t
             mode = MODE_PROT;
             a.Bt = c->B[c->bcur];
             a.Bn = c->B[c->bcur ^ 1];
+            a.Wn = c->W[c->bcur ^ 1];
             a.slot = c->slot[t & 1];
             a.zero_ptr = &c->slot[(t + 1) & 1]->count;
-            a.zero_n = 1;
+            a.zero_n = 2;  // the next sweep's row and input-row counts
         }
-        hipError_t e = launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream);
+        hipError_t e;
+        if (c->mem_faults) {
+            e = launch_mem_flip(c->dtype, c->u[c->cur], c->nx, c->ny, c->faults, c->fault_first,
+                                c->fault_tmax, tbase, a.t_off, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "memory fault launch");
+        }
+        e = launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
         if (c->mode == ABFT_MODE_ONLINE && c->auto_correct) {
-            FixArgs f{};
-            f.uin = c->u[c->cur];
-            f.uout = c->u[c->cur ^ 1];
-            f.Bn = c->B[c->bcur ^ 1];
-            f.cA = c->cA;
-            f.st = c->st;
-            f.nx = c->nx;
-            f.ny = c->ny;
-            f.nz = c->nz;
-            f.eps = c->eps;
-            f.slot = c->slot[t & 1];
-            f.cnt = c->cnt;
-            f.ev = c->ev;
-            f.ev_cap = c->ev_cap;
-            f.t_base = tbase;
-            f.t_off = a.t_off;
+            const FixArgs f = online_fix_args(c, c->cur, c->bcur, t, tbase, a.t_off);
             e = launch_fixup(c->dtype, f, c->stream);
             if (e != hipSuccess) return hip_fail(c, e, "locate/correct launch");
         }
@@ -473,7 +497,14 @@ abft_status offline_sweep(abft_ctx* c, int j, int k, int attempt, const uint32_t
         a.zero_n = 2;
     }
     const int mode = (j == k - 1) ? MODE_CSUM : MODE_PLAIN;
-    hipError_t e = launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream);
+    hipError_t e;
+    if (c->mem_faults && attempt == 0) {
+        // the window's first input is the checkpoint itself
+        e = launch_mem_flip(c->dtype, c->u[buf_of(c, j)], c->nx, c->ny, c->faults,
+                            c->fault_first, c->fault_tmax, nullptr, a.t_off, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "memory fault launch");
+    }
+    e = launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "offline sweep launch");
     return ABFT_OK;
 }
@@ -945,6 +976,9 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
         (s = dalloc(c, &c->ticket, 4 * sizeof(uint32_t))) ||
         (s = dalloc(c, &c->tbase, sizeof(int64_t))))
         return bail(s);
+    if (c->mode == ABFT_MODE_ONLINE &&
+        ((s = dalloc(c, &c->W[0], nrows * 8)) || (s = dalloc(c, &c->W[1], nrows * 8))))
+        return bail(s);
     if (c->mode == ABFT_MODE_OFFLINE) {
         if (p->u2 != nullptr) {
             if (p->u2 == p->u0 || p->u2 == p->u1)
@@ -978,6 +1012,9 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
     INIT_CHK(launch_row_sums(c->dtype, c->C, c->cs, c->nx, (int64_t)nrows, c->cB, c->stream));
     INIT_CHK(launch_col_sums(c->dtype, c->C, c->cs, c->nx, c->ny, c->nz, c->cA, c->stream));
     INIT_CHK(launch_row_sums(c->dtype, c->u[0], 0.0, c->nx, (int64_t)nrows, c->B[0], c->stream));
+    if (c->W[0] != nullptr)
+        INIT_CHK(launch_weighted_row_sums(c->dtype, c->u[0], c->nx, (int64_t)nrows, c->W[0],
+                                          c->stream));
     INIT_CHK(hipStreamSynchronize(c->stream));
 #undef INIT_CHK
     *out = c;
@@ -1067,9 +1104,9 @@ abft_status abft_stencil_check(abft_ctx* c, abft_report* out)
             pending += n;
         }
     } else if (c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
-        uint32_t n = 0;
-        HIPCHK(c, hipMemcpy(&n, &c->slot[(c->t - 1) & 1]->count, 4, hipMemcpyDeviceToHost));
-        pending = n;
+        uint32_t n[2] = {0, 0};  // flagged output rows, flagged input rows
+        HIPCHK(c, hipMemcpy(n, &c->slot[(c->t - 1) & 1]->count, 8, hipMemcpyDeviceToHost));
+        pending = (int64_t)n[0] + n[1];
     } else if (c->halted) {
         uint32_t n = 0;
         HIPCHK(c, hipMemcpy(&n, c->win + 2 * (c->win_index & 1), 4, hipMemcpyDeviceToHost));
@@ -1089,6 +1126,9 @@ abft_status abft_stencil_check(abft_ctx* c, abft_report* out)
         out->events_total = (int64_t)h.events_total;
         out->pending = pending;
         out->sweeps_skipped = c->skipped;
+        out->mem_flagged = (int64_t)h.mem_flagged;
+        out->mem_corrected = (int64_t)h.mem_corrected;
+        out->mem_unlocated = (int64_t)h.mem_unlocated;
         double nm = 0.0;
         std::memcpy(&nm, &h.noise_bits, sizeof(nm));
         out->max_noise = nm;
@@ -1118,21 +1158,7 @@ abft_status abft_stencil_correct(abft_ctx* c, abft_report* inout)
         if (e != hipSuccess) return hip_fail(c, e, "batched locate/correct launch");
     } else if (c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
         const int64_t t = c->t - 1;
-        FixArgs f{};
-        f.uin = c->u[c->cur ^ 1];
-        f.uout = c->u[c->cur];
-        f.Bn = c->B[c->bcur];
-        f.cA = c->cA;
-        f.st = c->st;
-        f.nx = c->nx;
-        f.ny = c->ny;
-        f.nz = c->nz;
-        f.eps = c->eps;
-        f.slot = c->slot[t & 1];
-        f.cnt = c->cnt;
-        f.ev = c->ev;
-        f.ev_cap = c->ev_cap;
-        f.t_off = t;
+        const FixArgs f = online_fix_args(c, c->cur ^ 1, c->bcur ^ 1, t, nullptr, t);
         hipError_t e = launch_fixup(c->dtype, f, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "locate/correct launch");
     } else if (c->mode == ABFT_MODE_OFFLINE && c->halted) {
@@ -1217,6 +1243,7 @@ abft_status abft_stencil_inject(abft_ctx* c, const abft_fault* f, int32_t n)
     c->fault_first = nullptr;
     c->fault_tmax = 0;
     c->nfaults = 0;
+    c->mem_faults = false;
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
     if (n == 0) return ABFT_OK;
@@ -1238,6 +1265,8 @@ abft_status abft_stencil_inject(abft_ctx* c, const abft_fault* f, int32_t n)
                         hipMemcpyHostToDevice));
     c->fault_tmax = tmax;
     c->nfaults = n;
+    c->mem_faults = std::any_of(v.begin(), v.end(),
+                                [](const abft_fault& x) { return x.kind == ABFT_FAULT_MEMORY; });
     return ABFT_OK;
 }
 
@@ -1252,10 +1281,11 @@ abft_status abft_stencil_autotune(abft_ctx* c)
     FlagSlot* sslot = nullptr;
     Counters* scnt = nullptr;
     double* sB = nullptr;
+    double* sW = nullptr;
     abft_status s;
     const size_t nrows = (size_t)c->nz * c->ny;
     if ((s = dalloc(c, &sslot, sizeof(FlagSlot))) || (s = dalloc(c, &scnt, sizeof(Counters))) ||
-        (s = dalloc(c, &sB, nrows * 8)))
+        (s = dalloc(c, &sB, nrows * 8)) || (s = dalloc(c, &sW, nrows * 8)))
         return s;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
@@ -1299,6 +1329,7 @@ abft_status abft_stencil_autotune(abft_ctx* c)
         a.slot = sslot;
         a.Bt = c->mode == ABFT_MODE_OFFLINE ? c->B[c->bck] : c->B[c->bcur];
         a.Bn = sB;
+        if (mode == MODE_PROT) a.Wn = sW;  // timed with the input-side check
         a.t_off = c->t;
         bool ok = true;
         for (int w = 0; w < 2 && ok; ++w)
@@ -1327,7 +1358,8 @@ abft_status abft_stencil_autotune(abft_ctx* c)
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    for (void* p : {static_cast<void*>(sslot), static_cast<void*>(scnt), static_cast<void*>(sB)}) {
+    for (void* p : {static_cast<void*>(sslot), static_cast<void*>(scnt), static_cast<void*>(sB),
+                    static_cast<void*>(sW)}) {
         auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
         if (it != c->allocs.end()) c->allocs.erase(it);
         (void)hipFree(p);

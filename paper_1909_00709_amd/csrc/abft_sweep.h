@@ -27,6 +27,64 @@ namespace abft {
 // registers, lower occupancy).  The fp32 chain is kept.
 constexpr bool kStencilAccF64 = false;
 
+// Sum of a row held by LPR lanes, NCH chunks of VEC values per lane: each lane adds its values
+// in chunk order, then the row's lanes are reduced in a fixed order.  Every lane must call it.
+template <int CS, int LPR, int NCH, int VEC, typename T>
+__device__ __forceinline__ double row_sum(const T (&d)[NCH][VEC])
+{
+    if constexpr (CS == CS_F64) {
+        double p = 0.0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) p += (double)d[c][v];
+        return segment_total<LPR>(row16_sum(p));
+    } else {
+        CPair p{0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) p = cpair_add1(p, (float)d[c][v]);
+        return segment_total<LPR>(row16_pair(p));
+    }
+}
+
+// Index-weighted row sum, sum over x of (x + 1) u(x), in fp64 (values past the row end are
+// zero).  Every lane must call it.
+template <int LPR, int NCH, int VEC, typename T>
+__device__ __forceinline__ double weighted_row_sum(const T (&d)[NCH][VEC], int sl)
+{
+    double p = 0.0;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+            p = fma((double)(c * LPR * VEC + sl * VEC + v + 1), (double)d[c][v], p);
+    return segment_total<LPR>(row16_sum(p));
+}
+
+// The input-side check of one row (the first case in the proof of Theorem 2: a value changed
+// in memory after its checksum was taken): the row's sum as read against the stored checksum,
+// with the threshold test of Section 3.4.  A mismatch is remembered for the repair.
+__device__ __forceinline__ void check_input_row(const SweepArgs& a, int64_t t, int z, int y,
+                                                double sum_read, double stored)
+{
+    if (!(fabs(sum_read - stored) <= a.eps * fabs(stored))) {
+        const unsigned i = atomicAdd(&a.slot->mcount, 1u);
+        if (i < (unsigned)kMaxMemFlags) {
+            MemFlag mf;
+            mf.z = z;
+            mf.y = y;
+            a.slot->mrows[i] = mf;
+        } else {
+            atomicAdd(&a.cnt->overflow, 1ull);
+        }
+        atomicAdd(&a.cnt->mem_flagged, 1ull);
+        emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_MEM_FLAG, z, y, -1, sum_read, stored,
+                   a.grid);
+    }
+}
+
 // One tile (TY rows x tz planes) of one sweep, run by one block.  smem_raw is the block's
 // dynamic LDS (sweep_lds_bytes).
 template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF, int NW, int RAD>
@@ -249,10 +307,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             load_halo(hn, z0 + 1);
         }
     }
-    // checksum and boundary-term table: [TY][tz] doubles each, after the two plane buffers
+    // checksum, boundary-term, input-sum and weighted-sum tables: [TY][tz] doubles each,
+    // after the two plane buffers
     double* tabS = reinterpret_cast<double*>(smem_raw + (size_t)2 * plane_elems * sizeof(T));
     double* tabE = tabS + TY * a.tz;
+    double* tabI = tabE + TY * a.tz;
+    double* tabW = tabI + TY * a.tz;
     const bool keep_e = MODE == MODE_PROT || a.E != nullptr;
+    const bool memchk = MODE == MODE_PROT && a.Wn != nullptr;
 
     for (int z = z0; z < z1; ++z) {
         // planes ahead in flight while this one is computed
@@ -388,23 +450,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
         // the ghosts).  Both go to a small LDS table; the prediction and the comparison for
         // all planes of the tile run after the march, so none of their loads sits in this loop.
         if constexpr (MODE != MODE_PLAIN) {
-            double S;
-            if constexpr (CS == CS_F64) {
-                double p = 0.0;
-#pragma unroll
-                for (int c = 0; c < NCH; ++c)
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) p += (double)o[c][v];
-                S = segment_total<LPR>(row16_sum(p));
-            } else {
-                CPair p{0.f, 0.f};
-#pragma unroll
-                for (int c = 0; c < NCH; ++c)
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) p = cpair_add1(p, (float)o[c][v]);
-                S = segment_total<LPR>(row16_pair(p));
-            }
+            const double S = row_sum<CS, LPR, NCH, VEC>(o);
             if (row_ok && sl == 0) tabS[r * a.tz + (z - z0)] = S;
+        }
+        if (memchk) {
+            // the input row as this sweep read it, summed like the output row (the stored
+            // checksum it is compared with after the march was formed the same way), and the
+            // index-weighted sum of the output row, which places a changed point later
+            const double Si = row_sum<CS, LPR, NCH, VEC>(pl[RAD]);
+            const double Sw = weighted_row_sum<LPR, NCH, VEC>(o, sl);
+            if (row_ok && sl == 0) {
+                tabI[r * a.tz + (z - z0)] = Si;
+                tabW[r * a.tz + (z - z0)] = Sw;
+            }
         }
         if (keep_e && row_ok && sl == 0) {
             // shift dx < 0 reads G(dx .. -1) and drops u(nx+dx .. nx-1); dx > 0 reads
@@ -491,6 +549,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                             bp += a.st.w[w_slot(2, d, -1)] * (first ? pfz[d - 1][0] : brow(z - d, y));
                         if (has(w_slot(2, d, 1)))
                             bp += a.st.w[w_slot(2, d, 1)] * (first ? pfz[d - 1][1] : brow(z + d, y));
+                    }
+                    if (memchk) {
+                        a.Wn[l] = tabW[r * a.tz + pz];
+                        check_input_row(a, t, z, y, tabI[r * a.tz + pz], b0);
                     }
                     // Section 3.4, written so that NaN and Inf mismatches are flagged
                     const double dlt = fabs(S - bp);

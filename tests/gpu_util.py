@@ -10,7 +10,8 @@ import oracle as O
 import workloads as W
 
 KIND_NAMES = {1: "row", 2: "corrected", 3: "checksum", 4: "uncorrectable", 5: "window",
-              6: "rollback", 7: "persistent", 8: "col"}
+              6: "rollback", 7: "persistent", 8: "col", 9: "mem", 10: "mem_corrected",
+              11: "mem_unlocated"}
 
 
 def say(*args):
@@ -59,7 +60,7 @@ def run_oracle(u0, taps, nsweeps, *, C=None, c_scalar=0.0, mode="online", eps=1e
                  auto_correct=auto_correct, faults=plan)
 
 
-def event_keys(ev, kinds=(1, 2, 3, 4, 5, 6, 7, 8), skip=None):
+def event_keys(ev, kinds=(1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11), skip=None):
     """Set of (kind, sweep, z, y, x) for the selected kinds; skip(e) drops marginal entries."""
     out = set()
     for e in ev:
