@@ -144,7 +144,7 @@ def bench_configs(stream, timed, tune=True):
                 # "prot": the protected sweep kernel alone (online, no locate launches)
                 S = abft.Stencil(u, w.taps, C=C, mode="online" if mode == "prot" else mode,
                                  threshold=eps, csum=cs, period=chunk, stream=stream,
-                                 auto_correct=mode != "prot")
+                                 auto_correct=mode != "prot", input_check=False)
                 if tune:
                     S.autotune()
                 if mode == "offline":
@@ -275,14 +275,19 @@ def bench_radius2(stream, timed, u0, C, tune=True, k=10, steps=10, taps=DIFF4_TA
     npts = u0.numel()
     res = {"workload": f"{name}, {tuple(u0.shape)} fp32"}
     for name, mode, kw in (("plain", "none", {}),
-                           ("prot_kernel", "online", dict(threshold=2e-7, auto_correct=False)),
-                           ("online", "online", dict(threshold=2e-7)),
+                           ("prot_kernel", "online", dict(threshold=2e-7, auto_correct=False,
+                                                          input_check=False)),
+                           ("online", "online", dict(threshold=2e-7, input_check=False)),
+                           ("prot_kernel_input_check", "online",
+                            dict(threshold=2e-7, auto_correct=False, input_check=True)),
+                           ("online_input_check", "online", dict(threshold=2e-7,
+                                                                 input_check=True)),
                            ("offline", "offline", dict(threshold=2e-6, period=k))):
         with torch.cuda.stream(stream):
             S = abft.Stencil(u0.clone(), taps, C=C, mode=mode, stream=stream, **kw)
             if tune:
                 S.autotune()
-            if name == "online":
+            if name.startswith("online"):
                 S.step_graph(k)
                 ms = timed(lambda: S.step_graph(k), steps) / k
             else:
@@ -297,7 +302,8 @@ def bench_radius2(stream, timed, u0, C, tune=True, k=10, steps=10, taps=DIFF4_TA
                 res[f"{name}_noise"] = rep["max_noise"]
             S.close()
     res["plain_GBs"] = round(12.0 * npts / (res["plain_ms_per_sweep"] * 1e-3) / 1e9, 1)
-    for name in ("prot_kernel", "online", "offline"):
+    for name in ("prot_kernel", "online", "prot_kernel_input_check", "online_input_check",
+                 "offline"):
         res[f"overhead_{name}_pct"] = round(
             (res[f"{name}_ms_per_sweep"] / res["plain_ms_per_sweep"] - 1) * 100, 2)
     return res
@@ -395,27 +401,32 @@ def main():
     # ---- protected sweep kernel alone (online, no locate launches) ----------------------------
     prot_ms = None
     if args.only in (None, "prot"):
-        for cs in ("f64", "f32comp"):
-            S = make("online", threshold=1e-7, csum=cs, auto_correct=False)
+        for cs, ic in (("f64", False), ("f32comp", False), (args.csum, True)):
+            S = make("online", threshold=1e-7, csum=cs, auto_correct=False, input_check=ic)
             S.step(5)
             ms = timed(lambda: S.step(1), 10 * max(1, args.steps // 2))
             rep, _ = S.check()
-            assert rep["rows_flagged"] == 0, rep
-            out[f"prot_ms_{cs}"] = ms
-            out[f"prot_shape_{cs}"] = S.launch_shape()
-            out[f"prot_noise_{cs}"] = rep["max_noise"]
+            assert rep["rows_flagged"] == 0 and rep["mem_flagged"] == 0, rep
+            key = "input_check" if ic else cs
+            out[f"prot_ms_{key}"] = ms
+            out[f"prot_shape_{key}"] = S.launch_shape()
+            out[f"prot_noise_{key}"] = rep["max_noise"]
             S.close()
         prot_ms = out[f"prot_ms_{args.csum}"]
 
     # ---- online ABFT: every sweep checked, locate/correct launch after each -------------------
     online_ms = None
     if args.only in (None, "online"):
-        S = make("online", threshold=1e-7, csum=args.csum, auto_correct=True)
-        S.step_graph(k)
-        online_ms = timed(lambda: S.step_graph(k), max(1, args.steps // 2)) / k
-        rep, _ = S.check()
-        assert rep["rows_flagged"] == 0, rep
-        S.close()
+        for ic in (False, True):
+            S = make("online", threshold=1e-7, csum=args.csum, auto_correct=True,
+                     input_check=ic)
+            S.step_graph(k)
+            ms = timed(lambda: S.step_graph(k), max(1, args.steps // 2)) / k
+            rep, _ = S.check()
+            assert rep["rows_flagged"] == 0 and rep["mem_flagged"] == 0, rep
+            out["online_ms_input_check" if ic else "online_ms"] = ms
+            S.close()
+        online_ms = out["online_ms"]
 
     # ---- headline: offline ABFT windows ---------------------------------------------------
     offline_ms = None
@@ -469,8 +480,10 @@ def main():
 
     if args.only is not None:
         print(json.dumps({"only": args.only, "plain_ms": plain_ms, "prot_ms": prot_ms,
-                          "online_ms_per_sweep": online_ms, "offline_ms_per_window": offline_ms,
-                          "batch": batch}))
+                          "prot_ms_input_check": out.get("prot_ms_input_check"),
+                          "online_ms_per_sweep": online_ms,
+                          "online_ms_input_check": out.get("online_ms_input_check"),
+                          "offline_ms_per_window": offline_ms, "batch": batch}))
         return
 
     gpts = lambda ms, sweeps=1: npts * sweeps / (ms * 1e-3) / 1e9
@@ -533,6 +546,9 @@ def main():
         "plain_gpts": round(gpts(plain_ms), 3),
         "online_gpts": round(gpts(online_ms), 3),
         "prot_kernel_gpts": round(gpts(prot_ms), 3),
+        # the same with the input-side check (memory-resident faults) on
+        "online_input_check_gpts": round(gpts(out["online_ms_input_check"]), 3),
+        "prot_kernel_input_check_gpts": round(gpts(out["prot_ms_input_check"]), 3),
         "prot_kernel_gpts_by_csum": {cs: round(gpts(out[f"prot_ms_{cs}"]), 3)
                                      for cs in ("f64", "f32comp")},
         "launch_shapes": {"plain": out.get("plain_shape"),
@@ -540,6 +556,10 @@ def main():
         "overhead_offline_pct": round((offline_ms / (k * plain_ms) - 1) * 100, 2),
         "overhead_online_pct": round((online_ms / plain_ms - 1) * 100, 2),
         "overhead_prot_kernel_pct": round((prot_ms / plain_ms - 1) * 100, 2),
+        "overhead_online_input_check_pct": round(
+            (out["online_ms_input_check"] / plain_ms - 1) * 100, 2),
+        "overhead_prot_kernel_input_check_pct": round(
+            (out["prot_ms_input_check"] / plain_ms - 1) * 100, 2),
         "paper_context": "paper: <8% ABFT overhead, Xeon E5-2640 v4, 8 OpenMP threads, "
                          "512x512x8 fp32 HotSpot3D tiles (CPU, other hardware)",
         "cpu_baseline": cpu,

@@ -104,7 +104,13 @@ typedef struct {
                                    (offline) on the device without a host sync; 0: detection
                                    only, repair on abft_stencil_correct */
     int32_t max_events;         /* device event log capacity; 0 selects 4096 */
-    int32_t pad;
+    int32_t input_check;        /* online, single grids: 1 also checks each sweep's input rows
+                                   against the checksums stored when they were written (the
+                                   first case in the proof of Theorem 2, faults that arise in
+                                   memory between sweeps) and, with auto_correct, repairs a
+                                   changed input point and the outputs that read it; keeps an
+                                   index-weighted row sum beside each checksum.  0: off.
+                                   Ignored in the other modes and for batches. */
     const char* tuning_cache;   /* autotuner cache file (read at init, written by autotune),
                                    or NULL */
 } abft_options;

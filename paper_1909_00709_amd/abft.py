@@ -55,7 +55,7 @@ class AbftOptions(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("period", ctypes.c_int32),
                 ("threshold", ctypes.c_double), ("csum", ctypes.c_int32),
                 ("auto_correct", ctypes.c_int32), ("max_events", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("tuning_cache", ctypes.c_char_p)]
+                ("input_check", ctypes.c_int32), ("tuning_cache", ctypes.c_char_p)]
 
 
 class AbftEvent(ctypes.Structure):
@@ -238,20 +238,22 @@ def make_problem(shape, dtype_code, taps, u0_ptr, u1_ptr, u2_ptr=None, cterm_ptr
 
 
 def make_options(mode="online", period=10, threshold=1e-7, csum="f64", auto_correct=True,
-                 max_events=4096, tuning_cache=None):
+                 max_events=4096, tuning_cache=None, input_check=False):
     return AbftOptions(_MODE[mode] if isinstance(mode, str) else mode, int(period),
                        float(threshold), _CSUM[csum] if isinstance(csum, str) else csum,
-                       int(bool(auto_correct)), int(max_events), 0,
+                       int(bool(auto_correct)), int(max_events), int(bool(input_check)),
                        tuning_cache.encode() if tuning_cache else None)
 
 
 class Stencil:
     """One protected grid on the GPU.  u0 is a contiguous device tensor [nz][ny][nx] (float32
-    or float64) holding u^0; the work buffers are allocated with torch."""
+    or float64) holding u^0; the work buffers are allocated with torch.  input_check (online
+    mode) also checks each sweep's input rows against their stored checksums and repairs
+    faults that arose in memory between sweeps; it is on unless turned off."""
 
     def __init__(self, u0, taps, *, C=None, c_scalar=0.0, bc="clamp", bc_value=0.0,
                  mode="online", period=10, threshold=1e-7, csum="f64", auto_correct=True,
-                 max_events=4096, stream=None, tuning_cache=None):
+                 max_events=4096, stream=None, tuning_cache=None, input_check=True):
         import torch
         if not u0.is_cuda or not u0.is_contiguous() or u0.dim() != 3:
             raise ValueError("u0 must be a contiguous 3D device tensor [nz][ny][nx]")
@@ -274,7 +276,7 @@ class Stencil:
                                     C.data_ptr() if C is not None else None, c_scalar, bc,
                                     bc_value)
         self.options = make_options(mode, period, threshold, csum, auto_correct, max_events,
-                                    tuning_cache)
+                                    tuning_cache, input_check)
         s, ctx = abft_stencil_init(self.problem, self.options, self.stream.cuda_stream)
         if s != ABFT_OK:
             raise AbftError(s, abft_last_error(None))

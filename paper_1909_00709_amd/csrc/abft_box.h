@@ -27,6 +27,8 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
                                                unsigned char* smem_raw)
 {
     using V = VecOps<T, VEC>;
+    constexpr bool kProt = MODE == MODE_PROT || MODE == MODE_PROTM;
+    constexpr bool kMemChk = MODE == MODE_PROTM;  // also the input-side check (a.Wn set)
     constexpr int NT = NW * 64;
     constexpr int RPW = 64 / LPR;
     constexpr int TY = NW * RPW;
@@ -170,7 +172,7 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) pre[dz][dy] = 0.0;
     unsigned long long nknown = 0ull;
-    if constexpr (MODE == MODE_PROT) {
+    if constexpr (kProt) {
         nknown = noise_known(a.cnt);
         if (row_ok && sl < z1 - z0) {
             const int z = z0 + sl;
@@ -212,8 +214,7 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
     double* tabE = tabS + TY * a.tz;
     double* tabI = tabE + TY * a.tz;
     double* tabW = tabI + TY * a.tz;
-    const bool keep_e = MODE == MODE_PROT || a.E != nullptr;
-    const bool memchk = MODE == MODE_PROT && a.Wn != nullptr;
+    const bool keep_e = kProt || a.E != nullptr;
     using Acc = T;
 
     for (int z = z0; z < z1; ++z) {
@@ -306,7 +307,7 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
             const double S = row_sum<CS, LPR, NCH, VEC>(o);
             if (row_ok && sl == 0) tabS[r * a.tz + (z - z0)] = S;
         }
-        if (memchk) {
+        if constexpr (kMemChk) {
             // the input row as read (from the ring) and the output's index-weighted sum, as in
             // the star sweep
             T ci[NCH][VEC];
@@ -321,7 +322,7 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
                 }
             }
             const double Si = row_sum<CS, LPR, NCH, VEC>(ci);
-            const double Sw = weighted_row_sum<LPR, NCH, VEC>(o, sl);
+            const double Sw = weighted_row_sum<LPR, NCH, VEC>(o, (double)(sl * VEC + 1));
             if (row_ok && sl == 0) {
                 tabI[r * a.tz + (z - z0)] = Si;
                 tabW[r * a.tz + (z - z0)] = Sw;
@@ -360,7 +361,7 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
             if constexpr (MODE != MODE_PLAIN) {
                 const double S = tabS[r * a.tz + pz];
                 a.Bn[l] = S;
-                if constexpr (MODE == MODE_PROT) {
+                if constexpr (kProt) {
                     // Theorem 1 for the box: the weight sums over dx times the nine input
                     // row sums, plus the boundary terms formed in the march
                     const bool first = pz == sl;
@@ -382,7 +383,7 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
                             if (any)
                                 bp += wsum * (first ? pre[dz + 1][dy + 1] : brow(z + dz, y + dy));
                         }
-                    if (memchk) {
+                    if constexpr (kMemChk) {
                         a.Wn[l] = tabW[r * a.tz + pz];
                         check_input_row(a, t, z, y, tabI[r * a.tz + pz],
                                         first ? pre[1][1] : a.Bt[l]);
@@ -410,7 +411,7 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
             }
         }
     }
-    if constexpr (MODE == MODE_PROT) record_noise(a.cnt, noise, nknown);
+    if constexpr (kProt) record_noise(a.cnt, noise, nknown);
 }
 
 template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int NW>

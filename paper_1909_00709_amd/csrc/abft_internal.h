@@ -82,7 +82,9 @@ struct Counters {
 };
 
 // Sweep kernel variants.
-enum { MODE_PLAIN = 0, MODE_CSUM = 1, MODE_PROT = 2 };
+// PROT: checksum, prediction and comparison fused in the sweep; PROTM: PROT plus the check of
+// the input rows against their stored checksums and the output's index-weighted row sums.
+enum { MODE_PLAIN = 0, MODE_CSUM = 1, MODE_PROT = 2, MODE_PROTM = 3 };
 enum { CS_F64 = 0, CS_F32C = 1 };
 
 struct SweepArgs {
@@ -100,8 +102,7 @@ struct SweepArgs {
     // checksums
     const double* Bt;       // row checksums of uin (prediction input)
     double* Bn;             // row checksums of uout (written)
-    double* Wn;             // index-weighted row sums of uout (written), or null; when set,
-                            // the protected sweep also checks its input rows against Bt
+    double* Wn;             // index-weighted row sums of uout (written by the PROTM sweep)
     const double* cB;       // constant-term row checksums
     double eps;
     FlagSlot* slot;         // flagged rows of this sweep
@@ -231,7 +232,9 @@ struct SweepShape {
 };
 
 bool sweep_shape_supported(int dtype, const SweepShape& s);
-size_t sweep_lds_bytes(int dtype, int nx, const SweepShape& s);
+// Dynamic LDS of a sweep block: plane buffers and the per-tile tables (two more tables for
+// the input-side check).
+size_t sweep_lds_bytes(int dtype, int nx, const SweepShape& s, bool input_check = false);
 int sweep_rows_per_block(const SweepShape& s);
 hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, const SweepArgs& a,
                         hipStream_t st);
@@ -302,6 +305,12 @@ ABFT_DECL_SWEEP(launch_sweep_f32_prot)
 ABFT_DECL_SWEEP(launch_sweep_f64_plain)
 ABFT_DECL_SWEEP(launch_sweep_f64_csum)
 ABFT_DECL_SWEEP(launch_sweep_f64_prot)
+ABFT_DECL_SWEEP(launch_sweep_f32_protm)
+ABFT_DECL_SWEEP(launch_sweep_f64_protm)
+ABFT_DECL_SWEEP(launch_sweep_r2_f32_protm)
+ABFT_DECL_SWEEP(launch_sweep_r2_f64_protm)
+ABFT_DECL_SWEEP(launch_sweep_box_f32_protm)
+ABFT_DECL_SWEEP(launch_sweep_box_f64_protm)
 #undef ABFT_DECL_SWEEP
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st);
 

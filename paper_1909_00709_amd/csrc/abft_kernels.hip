@@ -919,22 +919,35 @@ bool sweep_shape_supported(int dtype, const SweepShape& s)
 
 int sweep_rows_per_block(const SweepShape& s) { return s.nw * (64 / s.lpr); }
 
-size_t sweep_lds_bytes(int dtype, int nx, const SweepShape& s)
+size_t sweep_lds_bytes(int dtype, int nx, const SweepShape& s, bool input_check)
 {
     const size_t es = dtype == ABFT_F32 ? 4 : 8;
     const size_t ty = (size_t)sweep_rows_per_block(s);
     const size_t pad = (size_t)std::max(s.vec, s.rad);
     const size_t planes = s.box ? 3 : 2;  // the box sweep keeps a ring of three planes
+    const size_t tables = input_check ? 4 : 2;  // checksum, boundary term[, input, weighted]
     return planes * (ty + 2 * s.rad) * (nx + 2 * pad) * es  // plane buffers with halo rows
-           + 4 * ty * (size_t)s.tz * sizeof(double);  // checksum, boundary, input, weighted
+           + tables * ty * (size_t)s.tz * sizeof(double);
 }
 
 hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, const SweepArgs& a,
                         hipStream_t st)
 {
     if (!sweep_shape_supported(dtype, s)) return hipErrorInvalidValue;
-    const size_t lds = sweep_lds_bytes(dtype, a.nx, s);
+    const size_t lds = sweep_lds_bytes(dtype, a.nx, s, mode == MODE_PROTM);
     if (mode == MODE_PLAIN) csum = CS_F64;  // no checksum in the plain variant
+    if (mode == MODE_PROTM) {
+        if (a.Wn == nullptr) return hipErrorInvalidValue;
+        const bool f32 = dtype == ABFT_F32;
+        if (s.box)
+            return f32 ? launch_sweep_box_f32_protm(csum, s, a, st, lds)
+                       : launch_sweep_box_f64_protm(csum, s, a, st, lds);
+        if (s.rad == 2)
+            return f32 ? launch_sweep_r2_f32_protm(csum, s, a, st, lds)
+                       : launch_sweep_r2_f64_protm(csum, s, a, st, lds);
+        return f32 ? launch_sweep_f32_protm(csum, s, a, st, lds)
+                   : launch_sweep_f64_protm(csum, s, a, st, lds);
+    }
     if (s.box) {
         if (dtype == ABFT_F32) return launch_sweep_box_f32(mode, csum, s, a, st, lds);
         return launch_sweep_box_f64(mode, csum, s, a, st, lds);

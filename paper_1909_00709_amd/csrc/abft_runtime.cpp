@@ -46,7 +46,7 @@ struct abft_ctx {
     void* u[3] = {nullptr, nullptr, nullptr};
     bool own_u2 = false;
     // options
-    int mode = 0, period = 1, csum = CS_F64, auto_correct = 1;
+    int mode = 0, period = 1, csum = CS_F64, auto_correct = 1, input_check = 0;
     double eps = 0.0;
     std::string cache_path;
     hipStream_t stream = nullptr;
@@ -243,7 +243,7 @@ bool default_shape(int dtype, int nx, int ny, int nz, int rad, int box, SweepSha
     };
     r.nw = 8;
     if (slabs(kTargetTilesWide) < kTargetTilesWide || !sweep_shape_supported(dtype, r) ||
-        sweep_lds_bytes(dtype, nx, r) > kSweepLdsLimit) {
+        sweep_lds_bytes(dtype, nx, r, true) > kSweepLdsLimit) {
         r.nw = 4;
         slabs(kTargetTiles);
     }
@@ -259,7 +259,7 @@ abft_status apply_shape(abft_ctx* c, const SweepShape& shape)
     if (!sweep_shape_supported(c->dtype, s)) return fail(c, ABFT_E_UNSUPPORTED, "launch shape");
     if ((int64_t)s.lpr * s.nch * s.vec < c->nx) return fail(c, ABFT_E_UNSUPPORTED, "row too long");
     if (s.vec > 1 && c->nx % s.vec) return fail(c, ABFT_E_UNSUPPORTED, "row not 16-byte multiple");
-    if (sweep_lds_bytes(c->dtype, c->nx, s) > kSweepLdsLimit)
+    if (sweep_lds_bytes(c->dtype, c->nx, s, c->input_check) > kSweepLdsLimit)
         return fail(c, ABFT_E_UNSUPPORTED, "rows too long for the LDS plane buffers");
     const int ty = sweep_rows_per_block(s);
     const int64_t nyb = (c->ny + ty - 1) / ty;
@@ -453,7 +453,7 @@ abft_status enqueue_online(abft_ctx* c, int64_t n, const int64_t* tbase, int64_t
         a.t_off = tbase ? t - t0 : t;
         int mode = MODE_PLAIN;
         if (c->mode == ABFT_MODE_ONLINE) {
-            mode = MODE_PROT;
+            mode = c->input_check ? MODE_PROTM : MODE_PROT;
             a.Bt = c->B[c->bcur];
             a.Bn = c->B[c->bcur ^ 1];
             a.Wn = c->W[c->bcur ^ 1];
@@ -914,6 +914,7 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
     c->eps = o->threshold;
     c->csum = o->csum == ABFT_CSUM_F32_COMP ? CS_F32C : CS_F64;
     c->auto_correct = o->auto_correct ? 1 : 0;
+    c->input_check = (o->input_check && o->mode == ABFT_MODE_ONLINE) ? 1 : 0;
     c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
     if (o->tuning_cache) c->cache_path = o->tuning_cache;
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -976,7 +977,7 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
         (s = dalloc(c, &c->ticket, 4 * sizeof(uint32_t))) ||
         (s = dalloc(c, &c->tbase, sizeof(int64_t))))
         return bail(s);
-    if (c->mode == ABFT_MODE_ONLINE &&
+    if (c->input_check &&
         ((s = dalloc(c, &c->W[0], nrows * 8)) || (s = dalloc(c, &c->W[1], nrows * 8))))
         return bail(s);
     if (c->mode == ABFT_MODE_OFFLINE) {
@@ -1302,7 +1303,8 @@ abft_status abft_stencil_autotune(abft_ctx* c)
                         if (!sweep_shape_supported(c->dtype, sh)) continue;
                         if ((int64_t)lpr * nch * vec < c->nx) continue;
                         if ((int64_t)lpr * (nch / 2) * vec >= c->nx && nch > 1) continue;  // minimal
-                        if (sweep_lds_bytes(c->dtype, c->nx, sh) > kSweepLdsLimit) continue;
+                        if (sweep_lds_bytes(c->dtype, c->nx, sh, c->input_check) > kSweepLdsLimit)
+                            continue;
                         for (int tz : {2, 4, 8, 16, 32, 64, 128}) {
                             if (tz > c->nz && tz != 2) continue;
                             sh.tz = std::min(tz, c->nz);
@@ -1315,7 +1317,8 @@ abft_status abft_stencil_autotune(abft_ctx* c)
     const SweepShape keep = c->shape;
     SweepShape best = keep;
     float best_ms = 1e30f;
-    const int mode = c->mode == ABFT_MODE_ONLINE ? MODE_PROT : MODE_PLAIN;
+    const int mode = c->mode != ABFT_MODE_ONLINE ? MODE_PLAIN
+                     : (c->input_check ? MODE_PROTM : MODE_PROT);
     for (const SweepShape& sh : cands) {
         if (apply_shape(c, sh)) continue;
         SweepArgs a = base_args(c);
@@ -1329,7 +1332,7 @@ abft_status abft_stencil_autotune(abft_ctx* c)
         a.slot = sslot;
         a.Bt = c->mode == ABFT_MODE_OFFLINE ? c->B[c->bck] : c->B[c->bcur];
         a.Bn = sB;
-        if (mode == MODE_PROT) a.Wn = sW;  // timed with the input-side check
+        if (mode == MODE_PROTM) a.Wn = sW;
         a.t_off = c->t;
         bool ok = true;
         for (int w = 0; w < 2 && ok; ++w)

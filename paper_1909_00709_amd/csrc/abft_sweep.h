@@ -50,16 +50,26 @@ __device__ __forceinline__ double row_sum(const T (&d)[NCH][VEC])
 }
 
 // Index-weighted row sum, sum over x of (x + 1) u(x), in fp64 (values past the row end are
-// zero).  Every lane must call it.
+// zero).  A lane holds x = c * LPR * VEC + x0 + v (x0 = sl * VEC), so its share is
+// (x0 + 1) * sum(u) + LPR * VEC * sum_c c * sum_v u + sum_c sum_v v * u: compile-time factors
+// except one per lane (x0 + 1, given as a double), which keeps the march's registers free.
+// Every lane must call it.
 template <int LPR, int NCH, int VEC, typename T>
-__device__ __forceinline__ double weighted_row_sum(const T (&d)[NCH][VEC], int sl)
+__device__ __forceinline__ double weighted_row_sum(const T (&d)[NCH][VEC], double x0p1)
 {
-    double p = 0.0;
+    double all = 0.0, byc = 0.0, byv = 0.0;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c)
+    for (int c = 0; c < NCH; ++c) {
+        double sc = 0.0;
 #pragma unroll
-        for (int v = 0; v < VEC; ++v)
-            p = fma((double)(c * LPR * VEC + sl * VEC + v + 1), (double)d[c][v], p);
+        for (int v = 0; v < VEC; ++v) {
+            sc += (double)d[c][v];
+            if (v > 0) byv = fma((double)v, (double)d[c][v], byv);
+        }
+        all += sc;
+        if (c > 0) byc = fma((double)c, sc, byc);
+    }
+    const double p = fma(x0p1, all, fma((double)(LPR * VEC), byc, byv));
     return segment_total<LPR>(row16_sum(p));
 }
 
@@ -93,6 +103,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
 {
     static_assert(RAD == 1 || RAD == 2, "star stencils of radius 1 or 2");
     using V = VecOps<T, VEC>;
+    constexpr bool kProt = MODE == MODE_PROT || MODE == MODE_PROTM;
+    constexpr bool kMemChk = MODE == MODE_PROTM;  // also the input-side check (a.Wn set)
     constexpr int NT = NW * 64;       // threads per block
     constexpr int RPW = 64 / LPR;     // rows per wavefront
     constexpr int TY = NW * RPW;      // rows per block
@@ -279,7 +291,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
 #pragma unroll
     for (int d = 0; d < RAD; ++d) pfy[d][0] = pfy[d][1] = pfz[d][0] = pfz[d][1] = 0.0;
     unsigned long long nknown = 0ull;
-    if constexpr (MODE == MODE_PROT) {
+    if constexpr (kProt) {
         nknown = noise_known(a.cnt);
         if (kPrefetch && row_ok && sl < z1 - z0) {
             const int z = z0 + sl;
@@ -313,10 +325,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
     double* tabE = tabS + TY * a.tz;
     double* tabI = tabE + TY * a.tz;
     double* tabW = tabI + TY * a.tz;
-    const bool keep_e = MODE == MODE_PROT || a.E != nullptr;
-    const bool memchk = MODE == MODE_PROT && a.Wn != nullptr;
+    const bool keep_e = kProt || a.E != nullptr;
 
     for (int z = z0; z < z1; ++z) {
+        if constexpr (kMemChk) {
+            // the input row as this sweep reads it, summed like an output row (the stored
+            // checksum it is compared with after the march was formed the same way); done
+            // before the next planes are in flight, when the fewest registers are live
+            const double Si = row_sum<CS, LPR, NCH, VEC>(pl[RAD]);
+            if (row_ok && sl == 0) tabI[r * a.tz + (z - z0)] = Si;
+        }
         // planes ahead in flight while this one is computed
         if constexpr (PF > 1) {
             if (z + 2 < z1) {
@@ -453,16 +471,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             const double S = row_sum<CS, LPR, NCH, VEC>(o);
             if (row_ok && sl == 0) tabS[r * a.tz + (z - z0)] = S;
         }
-        if (memchk) {
-            // the input row as this sweep read it, summed like the output row (the stored
-            // checksum it is compared with after the march was formed the same way), and the
-            // index-weighted sum of the output row, which places a changed point later
-            const double Si = row_sum<CS, LPR, NCH, VEC>(pl[RAD]);
-            const double Sw = weighted_row_sum<LPR, NCH, VEC>(o, sl);
-            if (row_ok && sl == 0) {
-                tabI[r * a.tz + (z - z0)] = Si;
-                tabW[r * a.tz + (z - z0)] = Sw;
-            }
+        if constexpr (kMemChk) {
+            // the index-weighted sum of the output row, which places a changed point later
+            const double Sw = weighted_row_sum<LPR, NCH, VEC>(o, (double)(sl * VEC + 1));
+            if (row_ok && sl == 0) tabW[r * a.tz + (z - z0)] = Sw;
         }
         if (keep_e && row_ok && sl == 0) {
             // shift dx < 0 reads G(dx .. -1) and drops u(nx+dx .. nx-1); dx > 0 reads
@@ -524,7 +536,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             if constexpr (MODE != MODE_PLAIN) {
                 const double S = tabS[r * a.tz + pz];
                 a.Bn[l] = S;
-                if constexpr (MODE == MODE_PROT) {
+                if constexpr (kProt) {
                     // Theorem 1 (Eq.(5)) on the checksum plane: the x shifts become the
                     // boundary term e of the input row, the y and z shifts read the
                     // neighbouring rows' checksums (loaded before the march for the first
@@ -550,7 +562,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                         if (has(w_slot(2, d, 1)))
                             bp += a.st.w[w_slot(2, d, 1)] * (first ? pfz[d - 1][1] : brow(z + d, y));
                     }
-                    if (memchk) {
+                    if constexpr (kMemChk) {
                         a.Wn[l] = tabW[r * a.tz + pz];
                         check_input_row(a, t, z, y, tabI[r * a.tz + pz], b0);
                     }
@@ -578,7 +590,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             }
         }
     }
-    if constexpr (MODE == MODE_PROT) record_noise(a.cnt, noise, nknown);
+    if constexpr (kProt) record_noise(a.cnt, noise, nknown);
 }
 
 template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int PF, int NW, int RAD>
