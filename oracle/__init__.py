@@ -85,8 +85,8 @@ def lib():
         L.orc_detect.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, vp]
         L.orc_detect.restype = ctypes.c_int64
         L.orc_run.argtypes = [P, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                              vp, vp, ctypes.c_int64, vp, ctypes.c_int64, vp, ctypes.c_int64,
-                              ctypes.POINTER(_Counters)]
+                              ctypes.c_int, vp, vp, ctypes.c_int64, vp, ctypes.c_int64, vp,
+                              ctypes.c_int64, ctypes.POINTER(_Counters)]
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_get_threads.restype = ctypes.c_int
         _lib = L
@@ -207,8 +207,9 @@ class Problem:
 
     # ---- whole runs -----------------------------------------------------------------------
     def run(self, u0, nsweeps, C=None, mode=MODE_ONLINE, period=10, eps=1e-12,
-            auto_correct=True, faults=None, max_events=100000):
-        """Returns (final grid, events structured array, counters dict)."""
+            auto_correct=True, faults=None, max_events=100000, input_check=True):
+        """Returns (final grid, events structured array, counters dict).  input_check (online
+        mode): also check each sweep's input rows against the stored checksums."""
         u_a = self._grid(u0).copy()
         u_b = np.empty_like(u_a)
         C = self._const(C)
@@ -217,8 +218,8 @@ class Problem:
         ev = np.zeros(max_events, dtype=EVENT_DTYPE)
         cnt = _Counters()
         rc = lib().orc_run(self.ref, _ptr(C), mode, period, eps, int(bool(auto_correct)),
-                           _ptr(u_a), _ptr(u_b), nsweeps, fptr, nf, _ptr(ev), max_events,
-                           ctypes.byref(cnt))
+                           int(bool(input_check)), _ptr(u_a), _ptr(u_b), nsweeps, fptr, nf,
+                           _ptr(ev), max_events, ctypes.byref(cnt))
         if rc != 0:
             raise ValueError(f"orc_run failed with code {rc}")
         counters = {f: getattr(cnt, f) for f in COUNTER_FIELDS}

@@ -374,6 +374,7 @@ typedef struct {
     const void* C;
     double eps;
     int auto_correct;
+    int input_check;
     const orc_fault* faults;
     int64_t nfaults;
     orc_event* ev;
@@ -590,9 +591,12 @@ static void online_check(run_state* S, int64_t sweep, void* uin, void* uout)
             emit(S, sweep, ORC_EV_ROW_FLAG, (int)(l / p->ny), (int)(l % p->ny), -1, S->Bn[l],
                  S->Bp[l]);
         }
-    orc_row_checksums(p, uin, S->Bi);
-    const int64_t nm = orc_detect(nrows, S->Bi, S->B, S->eps, S->mflag);
-    for (int64_t l = 0; l < nrows; l++)
+    int64_t nm = 0;
+    if (S->input_check) {
+        orc_row_checksums(p, uin, S->Bi);
+        nm = orc_detect(nrows, S->Bi, S->B, S->eps, S->mflag);
+    }
+    for (int64_t l = 0; l < nrows && nm > 0; l++)
         if (S->mflag[l]) {
             S->cnt->mem_flagged++;
             emit(S, sweep, ORC_EV_MEM_FLAG, (int)(l / p->ny), (int)(l % p->ny), -1, S->Bi[l],
@@ -630,7 +634,7 @@ static void online_check(run_state* S, int64_t sweep, void* uin, void* uout)
 }
 
 int orc_run(const orc_problem* p, const void* C, int mode, int period, double eps,
-            int auto_correct, void* u_a, void* u_b, int64_t nsweeps,
+            int auto_correct, int input_check, void* u_a, void* u_b, int64_t nsweeps,
             const orc_fault* faults, int64_t nfaults,
             orc_event* events, int64_t max_events, orc_counters* counters)
 {
@@ -660,6 +664,7 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
     S.C = C;
     S.eps = eps;
     S.auto_correct = auto_correct;
+    S.input_check = input_check && mode == ORC_MODE_ONLINE;
     S.faults = faults;
     S.nfaults = nfaults;
     S.ev = events;
@@ -696,18 +701,16 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
     void* uout = u_b;
 
     if (mode != ORC_MODE_OFFLINE) {
-        if (mode == ORC_MODE_ONLINE) {
-            orc_row_checksums(p, uin, S.B);
-            orc_weighted_row_checksums(p, uin, S.W);
-        }
+        if (mode == ORC_MODE_ONLINE) orc_row_checksums(p, uin, S.B);
+        if (S.input_check) orc_weighted_row_checksums(p, uin, S.W);
         for (int64_t t = 0; t < nsweeps; t++) {
             inject(&S, uin, t, 0, ORC_FAULT_MEMORY);
             orc_sweep(p, C, uin, uout);
             inject(&S, uout, t, 0, ORC_FAULT_STORE);
             if (mode == ORC_MODE_ONLINE) {
                 online_check(&S, t, uin, uout);
-                /* the checksums of the output as it stands after any repair */
-                orc_weighted_row_checksums(p, uout, S.Wn);
+                /* the weighted sums of the output as it stands after any repair */
+                if (S.input_check) orc_weighted_row_checksums(p, uout, S.Wn);
                 double* tmp = S.B;
                 S.B = S.Bn;
                 S.Bn = tmp;

@@ -130,14 +130,15 @@ int64_t orc_detect(int64_t n, const double* direct, const double* pred, double e
  * mode (ORC_MODE_*), with the fault plan applied (STORE faults to stored values, MEMORY faults
  * to a sweep's input grid before it is read).  The final grid is left in u_a.  period is the
  * offline window length.  With auto_correct == 0 in offline mode the run stops after the first
- * flagged window (the checkpoint is still valid) and sweeps_done tells where.  Online, each
- * sweep also compares the sums of its input rows with the stored checksums; a mismatched row
- * is repaired before the sweep's own flags are examined (see online_check).  Offline, the
+ * flagged window (the checkpoint is still valid) and sweeps_done tells where.  Online with
+ * input_check != 0, each sweep also compares the sums of its input rows with the stored
+ * checksums; a mismatched row is repaired before the sweep's own flags are examined (see
+ * online_check).  Offline, the
  * checkpoint is the window's first input in place, so a MEMORY fault on a window's first
  * sweep corrupts the checkpoint too.  Events are written up to max_events.  Returns 0 or a
  * negative code. */
 int orc_run(const orc_problem* p, const void* C, int mode, int period, double eps,
-            int auto_correct, void* u_a, void* u_b, int64_t nsweeps,
+            int auto_correct, int input_check, void* u_a, void* u_b, int64_t nsweeps,
             const orc_fault* faults, int64_t nfaults,
             orc_event* events, int64_t max_events, orc_counters* counters);
 

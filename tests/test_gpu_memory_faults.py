@@ -187,3 +187,20 @@ def test_memory_faults_rejected_where_unsupported():
             S.inject(W.make_plan([(0, 0, 0, 0, 3, 1, MEM)]))
     finally:
         S.close()
+
+
+def test_memory_flip_without_input_check():
+    """Input-side check off: the output check reports the reached rows as checksum-side
+    mismatches, as the oracle does, and the grid follows the unprotected run."""
+    shape = (6, 24, 128)
+    u0, C = _thermal(shape)
+    plan = W.make_plan([(3, 2, 7, 11, 29, 0, MEM)])
+    say("memory flip, input check off")
+    g, gev, grep, _ = run_gpu(u0, W.THERMAL_TAPS, 6, C=C, eps=1e-7, plan=plan,
+                              input_check=False)
+    o, oev, ocnt = run_oracle(u0, W.THERMAL_TAPS, 6, C=C, eps=1e-7, plan=plan,
+                              input_check=False)
+    assert event_keys(gev) == event_keys(oev)
+    assert grep["mem_flagged"] == 0 and grep["checksum_faults"] == ocnt["checksum_faults"] > 0
+    none = run_gpu(u0, W.THERMAL_TAPS, 6, C=C, mode="none", plan=plan)[0]
+    assert np.array_equal(g, none)

@@ -193,3 +193,22 @@ def test_bad_fault_kind_rejected(orc):
     plan = W.make_plan([(0, 0, 0, 0, 3, 0, 2)])
     with pytest.raises(ValueError):
         p.run(np.zeros(shape, np.float32), 1, faults=plan)
+
+
+def test_memory_flip_without_input_check(orc):
+    """With the input-side check off, the output check still sees the flip one sweep later
+    (Theorem 2: the direct checksums are wrong, the predicted ones right), in the rows the
+    changed point reaches, but nothing places it: the layer's columns agree with their
+    prediction from the changed input, so the mismatches are reported as checksum-side."""
+    shape = (4, 12, 40)
+    u0, C = _thermal(shape)
+    p = orc.Problem(shape, orc.F32, W.THERMAL_TAPS)
+    t, z, y, x = 3, 2, 7, 11
+    plan = W.make_plan([(t, z, y, x, 29, 0, MEM)])
+    fin, ev, cnt = p.run(u0, 6, C, eps=1e-7, faults=plan, input_check=False)
+    assert cnt["mem_flagged"] == 0 and cnt["mem_corrected"] == 0
+    rows = {(int(e["z"]), int(e["y"])) for e in ev[ev["kind"] == orc.EV_ROW_FLAG]}
+    assert (z, y) in rows and rows <= {(z, y), (z, y - 1), (z, y + 1), (z - 1, y), (z + 1, y)}
+    assert cnt["corrected"] == 0 and cnt["checksum_faults"] == len(rows)
+    none, _, _ = p.run(u0, 6, C, mode=orc.MODE_NONE, faults=plan)
+    assert np.array_equal(fin, none)
