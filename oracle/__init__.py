@@ -207,9 +207,11 @@ class Problem:
 
     # ---- whole runs -----------------------------------------------------------------------
     def run(self, u0, nsweeps, C=None, mode=MODE_ONLINE, period=10, eps=1e-12,
-            auto_correct=True, faults=None, max_events=100000, input_check=True):
-        """Returns (final grid, events structured array, counters dict).  input_check (online
-        mode): also check each sweep's input rows against the stored checksums."""
+            auto_correct=True, faults=None, max_events=100000, input_check=True,
+            recompute=False):
+        """Returns (final grid, events structured array, counters dict).  Online mode:
+        input_check also checks each sweep's input rows against the stored checksums;
+        recompute corrects located points by evaluating them again from the sweep's input."""
         u_a = self._grid(u0).copy()
         u_b = np.empty_like(u_a)
         C = self._const(C)
@@ -218,7 +220,8 @@ class Problem:
         ev = np.zeros(max_events, dtype=EVENT_DTYPE)
         cnt = _Counters()
         rc = lib().orc_run(self.ref, _ptr(C), mode, period, eps, int(bool(auto_correct)),
-                           int(bool(input_check)), _ptr(u_a), _ptr(u_b), nsweeps, fptr, nf,
+                           (1 if input_check else 0) | (2 if recompute else 0), _ptr(u_a),
+                           _ptr(u_b), nsweeps, fptr, nf,
                            _ptr(ev), max_events, ctypes.byref(cnt))
         if rc != 0:
             raise ValueError(f"orc_run failed with code {rc}")

@@ -375,6 +375,7 @@ typedef struct {
     double eps;
     int auto_correct;
     int input_check;
+    int recompute;
     const orc_fault* faults;
     int64_t nfaults;
     orc_event* ev;
@@ -459,12 +460,18 @@ static void recompute_row(run_state* S, const void* u, int z, int y, double* B)
     B[(int64_t)z * p->ny + y] = cs_val(s);
 }
 
+/* Most intersection points evaluated again in one layer (recompute correction). */
+#define ORC_MAX_RECOMPUTE 65536
+
 /* Sections 3.4-3.5 for one layer with flagged rows: the column checksums of the layer locate
- * the corrupted columns, the intersection gives the points, Eq.(10) gives their values. */
+ * the corrupted columns, the intersection gives the points, Eq.(10) gives their values.
+ * With the recompute correction (the locality the paper cites for stencils: an output point
+ * depends only on its stencil neighbours of the sweep's input, which is intact online) each
+ * intersection point is evaluated again from the input; a point that was not corrupted gets
+ * its own value back, so several rows and columns flagged together are corrected as well. */
 static void locate_correct_layer(run_state* S, int64_t sweep, const void* uin, void* uout, int z)
 {
     const orc_problem* p = S->p;
-    (void)uin;
     int R = 0, K = 0;
     int* ys = (int*)malloc(sizeof(int) * (size_t)p->ny);
     int* xs = (int*)malloc(sizeof(int) * (size_t)p->nx);
@@ -487,6 +494,20 @@ static void locate_correct_layer(run_state* S, int64_t sweep, const void* uin, v
             emit(S, sweep, ORC_EV_CHECKSUM_FAULT, z, ys[i], -1, S->Bn[(int64_t)z * p->ny + ys[i]],
                  S->Bp[(int64_t)z * p->ny + ys[i]]);
         }
+    } else if (S->recompute && (int64_t)R * K <= ORC_MAX_RECOMPUTE) {
+        for (int i = 0; i < R; i++)
+            for (int j = 0; j < K; j++) {
+                const int y = ys[i], x = xs[j];
+                const int64_t c = idx(p, x, y, z);
+                const double old = ld(p->dtype, uout, c);
+                st(p->dtype, uout, c, point(p, S->w, S->c_scalar, S->C, uin, x, y, z));
+                const double nv = ld(p->dtype, uout, c);
+                if (memcmp(&old, &nv, sizeof(double)) != 0) { /* bits changed */
+                    S->cnt->corrected++;
+                    emit(S, sweep, ORC_EV_CORRECTED, z, y, x, old, nv);
+                }
+            }
+        for (int i = 0; i < R; i++) recompute_row(S, uout, z, ys[i], S->Bn);
     } else if (R >= 2 && K >= 2) {
         S->cnt->uncorrectable++;
         emit(S, sweep, ORC_EV_UNCORRECTABLE, z, -1, -1, (double)R, (double)K);
@@ -634,7 +655,7 @@ static void online_check(run_state* S, int64_t sweep, void* uin, void* uout)
 }
 
 int orc_run(const orc_problem* p, const void* C, int mode, int period, double eps,
-            int auto_correct, int input_check, void* u_a, void* u_b, int64_t nsweeps,
+            int auto_correct, int flags, void* u_a, void* u_b, int64_t nsweeps,
             const orc_fault* faults, int64_t nfaults,
             orc_event* events, int64_t max_events, orc_counters* counters)
 {
@@ -664,7 +685,8 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
     S.C = C;
     S.eps = eps;
     S.auto_correct = auto_correct;
-    S.input_check = input_check && mode == ORC_MODE_ONLINE;
+    S.input_check = (flags & ORC_INPUT_CHECK) && mode == ORC_MODE_ONLINE;
+    S.recompute = (flags & ORC_RECOMPUTE) != 0;
     S.faults = faults;
     S.nfaults = nfaults;
     S.ev = events;

@@ -131,14 +131,22 @@ int64_t orc_detect(int64_t n, const double* direct, const double* pred, double e
  * to a sweep's input grid before it is read).  The final grid is left in u_a.  period is the
  * offline window length.  With auto_correct == 0 in offline mode the run stops after the first
  * flagged window (the checkpoint is still valid) and sweeps_done tells where.  Online with
- * input_check != 0, each sweep also compares the sums of its input rows with the stored
+ * ORC_INPUT_CHECK, each sweep also compares the sums of its input rows with the stored
  * checksums; a mismatched row is repaired before the sweep's own flags are examined (see
- * online_check).  Offline, the
+ * online_check).  With ORC_RECOMPUTE, located points are evaluated again instead of being
+ * rebuilt from the checksums (see locate_correct_layer).  Offline, the
  * checkpoint is the window's first input in place, so a MEMORY fault on a window's first
  * sweep corrupts the checkpoint too.  Events are written up to max_events.  Returns 0 or a
  * negative code. */
+/* Options of orc_run (flags). */
+enum {
+    ORC_INPUT_CHECK = 1, /* online: check each sweep's input rows against the stored checksums */
+    ORC_RECOMPUTE = 2    /* online: correct a located point by evaluating it again from the
+                            sweep's input (stencil locality) instead of Eq.(10) */
+};
+
 int orc_run(const orc_problem* p, const void* C, int mode, int period, double eps,
-            int auto_correct, int input_check, void* u_a, void* u_b, int64_t nsweeps,
+            int auto_correct, int flags, void* u_a, void* u_b, int64_t nsweeps,
             const orc_fault* faults, int64_t nfaults,
             orc_event* events, int64_t max_events, orc_counters* counters);
 
