@@ -66,6 +66,19 @@ typedef enum { ABFT_MODE_NONE = 0, ABFT_MODE_ONLINE = 1, ABFT_MODE_OFFLINE = 2 }
  * (two-sum) accumulation.  Both are compared in fp64. */
 typedef enum { ABFT_CSUM_F64 = 0, ABFT_CSUM_F32_COMP = 1 } abft_csum;
 
+/* How an online correction rebuilds a located point (Section 3.5). */
+typedef enum {
+    ABFT_CORRECT_CHECKSUM = 0,  /* Eq.(10): from the row or column checksum and the other
+                                   points of the line; rounding-limited; two or more rows and
+                                   columns flagged in one layer are uncorrectable */
+    ABFT_CORRECT_RECOMPUTE = 1  /* the point evaluated again from the sweep's input (which an
+                                   online sweep leaves intact), exactly as the sweep computes
+                                   it: bitwise the fault-free value; with several rows and
+                                   columns flagged in a layer every intersection is evaluated
+                                   again (at most 65536 per layer), unchanged points keep
+                                   their value */
+} abft_correction;
+
 /* One stencil point of the set S of Eq.(1): offsets and weight.  The weight is rounded once
  * to the grid dtype; the sweep and the checksum prediction both use that rounded value. */
 typedef struct {
@@ -113,6 +126,8 @@ typedef struct {
                                    Ignored in the other modes and for batches. */
     const char* tuning_cache;   /* autotuner cache file (read at init, written by autotune),
                                    or NULL */
+    int32_t correction;         /* an abft_correction value; online contexts and batches */
+    int32_t pad;
 } abft_options;
 
 /* Event kinds in the device log. */

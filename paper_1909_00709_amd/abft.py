@@ -24,6 +24,7 @@ ABFT_F32, ABFT_F64 = 0, 1
 ABFT_BC_CLAMP, ABFT_BC_PERIODIC, ABFT_BC_CONSTANT = 0, 1, 2
 ABFT_MODE_NONE, ABFT_MODE_ONLINE, ABFT_MODE_OFFLINE = 0, 1, 2
 ABFT_CSUM_F64, ABFT_CSUM_F32_COMP = 0, 1
+ABFT_CORRECT_CHECKSUM, ABFT_CORRECT_RECOMPUTE = 0, 1
 ABFT_EV_ROW_FLAG, ABFT_EV_CORRECTED, ABFT_EV_CHECKSUM_FAULT, ABFT_EV_UNCORRECTABLE = 1, 2, 3, 4
 ABFT_EV_WINDOW_FLAG, ABFT_EV_ROLLBACK, ABFT_EV_PERSISTENT, ABFT_EV_COL_FLAG = 5, 6, 7, 8
 ABFT_EV_MEM_FLAG, ABFT_EV_MEM_CORRECTED, ABFT_EV_MEM_UNLOCATED = 9, 10, 11
@@ -55,7 +56,8 @@ class AbftOptions(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("period", ctypes.c_int32),
                 ("threshold", ctypes.c_double), ("csum", ctypes.c_int32),
                 ("auto_correct", ctypes.c_int32), ("max_events", ctypes.c_int32),
-                ("input_check", ctypes.c_int32), ("tuning_cache", ctypes.c_char_p)]
+                ("input_check", ctypes.c_int32), ("tuning_cache", ctypes.c_char_p),
+                ("correction", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class AbftEvent(ctypes.Structure):
@@ -223,6 +225,7 @@ class AbftError(RuntimeError):
 _BC = {"clamp": ABFT_BC_CLAMP, "periodic": ABFT_BC_PERIODIC, "constant": ABFT_BC_CONSTANT}
 _MODE = {"none": ABFT_MODE_NONE, "online": ABFT_MODE_ONLINE, "offline": ABFT_MODE_OFFLINE}
 _CSUM = {"f64": ABFT_CSUM_F64, "f32comp": ABFT_CSUM_F32_COMP}
+_CORRECTION = {"checksum": ABFT_CORRECT_CHECKSUM, "recompute": ABFT_CORRECT_RECOMPUTE}
 
 
 def make_problem(shape, dtype_code, taps, u0_ptr, u1_ptr, u2_ptr=None, cterm_ptr=None,
@@ -238,11 +241,13 @@ def make_problem(shape, dtype_code, taps, u0_ptr, u1_ptr, u2_ptr=None, cterm_ptr
 
 
 def make_options(mode="online", period=10, threshold=1e-7, csum="f64", auto_correct=True,
-                 max_events=4096, tuning_cache=None, input_check=False):
+                 max_events=4096, tuning_cache=None, input_check=False, correction="checksum"):
     return AbftOptions(_MODE[mode] if isinstance(mode, str) else mode, int(period),
                        float(threshold), _CSUM[csum] if isinstance(csum, str) else csum,
                        int(bool(auto_correct)), int(max_events), int(bool(input_check)),
-                       tuning_cache.encode() if tuning_cache else None)
+                       tuning_cache.encode() if tuning_cache else None,
+                       _CORRECTION[correction] if isinstance(correction, str) else correction,
+                       0)
 
 
 class Stencil:
@@ -253,7 +258,8 @@ class Stencil:
 
     def __init__(self, u0, taps, *, C=None, c_scalar=0.0, bc="clamp", bc_value=0.0,
                  mode="online", period=10, threshold=1e-7, csum="f64", auto_correct=True,
-                 max_events=4096, stream=None, tuning_cache=None, input_check=True):
+                 max_events=4096, stream=None, tuning_cache=None, input_check=True,
+                 correction="checksum"):
         import torch
         if not u0.is_cuda or not u0.is_contiguous() or u0.dim() != 3:
             raise ValueError("u0 must be a contiguous 3D device tensor [nz][ny][nx]")
@@ -276,7 +282,7 @@ class Stencil:
                                     C.data_ptr() if C is not None else None, c_scalar, bc,
                                     bc_value)
         self.options = make_options(mode, period, threshold, csum, auto_correct, max_events,
-                                    tuning_cache, input_check)
+                                    tuning_cache, input_check, correction)
         s, ctx = abft_stencil_init(self.problem, self.options, self.stream.cuda_stream)
         if s != ABFT_OK:
             raise AbftError(s, abft_last_error(None))
@@ -359,7 +365,8 @@ class Batch:
     taps and the options."""
 
     def __init__(self, grids, taps, *, c_scalar=0.0, bc="clamp", bc_value=0.0, mode="online",
-                 threshold=1e-7, csum="f64", auto_correct=True, max_events=4096, stream=None):
+                 threshold=1e-7, csum="f64", auto_correct=True, max_events=4096, stream=None,
+                 correction="checksum"):
         import torch
         self.torch = torch
         self.bufs, self.Cs, problems = [], [], []
@@ -377,7 +384,8 @@ class Batch:
         self.problems = problems
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.max_events = max_events
-        self.options = make_options(mode, 1, threshold, csum, auto_correct, max_events)
+        self.options = make_options(mode, 1, threshold, csum, auto_correct, max_events,
+                                    correction=correction)
         s, ctx = abft_stencil_init_batch(problems, self.options, self.stream.cuda_stream)
         if s != ABFT_OK:
             raise AbftError(s, abft_last_error(None))

@@ -11,6 +11,7 @@ namespace abft {
 
 constexpr int kMaxFlags = 1024;   // flagged rows remembered per sweep for location
 constexpr int kMaxMemFlags = 64;  // mismatched input rows remembered per sweep for repair
+constexpr int kMaxRecompute = 65536;  // intersection points evaluated again per layer
 constexpr int kSweepBlock = 256;  // threads per block of the batched sweep (4 wavefronts)
 constexpr int kWideBlockLaneBytes = 64;  // most row bytes per lane for 8-wavefront sweep blocks
 constexpr int kFixBlock = 512;    // threads of the single locate/correct block
@@ -134,6 +135,7 @@ struct FixArgs {
     const double* cB;
     const void* C;
     double c_scalar;
+    int32_t recompute;      // correct located points by evaluating them again (else Eq.(10))
     Stencil st;
     int32_t nx, ny, nz;
     double eps;
@@ -210,6 +212,7 @@ struct BatchArgs {
     const int64_t* t_base;
     int64_t t_off;
     int32_t attempt;
+    int32_t recompute;      // locate/correct: evaluate located points again (else Eq.(10))
     double eps;
     Counters* cnt;
     abft_event* ev;

@@ -156,6 +156,15 @@ __device__ __forceinline__ int window_coord(int c, int n, int bc)
     return bc == ABFT_BC_PERIODIC ? map_coord(c, n, bc) : -1;
 }
 
+template <typename T>
+__device__ __forceinline__ bool same_bits(T a, T b)
+{
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(uint32_t, a) == __builtin_bit_cast(uint32_t, b);
+    else
+        return __builtin_bit_cast(uint64_t, a) == __builtin_bit_cast(uint64_t, b);
+}
+
 // Sum and index-weighted sum of one row, by the whole block (fixed order).
 template <typename T>
 __device__ void block_row_sums(const T* row, int nx, double* red, double* s, double* w)
@@ -535,6 +544,33 @@ __device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* re
                                slot->rows[ri].y, -1, slot->rows[ri].direct, slot->rows[ri].pred,
                                a.grid);
                 }
+        } else if (a.recompute && (int64_t)R * K <= kMaxRecompute) {
+            // stencil locality: every intersection point evaluated again from the sweep's
+            // input, with the sweep's operations; a point that was not corrupted gets its own
+            // bits back and is not reported
+            const T* uin_t = static_cast<const T*>(a.uin);
+            for (int q = tid; q < R * K; q += kFixBlock) {
+                const int y = slot->rows[i + q / K].y, x = xs[q % K];
+                T* pt = uout + (size_t)z * ps + (size_t)y * nx + x;
+                const T old = *pt;
+                const T nv = point_value<T, RAD, BOX>(a, uin_t, x, y, z);
+                if (!same_bits(old, nv)) {
+                    *pt = nv;
+                    atomicAdd(&a.cnt->corrected, 1ull);
+                    emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_CORRECTED, z, y, x,
+                               (double)old, (double)nv, a.grid);
+                }
+            }
+            __syncthreads();
+            for (int ri = i; ri < j; ++ri) {
+                const int y = slot->rows[ri].y;
+                double S, Wr;
+                block_row_sums(uout + (size_t)z * ps + (size_t)y * nx, nx, red, &S, &Wr);
+                if (tid == 0) {
+                    a.Bn[(size_t)z * ny + y] = S;
+                    if (a.Wn != nullptr) a.Wn[(size_t)z * ny + y] = Wr;
+                }
+            }
         } else if (R >= 2 && K >= 2) {
             if (tid == 0) {
                 atomicAdd(&a.cnt->uncorrectable, 1ull);
@@ -624,6 +660,9 @@ __global__ void __launch_bounds__(kFixBlock) fixup_batch_kernel(const BatchArgs 
     a.grid = g;
     a.t_base = b.t_base;
     a.t_off = b.t_off;
+    a.C = d.C;
+    a.c_scalar = d.c_scalar;
+    a.recompute = b.recompute;
     fixup_body<T, 1, 0>(a, smem_raw, red, sh_K);
 }
 

@@ -46,7 +46,7 @@ struct abft_ctx {
     void* u[3] = {nullptr, nullptr, nullptr};
     bool own_u2 = false;
     // options
-    int mode = 0, period = 1, csum = CS_F64, auto_correct = 1, input_check = 0;
+    int mode = 0, period = 1, csum = CS_F64, auto_correct = 1, input_check = 0, recompute = 0;
     double eps = 0.0;
     std::string cache_path;
     hipStream_t stream = nullptr;
@@ -428,6 +428,7 @@ FixArgs online_fix_args(const abft_ctx* c, int in, int bin, int64_t t, const int
     f.cB = c->cB;
     f.C = c->C;
     f.c_scalar = c->cs;
+    f.recompute = c->recompute;
     f.st = c->st;
     f.nx = c->nx;
     f.ny = c->ny;
@@ -695,6 +696,8 @@ abft_status validate_options(const abft_problem* p, const abft_options* o)
     if (o->csum == ABFT_CSUM_F32_COMP && p->dtype != ABFT_F32)
         return fail(nullptr, ABFT_E_INVAL, "compensated fp32 checksums need an fp32 grid");
     if (o->max_events < 0) return fail(nullptr, ABFT_E_INVAL, "max_events");
+    if (o->correction != ABFT_CORRECT_CHECKSUM && o->correction != ABFT_CORRECT_RECOMPUTE)
+        return fail(nullptr, ABFT_E_INVAL, "correction");
     return ABFT_OK;
 }
 
@@ -783,6 +786,7 @@ BatchArgs batch_args(const abft_ctx* c, int64_t t, const int64_t* tbase, int64_t
     b.t_base = tbase;
     b.t_off = tbase ? t - t0 : t;
     b.eps = c->eps;
+    b.recompute = c->recompute;
     b.cnt = c->cnt;
     b.ev = c->ev;
     b.ev_cap = c->ev_cap;
@@ -914,6 +918,7 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
     c->eps = o->threshold;
     c->csum = o->csum == ABFT_CSUM_F32_COMP ? CS_F32C : CS_F64;
     c->auto_correct = o->auto_correct ? 1 : 0;
+    c->recompute = o->correction == ABFT_CORRECT_RECOMPUTE ? 1 : 0;
     c->input_check = (o->input_check && o->mode == ABFT_MODE_ONLINE) ? 1 : 0;
     c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
     if (o->tuning_cache) c->cache_path = o->tuning_cache;
@@ -1414,6 +1419,7 @@ abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft
     c->eps = o->threshold;
     c->csum = o->csum == ABFT_CSUM_F32_COMP ? CS_F32C : CS_F64;
     c->auto_correct = o->auto_correct ? 1 : 0;
+    c->recompute = o->correction == ABFT_CORRECT_RECOMPUTE ? 1 : 0;
     c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
     c->stream = static_cast<hipStream_t>(hip_stream);
     auto bail = [&](abft_status st) {

@@ -22,7 +22,8 @@ def say(*args):
 
 def run_gpu(u0, taps, nsweeps, *, C=None, c_scalar=0.0, mode="online", eps=1e-12, period=10,
             csum="f64", auto_correct=True, plan=None, bc="clamp", bc_value=0.0, graph=False,
-            chunks=None, max_events=1 << 16, autotune=False, input_check=True):
+            chunks=None, max_events=1 << 16, autotune=False, input_check=True,
+            correction="checksum"):
     """Returns (final grid as numpy, events, report, stencil-shape)."""
     import torch
     from paper_1909_00709_amd import abft
@@ -32,7 +33,8 @@ def run_gpu(u0, taps, nsweeps, *, C=None, c_scalar=0.0, mode="online", eps=1e-12
         Ct = torch.from_numpy(np.ascontiguousarray(C)).cuda() if C is not None else None
         S = abft.Stencil(ut, taps, C=Ct, c_scalar=c_scalar, bc=bc, bc_value=bc_value, mode=mode,
                          period=period, threshold=eps, csum=csum, auto_correct=auto_correct,
-                         max_events=max_events, stream=stream, input_check=input_check)
+                         max_events=max_events, stream=stream, input_check=input_check,
+                         correction=correction)
         try:
             if autotune:
                 S.autotune()
@@ -52,13 +54,14 @@ def run_gpu(u0, taps, nsweeps, *, C=None, c_scalar=0.0, mode="online", eps=1e-12
 
 def run_oracle(u0, taps, nsweeps, *, C=None, c_scalar=0.0, mode="online", eps=1e-12, period=10,
                auto_correct=True, plan=None, bc="clamp", bc_value=0.0, dtype=None,
-               input_check=True):
+               input_check=True, recompute=False):
     bcs = {"clamp": O.BC_CLAMP, "periodic": O.BC_PERIODIC, "constant": O.BC_CONSTANT}
     modes = {"none": O.MODE_NONE, "online": O.MODE_ONLINE, "offline": O.MODE_OFFLINE}
     dt = dtype if dtype is not None else (O.F32 if u0.dtype == np.float32 else O.F64)
     p = O.Problem(u0.shape, dt, taps, bc=bcs[bc], bc_value=bc_value, c_scalar=c_scalar)
     return p.run(u0, nsweeps, C, mode=modes[mode], period=period, eps=eps,
-                 auto_correct=auto_correct, faults=plan, input_check=input_check)
+                 auto_correct=auto_correct, faults=plan, input_check=input_check,
+                 recompute=recompute)
 
 
 def event_keys(ev, kinds=(1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11), skip=None):

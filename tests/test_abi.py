@@ -46,6 +46,7 @@ int main(void) {
   P(abft_problem, taps) P(abft_problem, bc_value) P(abft_problem, cterm)
   P(abft_problem, cterm_scalar) P(abft_problem, u0) P(abft_problem, u1) P(abft_problem, u2)
   P(abft_options, threshold) P(abft_options, csum) P(abft_options, tuning_cache)
+  P(abft_options, input_check) P(abft_options, correction)
   P(abft_event, a) P(abft_event, grid) P(abft_fault, grid)
   P(abft_report, max_noise) P(abft_report, nevents) P(abft_report, events)
   return 0;

@@ -10,14 +10,14 @@ pytestmark = pytest.mark.gpu
 
 
 def _run_batch(shapes, inputs, nsweeps, plan, *, eps=1e-7, graph=False, persistent=None,
-               autotune=False, chunks=None, csum="f64"):
+               autotune=False, chunks=None, csum="f64", correction="checksum"):
     import torch
     from paper_1909_00709_amd import abft
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         grids = [(torch.from_numpy(u).cuda(), torch.from_numpy(c).cuda()) for u, c in inputs]
         B = abft.Batch(grids, W.THERMAL_TAPS, threshold=eps, csum=csum, stream=stream,
-                       max_events=1 << 14)
+                       max_events=1 << 14, correction=correction)
         try:
             if autotune:
                 B.autotune()
