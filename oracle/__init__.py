@@ -85,8 +85,11 @@ def lib():
         L.orc_detect.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, vp]
         L.orc_detect.restype = ctypes.c_int64
         L.orc_run.argtypes = [P, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                              ctypes.c_int, vp, vp, ctypes.c_int64, vp, ctypes.c_int64, vp,
-                              ctypes.c_int64, ctypes.POINTER(_Counters)]
+                              ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int64, vp,
+                              ctypes.c_int64, vp, ctypes.c_int64, ctypes.POINTER(_Counters)]
+        L.orc_tile_checksums.argtypes = [P, vp, ctypes.c_int, dp]
+        L.orc_const_tile_checksums.argtypes = [P, vp, ctypes.c_int, dp]
+        L.orc_predict_tiles.argtypes = [P, dp, dp, vp, ctypes.c_int, dp]
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_get_threads.restype = ctypes.c_int
         _lib = L
@@ -143,6 +146,25 @@ class Problem:
         B = np.empty((nz, ny))
         lib().orc_row_checksums(self.ref, _ptr(self._grid(u)), _ptr(B))
         return B
+
+    def tile_checksums(self, u, T):
+        nz, ny, nx = self.shape
+        Bt = np.empty((nz, ny, nx // T))
+        lib().orc_tile_checksums(self.ref, _ptr(self._grid(u)), T, _ptr(Bt))
+        return Bt
+
+    def const_tile_checksums(self, C, T):
+        nz, ny, nx = self.shape
+        cBt = np.empty((nz, ny, nx // T))
+        lib().orc_const_tile_checksums(self.ref, _ptr(self._const(C)), T, _ptr(cBt))
+        return cBt
+
+    def predict_tiles(self, cBt, Bt, u, T):
+        Bp = np.empty_like(np.asarray(Bt, dtype=np.float64))
+        lib().orc_predict_tiles(self.ref, _ptr(np.ascontiguousarray(cBt, np.float64)),
+                                _ptr(np.ascontiguousarray(Bt, np.float64)),
+                                _ptr(self._grid(u)), T, _ptr(Bp))
+        return Bp
 
     def weighted_row_checksums(self, u):
         nz, ny, nx = self.shape
@@ -208,10 +230,11 @@ class Problem:
     # ---- whole runs -----------------------------------------------------------------------
     def run(self, u0, nsweeps, C=None, mode=MODE_ONLINE, period=10, eps=1e-12,
             auto_correct=True, faults=None, max_events=100000, input_check=True,
-            recompute=False):
+            recompute=False, tile_x=0):
         """Returns (final grid, events structured array, counters dict).  Online mode:
         input_check also checks each sweep's input rows against the stored checksums;
-        recompute corrects located points by evaluating them again from the sweep's input."""
+        recompute corrects located points by evaluating them again from the sweep's input;
+        tile_x > 0 keeps tile-local checksums of tile_x points (the input check is then off)."""
         u_a = self._grid(u0).copy()
         u_b = np.empty_like(u_a)
         C = self._const(C)
@@ -220,7 +243,8 @@ class Problem:
         ev = np.zeros(max_events, dtype=EVENT_DTYPE)
         cnt = _Counters()
         rc = lib().orc_run(self.ref, _ptr(C), mode, period, eps, int(bool(auto_correct)),
-                           (1 if input_check else 0) | (2 if recompute else 0), _ptr(u_a),
+                           (1 if input_check and not tile_x else 0) | (2 if recompute else 0),
+                           int(tile_x), _ptr(u_a),
                            _ptr(u_b), nsweeps, fptr, nf,
                            _ptr(ev), max_events, ctypes.byref(cnt))
         if rc != 0:

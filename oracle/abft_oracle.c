@@ -184,6 +184,84 @@ void orc_weighted_row_checksums(const orc_problem* p, const void* u, double* W)
         }
 }
 
+/* Tile-local row checksums (the method on sub-domains of T points along x). */
+void orc_tile_checksums(const orc_problem* p, const void* u, int T, double* Bt)
+{
+    const int64_t ntx = p->nx / T;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < p->nz; z++)
+        for (int64_t y = 0; y < p->ny; y++)
+            for (int64_t k = 0; k < ntx; k++) {
+                csum s = {0.0, 0.0};
+                for (int64_t x = k * T; x < (k + 1) * T; x++)
+                    cs_add(&s, ld(p->dtype, u, idx(p, x, y, z)));
+                Bt[(z * p->ny + y) * ntx + k] = cs_val(s);
+            }
+}
+
+void orc_const_tile_checksums(const orc_problem* p, const void* C, int T, double* cBt)
+{
+    const double cs = round_to(p->dtype, p->c_scalar);
+    const int64_t ntx = p->nx / T;
+    for (int64_t z = 0; z < p->nz; z++)
+        for (int64_t y = 0; y < p->ny; y++)
+            for (int64_t k = 0; k < ntx; k++) {
+                csum s = {0.0, 0.0};
+                for (int64_t x = k * T; x < (k + 1) * T; x++)
+                    cs_add(&s, C ? ld(p->dtype, C, idx(p, x, y, z)) : cs);
+                cBt[(z * p->ny + y) * ntx + k] = cs_val(s);
+            }
+}
+
+/* Boundary term of tile k of row (y, z) of u for a shift dx: the ghost points that enter the
+ * tile minus the points that leave it.  Ghosts inside the row are the neighbouring tiles'
+ * points; beyond the row ends the boundary rule applies (G). */
+static double tile_boundary_term(const orc_problem* p, const void* u, int T, int64_t k,
+                                 int64_t y, int64_t z, int dx)
+{
+    const int64_t x0 = k * T;
+    double b = 0.0;
+    if (dx > 0) {
+        for (int q = 0; q < dx; q++)
+            b += ghost(p, u, x0 + T + q, y, z) - ld(p->dtype, u, idx(p, x0 + q, y, z));
+    } else if (dx < 0) {
+        for (int q = 1; q <= -dx; q++)
+            b += ghost(p, u, x0 - q, y, z) - ld(p->dtype, u, idx(p, x0 + T - q, y, z));
+    }
+    return b;
+}
+
+/* Theorem 1 on each tile: b'_{z,y,k} = c_{z,y,k} + sum_S w * (b_{z+dz, y+dy, k} + beta_k(dx)),
+ * the shifted rows mapped by the boundary rule (a row of constant ghosts sums to T * g). */
+void orc_predict_tiles(const orc_problem* p, const double* cBt, const double* Bt,
+                       const void* uin, int T, double* Bp)
+{
+    double* w = rounded_weights(p);
+    const double g = round_to(p->dtype, p->bc_value);
+    const int64_t ntx = p->nx / T;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < p->nz; z++)
+        for (int64_t y = 0; y < p->ny; y++)
+            for (int64_t k = 0; k < ntx; k++) {
+                double acc = cBt[(z * p->ny + y) * ntx + k];
+                for (int t = 0; t < p->ntaps; t++) {
+                    const orc_tap* tp = &p->taps[t];
+                    const int64_t yy = map_coord(p->bc, y + tp->dy, p->ny);
+                    const int64_t zz = map_coord(p->bc, z + tp->dz, p->nz);
+                    double R;
+                    if (yy < 0 || zz < 0) {
+                        R = (double)T * g;
+                    } else {
+                        R = Bt[(zz * p->ny + yy) * ntx + k];
+                        if (tp->dx != 0) R += tile_boundary_term(p, uin, T, k, yy, zz, tp->dx);
+                    }
+                    acc += w[t] * R;
+                }
+                Bp[(z * p->ny + y) * ntx + k] = acc;
+            }
+    free(w);
+}
+
 /* c_y and c_x of Theorem 1: the checksums of the constant term, computed once. */
 void orc_const_row_checksums(const orc_problem* p, const void* C, double* cB)
 {
@@ -390,6 +468,7 @@ typedef struct {
     double* w;       /* rounded weights */
     double c_scalar; /* rounded scalar constant term */
     int reach;       /* largest |offset| of any tap along any axis */
+    int tile;        /* tile-local checksums of this many points, or 0 (whole rows) */
 } run_state;
 
 static void emit(run_state* S, int64_t sweep, int kind, int z, int y, int x, double a, double b)
@@ -654,8 +733,169 @@ static void online_check(run_state* S, int64_t sweep, void* uin, void* uout)
     }
 }
 
+/* Value implied by tile checksum of the tile holding (x, y, z): the predicted tile sum minus
+ * the tile's other points (the partial-sum form of Eq.(10) on the sub-domain). */
+static double tile_value(run_state* S, const void* u, int z, int y, int x)
+{
+    const orc_problem* p = S->p;
+    const int T = S->tile;
+    const int64_t ntx = p->nx / T, k = x / T;
+    csum s = {0.0, 0.0};
+    for (int64_t q = k * T; q < (k + 1) * T; q++)
+        if (q != x) cs_add(&s, ld(p->dtype, u, idx(p, q, y, z)));
+    return S->Bp[((int64_t)z * p->ny + y) * ntx + k] - cs_val(s);
+}
+
+static void recompute_tile(run_state* S, const void* u, int z, int y, int64_t k)
+{
+    const orc_problem* p = S->p;
+    const int T = S->tile;
+    const int64_t ntx = p->nx / T;
+    csum s = {0.0, 0.0};
+    for (int64_t q = k * T; q < (k + 1) * T; q++) cs_add(&s, ld(p->dtype, u, idx(p, q, y, z)));
+    S->Bn[((int64_t)z * p->ny + y) * ntx + k] = cs_val(s);
+}
+
+/* Sections 3.4-3.5 on the tiles of one layer: the layer's flagged columns (whole columns, as
+ * for rows), and for each flagged tile the flagged columns inside its x range.  A flagged tile
+ * with none is a checksum-side mismatch.  A candidate point alone in its tile takes the tile
+ * checksum's value, alone in its column the column's, alone in both their mean (the row
+ * scheme's single-row single-column case); a candidate shared both ways makes the layer
+ * uncorrectable.  With the recompute correction every candidate is evaluated again. */
+static void locate_correct_layer_tiles(run_state* S, int64_t sweep, const void* uin, void* uout,
+                                       int z)
+{
+    const orc_problem* p = S->p;
+    const int T = S->tile;
+    const int64_t ntx = p->nx / T;
+    int K = 0, nt = 0, nc = 0;
+    int* xs = (int*)malloc(sizeof(int) * (size_t)p->nx);
+    int64_t* ft = (int64_t*)malloc(sizeof(int64_t) * (size_t)(p->ny * ntx));
+    int* cy = (int*)malloc(sizeof(int) * (size_t)(p->ny * ntx) * 4 + 16);
+    int* cx = (int*)malloc(sizeof(int) * (size_t)(p->ny * ntx) * 4 + 16);
+    int64_t cap = p->ny * ntx * 4 + 4;
+    for (int x = 0; x < p->nx; x++) {
+        const int64_t l = (int64_t)z * p->nx + x;
+        if (!(fabs(S->An[l] - S->Ap[l]) <= S->eps * fabs(S->Ap[l]))) {
+            xs[K++] = x;
+            S->cnt->cols_flagged++;
+            emit(S, sweep, ORC_EV_COL_FLAG, z, -1, x, S->An[l], S->Ap[l]);
+        }
+    }
+    int overflow = 0;
+    for (int64_t yk = 0; yk < p->ny * ntx; yk++) {
+        const int64_t l = (int64_t)z * p->ny * ntx + yk;
+        if (!S->rflag[l]) continue;
+        ft[nt++] = yk;
+        const int y = (int)(yk / ntx);
+        const int64_t k = yk % ntx;
+        int found = 0;
+        for (int j = 0; j < K; j++)
+            if (xs[j] / T == k) {
+                if (nc >= cap) {
+                    overflow = 1;
+                    break;
+                }
+                cy[nc] = y;
+                cx[nc] = xs[j];
+                nc++;
+                found = 1;
+            }
+        if (!found) {
+            S->cnt->checksum_faults++;
+            emit(S, sweep, ORC_EV_CHECKSUM_FAULT, z, y, (int)(k * T), S->Bn[l], S->Bp[l]);
+        }
+    }
+    if (nc > 0 && (overflow || (S->recompute && nc > ORC_MAX_RECOMPUTE))) {
+        S->cnt->uncorrectable++;
+        emit(S, sweep, ORC_EV_UNCORRECTABLE, z, -1, -1, (double)nt, (double)K);
+    } else if (nc > 0 && S->recompute) {
+        for (int i = 0; i < nc; i++) {
+            const int64_t c = idx(p, cx[i], cy[i], z);
+            const double old = ld(p->dtype, uout, c);
+            st(p->dtype, uout, c, point(p, S->w, S->c_scalar, S->C, uin, cx[i], cy[i], z));
+            const double nv = ld(p->dtype, uout, c);
+            if (memcmp(&old, &nv, sizeof(double)) != 0) {
+                S->cnt->corrected++;
+                emit(S, sweep, ORC_EV_CORRECTED, z, cy[i], cx[i], old, nv);
+            }
+        }
+    } else if (nc > 0) {
+        int ambiguous = 0;
+        int* in_tile = (int*)calloc((size_t)nc, sizeof(int));
+        int* in_col = (int*)calloc((size_t)nc, sizeof(int));
+        for (int i = 0; i < nc; i++)
+            for (int j = 0; j < nc; j++) {
+                if (cy[j] == cy[i] && cx[j] / T == cx[i] / T) in_tile[i]++;
+                if (cx[j] == cx[i]) in_col[i]++;
+            }
+        for (int i = 0; i < nc; i++) ambiguous |= in_tile[i] > 1 && in_col[i] > 1;
+        if (ambiguous) {
+            S->cnt->uncorrectable++;
+            emit(S, sweep, ORC_EV_UNCORRECTABLE, z, -1, -1, (double)nt, (double)K);
+        } else {
+            double* v = (double*)malloc(sizeof(double) * (size_t)nc);
+            for (int i = 0; i < nc; i++) {
+                if (in_tile[i] == 1 && in_col[i] == 1)
+                    v[i] = 0.5 * (tile_value(S, uout, z, cy[i], cx[i]) +
+                                  col_value(S, uout, z, cy[i], cx[i]));
+                else if (in_tile[i] == 1)
+                    v[i] = tile_value(S, uout, z, cy[i], cx[i]);
+                else
+                    v[i] = col_value(S, uout, z, cy[i], cx[i]);
+            }
+            for (int i = 0; i < nc; i++) {
+                const int64_t c = idx(p, cx[i], cy[i], z);
+                const double old = ld(p->dtype, uout, c);
+                st(p->dtype, uout, c, v[i]);
+                S->cnt->corrected++;
+                emit(S, sweep, ORC_EV_CORRECTED, z, cy[i], cx[i], old, ld(p->dtype, uout, c));
+            }
+            free(v);
+        }
+        free(in_tile);
+        free(in_col);
+    }
+    /* checksum update of the flagged tiles */
+    for (int i = 0; i < nt; i++) recompute_tile(S, uout, z, (int)(ft[i] / ntx), ft[i] % ntx);
+    free(xs);
+    free(ft);
+    free(cy);
+    free(cx);
+}
+
+/* Online ABFT with tile-local checksums: the tile sums of the output, their prediction
+ * (Theorem 1 on each tile) and the tile flags; after a flag the column stage of the rows
+ * scheme and the tile case analysis (locate_correct_layer_tiles). */
+static void online_check_tiles(run_state* S, int64_t sweep, const void* uin, void* uout)
+{
+    const orc_problem* p = S->p;
+    const int T = S->tile;
+    const int64_t ntx = p->nx / T, ntiles = (int64_t)p->nz * p->ny * ntx;
+    orc_tile_checksums(p, uout, T, S->Bn);
+    orc_predict_tiles(p, S->cB, S->B, uin, T, S->Bp);
+    const int64_t nf = orc_detect(ntiles, S->Bn, S->Bp, S->eps, S->rflag);
+    for (int64_t l = 0; l < ntiles; l++)
+        if (S->rflag[l]) {
+            S->cnt->rows_flagged++;
+            emit(S, sweep, ORC_EV_ROW_FLAG, (int)(l / (p->ny * ntx)), (int)((l / ntx) % p->ny),
+                 (int)((l % ntx) * T), S->Bn[l], S->Bp[l]);
+        }
+    if (!S->auto_correct || nf == 0) return;
+    orc_col_checksums(p, uin, S->At);
+    orc_col_strips(p, uin, S->cs);
+    orc_predict_cols(p, S->cA, S->At, S->cs, S->Ap);
+    orc_col_checksums(p, uout, S->An);
+    for (int z = 0; z < p->nz; z++) {
+        int any = 0;
+        for (int64_t yk = 0; yk < p->ny * ntx && !any; yk++)
+            any = S->rflag[(int64_t)z * p->ny * ntx + yk];
+        if (any) locate_correct_layer_tiles(S, sweep, uin, uout, z);
+    }
+}
+
 int orc_run(const orc_problem* p, const void* C, int mode, int period, double eps,
-            int auto_correct, int flags, void* u_a, void* u_b, int64_t nsweeps,
+            int auto_correct, int flags, int tile_x, void* u_a, void* u_b, int64_t nsweeps,
             const orc_fault* faults, int64_t nfaults,
             orc_event* events, int64_t max_events, orc_counters* counters)
 {
@@ -664,6 +904,11 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
     if (!u_a || !u_b || !counters || nsweeps < 0) return -1;
     if (mode < ORC_MODE_NONE || mode > ORC_MODE_OFFLINE) return -1;
     if (mode == ORC_MODE_OFFLINE && period < 1) return -1;
+    if (tile_x < 0 || (tile_x > 0 && (p->nx % tile_x != 0 || mode == ORC_MODE_OFFLINE ||
+                                      (flags & ORC_INPUT_CHECK))))
+        return -1;
+    for (int k = 0; k < p->ntaps && tile_x > 0; k++)
+        if (abs(p->taps[k].dx) > tile_x) return -2;
     const int bits = p->dtype == ORC_F32 ? 32 : 64;
     for (int64_t f = 0; f < nfaults; f++) {
         const orc_fault* F = &faults[f];
@@ -675,7 +920,9 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
     memset(counters, 0, sizeof(*counters));
 
     const int64_t n = (int64_t)p->nx * p->ny * p->nz;
-    const int64_t nrows = (int64_t)p->nz * p->ny, ncols = (int64_t)p->nz * p->nx;
+    /* checksum entries: rows, or tiles of rows */
+    const int64_t nrows = (int64_t)p->nz * p->ny * (tile_x > 0 ? p->nx / tile_x : 1),
+                  ncols = (int64_t)p->nz * p->nx;
     const size_t bytes = (size_t)n * elem_size(p->dtype);
     const int rx = orc_strip_width(p, 0), ry = orc_strip_width(p, 1);
 
@@ -687,6 +934,7 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
     S.auto_correct = auto_correct;
     S.input_check = (flags & ORC_INPUT_CHECK) && mode == ORC_MODE_ONLINE;
     S.recompute = (flags & ORC_RECOMPUTE) != 0;
+    S.tile = tile_x;
     S.faults = faults;
     S.nfaults = nfaults;
     S.ev = events;
@@ -716,21 +964,32 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
         if (m > S.reach) S.reach = m;
         if (abs(p->taps[k].dz) > S.reach) S.reach = abs(p->taps[k].dz);
     }
-    orc_const_row_checksums(p, C, S.cB);
+    if (tile_x > 0)
+        orc_const_tile_checksums(p, C, tile_x, S.cB);
+    else
+        orc_const_row_checksums(p, C, S.cB);
     orc_const_col_checksums(p, C, S.cA);
 
     void* uin = u_a;
     void* uout = u_b;
 
     if (mode != ORC_MODE_OFFLINE) {
-        if (mode == ORC_MODE_ONLINE) orc_row_checksums(p, uin, S.B);
+        if (mode == ORC_MODE_ONLINE) {
+            if (tile_x > 0)
+                orc_tile_checksums(p, uin, tile_x, S.B);
+            else
+                orc_row_checksums(p, uin, S.B);
+        }
         if (S.input_check) orc_weighted_row_checksums(p, uin, S.W);
         for (int64_t t = 0; t < nsweeps; t++) {
             inject(&S, uin, t, 0, ORC_FAULT_MEMORY);
             orc_sweep(p, C, uin, uout);
             inject(&S, uout, t, 0, ORC_FAULT_STORE);
             if (mode == ORC_MODE_ONLINE) {
-                online_check(&S, t, uin, uout);
+                if (tile_x > 0)
+                    online_check_tiles(&S, t, uin, uout);
+                else
+                    online_check(&S, t, uin, uout);
                 /* the weighted sums of the output as it stands after any repair */
                 if (S.input_check) orc_weighted_row_checksums(p, uout, S.Wn);
                 double* tmp = S.B;

@@ -105,6 +105,20 @@ void orc_col_checksums(const orc_problem* p, const void* u, double* A);
  * (x + 1) d. */
 void orc_weighted_row_checksums(const orc_problem* p, const void* u, double* W);
 
+/* Tile-local row checksums: the method applied on sub-domains (Section 3.1 defines the sweep
+ * on a domain or sub-domain, chunk or block).  Each row is cut into tiles of T points
+ * (T divides nx); Bt[z][y][k] = sum of u over tile k of row (z, y), compensated.  With C ==
+ * NULL in orc_const_tile_checksums the scalar constant term is used. */
+void orc_tile_checksums(const orc_problem* p, const void* u, int T, double* Bt);
+void orc_const_tile_checksums(const orc_problem* p, const void* C, int T, double* cBt);
+
+/* Theorem 1 for a tile as a sub-domain: the prediction of the next tile sums from the tile
+ * sums of the input, the constant term's tile sums and the boundary terms of the tile, whose
+ * ghost points are the neighbouring tiles' values inside the row and the boundary rule at
+ * the row ends (read from the input grid uin).  Needs |dx| <= T for every tap. */
+void orc_predict_tiles(const orc_problem* p, const double* cBt, const double* Bt,
+                       const void* uin, int T, double* Bp);
+
 /* The constant-term checksums c_y and c_x of Theorem 1. */
 void orc_const_row_checksums(const orc_problem* p, const void* C, double* cB);
 void orc_const_col_checksums(const orc_problem* p, const void* C, double* cA);
@@ -134,7 +148,9 @@ int64_t orc_detect(int64_t n, const double* direct, const double* pred, double e
  * ORC_INPUT_CHECK, each sweep also compares the sums of its input rows with the stored
  * checksums; a mismatched row is repaired before the sweep's own flags are examined (see
  * online_check).  With ORC_RECOMPUTE, located points are evaluated again instead of being
- * rebuilt from the checksums (see locate_correct_layer).  Offline, the
+ * rebuilt from the checksums (see locate_correct_layer).  tile_x > 0 (online or no
+ * protection, without ORC_INPUT_CHECK) keeps tile-local checksums of tile_x points instead of
+ * whole-row checksums (see online_check_tiles); 0 keeps row checksums.  Offline, the
  * checkpoint is the window's first input in place, so a MEMORY fault on a window's first
  * sweep corrupts the checkpoint too.  Events are written up to max_events.  Returns 0 or a
  * negative code. */
@@ -146,7 +162,7 @@ enum {
 };
 
 int orc_run(const orc_problem* p, const void* C, int mode, int period, double eps,
-            int auto_correct, int flags, void* u_a, void* u_b, int64_t nsweeps,
+            int auto_correct, int flags, int tile_x, void* u_a, void* u_b, int64_t nsweeps,
             const orc_fault* faults, int64_t nfaults,
             orc_event* events, int64_t max_events, orc_counters* counters);
 
