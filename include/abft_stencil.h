@@ -127,7 +127,17 @@ typedef struct {
     const char* tuning_cache;   /* autotuner cache file (read at init, written by autotune),
                                    or NULL */
     int32_t correction;         /* an abft_correction value; online contexts and batches */
-    int32_t pad;
+    int32_t tile_x;             /* 0: one checksum per row (Eq.(3)).  T > 0: tile-local
+                                   checksums, the method applied on sub-domains of T points
+                                   along x (Section 3.1's domain or sub-domain): one checksum
+                                   per tile of each row, predicted by Theorem 1 on the tile
+                                   with the neighbouring tiles as ghosts; errors in different
+                                   tiles of one layer are located separately and a change is
+                                   measured against a shorter sum.  On the GPU: online or
+                                   unprotected single grids, star stencils, fp64 checksum
+                                   accumulation, no input_check, T = 64 for fp32 grids and 32
+                                   for fp64 grids, nx a multiple of T; otherwise
+                                   ABFT_E_UNSUPPORTED. */
 } abft_options;
 
 /* Event kinds in the device log. */
@@ -256,7 +266,8 @@ abft_status abft_stencil_correct(abft_ctx* ctx, abft_report* inout);
  * batch context `grid` selects the grid; it must be 0 otherwise. */
 abft_status abft_stencil_current(abft_ctx* ctx, int32_t grid, void** dev_ptr, int64_t* sweep);
 
-/* The device plane [nz][ny] of fp64 row checksums that the next sweep's prediction uses. */
+/* The device plane [nz][ny] of fp64 row checksums that the next sweep's prediction uses
+ * ([nz][ny][nx / T] tile checksums with tile-local checksums of T points). */
 abft_status abft_stencil_checksums(abft_ctx* ctx, int32_t grid, double** dev_ptr);
 
 /* Replaces the fault plan (a test harness for Section 5.1's bit-flip injection).  The plan

@@ -57,7 +57,7 @@ class AbftOptions(ctypes.Structure):
                 ("threshold", ctypes.c_double), ("csum", ctypes.c_int32),
                 ("auto_correct", ctypes.c_int32), ("max_events", ctypes.c_int32),
                 ("input_check", ctypes.c_int32), ("tuning_cache", ctypes.c_char_p),
-                ("correction", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("correction", ctypes.c_int32), ("tile_x", ctypes.c_int32)]
 
 
 class AbftEvent(ctypes.Structure):
@@ -241,13 +241,14 @@ def make_problem(shape, dtype_code, taps, u0_ptr, u1_ptr, u2_ptr=None, cterm_ptr
 
 
 def make_options(mode="online", period=10, threshold=1e-7, csum="f64", auto_correct=True,
-                 max_events=4096, tuning_cache=None, input_check=False, correction="checksum"):
+                 max_events=4096, tuning_cache=None, input_check=False, correction="checksum",
+                 tile_x=0):
     return AbftOptions(_MODE[mode] if isinstance(mode, str) else mode, int(period),
                        float(threshold), _CSUM[csum] if isinstance(csum, str) else csum,
                        int(bool(auto_correct)), int(max_events), int(bool(input_check)),
                        tuning_cache.encode() if tuning_cache else None,
                        _CORRECTION[correction] if isinstance(correction, str) else correction,
-                       0)
+                       int(tile_x))
 
 
 class Stencil:
@@ -259,7 +260,7 @@ class Stencil:
     def __init__(self, u0, taps, *, C=None, c_scalar=0.0, bc="clamp", bc_value=0.0,
                  mode="online", period=10, threshold=1e-7, csum="f64", auto_correct=True,
                  max_events=4096, stream=None, tuning_cache=None, input_check=True,
-                 correction="checksum"):
+                 correction="checksum", tile_x=0):
         import torch
         if not u0.is_cuda or not u0.is_contiguous() or u0.dim() != 3:
             raise ValueError("u0 must be a contiguous 3D device tensor [nz][ny][nx]")
@@ -282,7 +283,7 @@ class Stencil:
                                     C.data_ptr() if C is not None else None, c_scalar, bc,
                                     bc_value)
         self.options = make_options(mode, period, threshold, csum, auto_correct, max_events,
-                                    tuning_cache, input_check, correction)
+                                    tuning_cache, input_check and not tile_x, correction, tile_x)
         s, ctx = abft_stencil_init(self.problem, self.options, self.stream.cuda_stream)
         if s != ABFT_OK:
             raise AbftError(s, abft_last_error(None))

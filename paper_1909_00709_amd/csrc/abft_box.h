@@ -395,6 +395,8 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
                             RowFlag rf;
                             rf.z = z;
                             rf.y = y;
+                            rf.k = 0;
+                            rf.pad = 0;
                             rf.direct = S;
                             rf.pred = bp;
                             a.slot->rows[i] = rf;

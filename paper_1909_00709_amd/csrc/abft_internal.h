@@ -55,6 +55,8 @@ struct Stencil {
 
 struct RowFlag {
     int32_t z, y;
+    int32_t k;              // tile index along x (tile-local checksums), 0 for whole rows
+    int32_t pad;
     double direct, pred;
 };
 
@@ -85,7 +87,8 @@ struct Counters {
 // Sweep kernel variants.
 // PROT: checksum, prediction and comparison fused in the sweep; PROTM: PROT plus the check of
 // the input rows against their stored checksums and the output's index-weighted row sums.
-enum { MODE_PLAIN = 0, MODE_CSUM = 1, MODE_PROT = 2, MODE_PROTM = 3 };
+// TILE: tile-local output sums and tile boundary terms (the check is a separate launch).
+enum { MODE_PLAIN = 0, MODE_CSUM = 1, MODE_PROT = 2, MODE_PROTM = 3, MODE_TILE = 4 };
 enum { CS_F64 = 0, CS_F32C = 1 };
 
 struct SweepArgs {
@@ -104,6 +107,7 @@ struct SweepArgs {
     const double* Bt;       // row checksums of uin (prediction input)
     double* Bn;             // row checksums of uout (written)
     double* Wn;             // index-weighted row sums of uout (written by the PROTM sweep)
+    double* Et;             // TILE: boundary terms of the input's tiles (written)
     const double* cB;       // constant-term row checksums
     double eps;
     FlagSlot* slot;         // flagged rows of this sweep
@@ -136,6 +140,7 @@ struct FixArgs {
     const void* C;
     double c_scalar;
     int32_t recompute;      // correct located points by evaluating them again (else Eq.(10))
+    int32_t tile_x;         // tile-local checksums of this many points, or 0 (whole rows)
     Stencil st;
     int32_t nx, ny, nz;
     double eps;
@@ -254,6 +259,25 @@ hipError_t launch_check(const CheckArgs& a, hipStream_t st);
 size_t check_lds_bytes(int ry, int rz);
 hipError_t launch_row_sums(int dtype, const void* u, double cs, int nx, int64_t nrows,
                            double* out, hipStream_t st);
+// Tile-local checksums: the prediction of every tile's sum (Theorem 1 on the tile) and the
+// comparison, after a MODE_TILE sweep.
+struct TileCheckArgs {
+    const double* Bt;       // tile sums of the input
+    const double* Bn;       // tile sums of the output (direct)
+    const double* cB;       // tile sums of the constant term
+    const double* Et;       // boundary terms of the input's tiles
+    Stencil st;
+    int32_t nx, ny, nz, tile_x;
+    double eps;
+    FlagSlot* slot;
+    Counters* cnt;
+    abft_event* ev;
+    int32_t ev_cap;
+    int32_t grid;
+    const int64_t* t_base;
+    int64_t t_off;
+};
+hipError_t launch_tile_check(const TileCheckArgs& a, hipStream_t st);
 hipError_t launch_weighted_row_sums(int dtype, const void* u, int nx, int64_t nrows, double* out,
                                     hipStream_t st);
 // Memory-resident faults of the plan for sweep t (kind MEMORY, first attempt): flip them in
@@ -314,6 +338,8 @@ ABFT_DECL_SWEEP(launch_sweep_r2_f32_protm)
 ABFT_DECL_SWEEP(launch_sweep_r2_f64_protm)
 ABFT_DECL_SWEEP(launch_sweep_box_f32_protm)
 ABFT_DECL_SWEEP(launch_sweep_box_f64_protm)
+ABFT_DECL_SWEEP(launch_sweep_f32_tile)
+ABFT_DECL_SWEEP(launch_sweep_f64_tile)
 #undef ABFT_DECL_SWEEP
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st);
 

@@ -279,6 +279,187 @@ __device__ int repair_inputs(const FixArgs& a, double* red, int64_t t)
 }
 
 // ------------------------------------------------------------------------------------------
+// Location and correction on the tiles of one layer (tile-local checksums).  The flagged
+// tiles are slot->rows[i .. j) (sorted by y, then tile), the layer's flagged columns xs[0 .. K)
+// (ascending).  The candidates of a tile are the flagged columns inside its x range.  A
+// flagged tile without one is a checksum-side mismatch.  A candidate alone in its tile takes
+// the tile checksum's value (its predicted sum minus the tile's other points), alone in its
+// column the column's, alone in both their mean; a candidate shared both ways makes the layer
+// uncorrectable.  With the recompute correction every candidate is evaluated again.  Then the
+// flagged tiles' sums are recomputed.
+// ------------------------------------------------------------------------------------------
+template <typename T, int RAD>
+__device__ void fix_tiles_layer(const FixArgs& a, int i, int j, int z, const int* xs, int K,
+                                const double* Ap, double* red, int& sh, int64_t t)
+{
+    FlagSlot* slot = a.slot;
+    const int tid = threadIdx.x, TT = a.tile_x, nx = a.nx, ny = a.ny, ntx = nx / TT;
+    const size_t ps = (size_t)nx * (size_t)ny;
+    T* uout = static_cast<T*>(a.uout);
+    const T* uin = static_cast<const T*>(a.uin);
+    // first flagged column at or after x (xs ascending)
+    auto first_col = [&](int x) {
+        int lo = 0, hi = K;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (xs[mid] < x) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
+    // flagged tiles of the layer with tile index k
+    auto tiles_at = [&](int k) {
+        int n = 0;
+        for (int ri = i; ri < j; ++ri) n += slot->rows[ri].k == k;
+        return n;
+    };
+    if (tid == 0) {
+        int ambiguous = 0, nc = 0;
+        for (int ri = i; ri < j; ++ri) {
+            const RowFlag& rf = slot->rows[ri];
+            const int c0 = first_col(rf.k * TT), c1 = first_col(rf.k * TT + TT);
+            const int nin = c1 - c0;
+            nc += nin;
+            if (nin == 0) {
+                atomicAdd(&a.cnt->checksum_faults, 1ull);
+                emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_CHECKSUM_FAULT, z, rf.y, rf.k * TT,
+                           rf.direct, rf.pred, a.grid);
+            } else if (nin > 1 && tiles_at(rf.k) > 1) {
+                ambiguous = 1;
+            }
+        }
+        const bool can = a.recompute ? nc <= kMaxRecompute : !ambiguous;
+        if (nc > 0 && !can) {
+            atomicAdd(&a.cnt->uncorrectable, 1ull);
+            emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_UNCORRECTABLE, z, -1, -1,
+                       (double)(j - i), (double)K, a.grid);
+        }
+        sh = (nc > 0 && can) ? 1 : 0;
+    }
+    __syncthreads();
+    const bool correct = sh != 0;
+    __syncthreads();
+    if (correct) {
+        for (int ri = i; ri < j; ++ri) {
+            const RowFlag rf = slot->rows[ri];
+            const int c0 = first_col(rf.k * TT), c1 = first_col(rf.k * TT + TT);
+            const int nin = c1 - c0;
+            T* row = uout + (size_t)z * ps + (size_t)rf.y * nx;
+            if (a.recompute) {
+                for (int q = c0 + tid; q < c1; q += kFixBlock) {
+                    const int x = xs[q];
+                    const T old = row[x];
+                    const T nv = point_value<T, RAD, 0>(a, uin, x, rf.y, z);
+                    if (!same_bits(old, nv)) {
+                        row[x] = nv;
+                        atomicAdd(&a.cnt->corrected, 1ull);
+                        emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_CORRECTED, z, rf.y, x,
+                                   (double)old, (double)nv, a.grid);
+                    }
+                }
+                continue;
+            }
+            const int ncol = tiles_at(rf.k);  // candidates in each of this tile's columns
+            for (int q = c0; q < c1; ++q) {
+                const int x = xs[q];
+                double vt = 0.0, vc = 0.0;
+                if (nin == 1) {
+                    double p = 0.0;
+                    for (int xx = rf.k * TT + tid; xx < rf.k * TT + TT; xx += kFixBlock)
+                        if (xx != x) p += (double)row[xx];
+                    vt = rf.pred - block_sum(p, red);
+                }
+                if (ncol == 1) {
+                    double p = 0.0;
+                    for (int yy = tid; yy < ny; yy += kFixBlock)
+                        if (yy != rf.y) p += (double)uout[(size_t)z * ps + (size_t)yy * nx + x];
+                    vc = Ap[x] - block_sum(p, red);
+                }
+                if (tid == 0) {
+                    const double v = (nin == 1 && ncol == 1) ? 0.5 * (vt + vc)
+                                                             : (nin == 1 ? vt : vc);
+                    const T old = row[x];
+                    row[x] = (T)v;
+                    atomicAdd(&a.cnt->corrected, 1ull);
+                    emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_CORRECTED, z, rf.y, x,
+                               (double)old, (double)(T)v, a.grid);
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+    }
+    // checksum update of the flagged tiles
+    for (int ri = i; ri < j; ++ri) {
+        const RowFlag rf = slot->rows[ri];
+        const T* row = uout + (size_t)z * ps + (size_t)rf.y * nx + (size_t)rf.k * TT;
+        double p = 0.0;
+        for (int xx = tid; xx < TT; xx += kFixBlock) p += (double)row[xx];
+        const double S = block_sum(p, red);
+        if (tid == 0) a.Bn[((size_t)z * ny + rf.y) * ntx + rf.k] = S;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Tile-local checksums: Theorem 1 on every tile and the comparison, one thread per tile.
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) tile_check_kernel(const TileCheckArgs a)
+{
+    const int TT = a.tile_x, ntx = a.nx / TT, ny = a.ny, nz = a.nz, bc = a.st.bc;
+    const int64_t n = (int64_t)nz * ny * ntx;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t t = a.t_off + (a.t_base != nullptr ? *a.t_base : 0);
+    const unsigned long long known = noise_known(a.cnt);
+    double noise = 0.0;
+    if (i < n) {
+        const int k = (int)(i % ntx);
+        const int y = (int)((i / ntx) % ny), z = (int)(i / ((int64_t)ntx * ny));
+        const uint32_t m = a.st.mask;
+        auto btile = [&](int z2, int y2) -> double {
+            const int mz = map_coord(z2, nz, bc), my = map_coord(y2, ny, bc);
+            if (mz < 0 || my < 0) return (double)TT * a.st.g;
+            return a.Bt[((size_t)mz * ny + my) * ntx + k];
+        };
+        const double b0 = a.Bt[i];
+        double bp = a.cB[i];
+        if (m & (1u << W_C)) bp += a.st.w[W_C] * b0;
+        for (int d = 1; d <= 2; ++d) {
+            if (m & (1u << w_slot(0, d, -1))) bp += a.st.w[w_slot(0, d, -1)] * b0;
+            if (m & (1u << w_slot(0, d, 1))) bp += a.st.w[w_slot(0, d, 1)] * b0;
+        }
+        bp += a.Et[i];
+        for (int d = 1; d <= 2; ++d) {
+            if (m & (1u << w_slot(1, d, -1))) bp += a.st.w[w_slot(1, d, -1)] * btile(z, y - d);
+            if (m & (1u << w_slot(1, d, 1))) bp += a.st.w[w_slot(1, d, 1)] * btile(z, y + d);
+            if (m & (1u << w_slot(2, d, -1))) bp += a.st.w[w_slot(2, d, -1)] * btile(z - d, y);
+            if (m & (1u << w_slot(2, d, 1))) bp += a.st.w[w_slot(2, d, 1)] * btile(z + d, y);
+        }
+        const double S = a.Bn[i];
+        const double dlt = fabs(S - bp);
+        if (!(dlt <= a.eps * fabs(bp))) {
+            const unsigned f = atomicAdd(&a.slot->count, 1u);
+            if (f < (unsigned)kMaxFlags) {
+                RowFlag rf;
+                rf.z = z;
+                rf.y = y;
+                rf.k = k;
+                rf.pad = 0;
+                rf.direct = S;
+                rf.pred = bp;
+                a.slot->rows[f] = rf;
+            } else {
+                atomicAdd(&a.cnt->overflow, 1ull);
+            }
+            atomicAdd(&a.cnt->rows_flagged, 1ull);
+            emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_ROW_FLAG, z, y, k * TT, S, bp, a.grid);
+        } else if (bp != 0.0) {
+            noise = dlt / fabs(bp);
+        }
+    }
+    record_noise(a.cnt, noise, known);
+}
+
+// ------------------------------------------------------------------------------------------
 // Locate and correct after a sweep whose row checks flagged something (Sections 3.4-3.5).
 // One block.  For each layer with flagged rows: the column checksums of the layer (Eq.(2)),
 // their prediction from the input grid (Theorem 1, Eq.(4)), the flagged columns, and the
@@ -353,7 +534,9 @@ __device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* re
             const RowFlag key = slot->rows[i];
             int j = i - 1;
             while (j >= 0 && (slot->rows[j].z > key.z ||
-                              (slot->rows[j].z == key.z && slot->rows[j].y > key.y))) {
+                              (slot->rows[j].z == key.z && (slot->rows[j].y > key.y ||
+                                                            (slot->rows[j].y == key.y &&
+                                                             slot->rows[j].k > key.k))))) {
                 slot->rows[j + 1] = slot->rows[j];
                 --j;
             }
@@ -535,7 +718,9 @@ __device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* re
         __syncthreads();
         const int K = sh_K;
 
-        if (K == 0) {
+        if (a.tile_x > 0) {
+            fix_tiles_layer<T, RAD>(a, i, j, z, xs, K, Ap, red, sh_K, t);
+        } else if (K == 0) {
             // the layer is consistent column-wise: the mismatch sits in a checksum
             if (tid == 0)
                 for (int ri = i; ri < j; ++ri) {
@@ -975,6 +1160,13 @@ hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, cons
     if (!sweep_shape_supported(dtype, s)) return hipErrorInvalidValue;
     const size_t lds = sweep_lds_bytes(dtype, a.nx, s, mode == MODE_PROTM);
     if (mode == MODE_PLAIN) csum = CS_F64;  // no checksum in the plain variant
+    if (mode == MODE_TILE) {
+        if (s.box || s.vec != 16 / (dtype == ABFT_F32 ? 4 : 8) || a.Bn == nullptr ||
+            a.Et == nullptr)
+            return hipErrorInvalidValue;
+        return dtype == ABFT_F32 ? launch_sweep_f32_tile(csum, s, a, st, lds)
+                                 : launch_sweep_f64_tile(csum, s, a, st, lds);
+    }
     if (mode == MODE_PROTM) {
         if (a.Wn == nullptr) return hipErrorInvalidValue;
         const bool f32 = dtype == ABFT_F32;
@@ -1077,6 +1269,14 @@ hipError_t launch_fixup(int dtype, const FixArgs& a, hipStream_t st)
     if (box) return go(fixup_kernel<double, 1, 1>);
     if (r2) return go(fixup_kernel<double, 2, 0>);
     return go(fixup_kernel<double, 1, 0>);
+}
+
+hipError_t launch_tile_check(const TileCheckArgs& a, hipStream_t st)
+{
+    if (a.tile_x < 1 || a.nx % a.tile_x) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)a.nz * a.ny * (a.nx / a.tile_x);
+    hipLaunchKernelGGL(tile_check_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 size_t check_lds_bytes(int ry, int rz) { return (size_t)2 * ry * rz * sizeof(double); }

@@ -47,6 +47,7 @@ struct abft_ctx {
     bool own_u2 = false;
     // options
     int mode = 0, period = 1, csum = CS_F64, auto_correct = 1, input_check = 0, recompute = 0;
+    int tile_x = 0;              // tile-local checksums of this many points, or 0 (rows)
     double eps = 0.0;
     std::string cache_path;
     hipStream_t stream = nullptr;
@@ -54,6 +55,7 @@ struct abft_ctx {
     std::vector<void*> allocs;
     double* B[2] = {nullptr, nullptr};
     double* W[2] = {nullptr, nullptr};  // online: index-weighted row sums beside B
+    double* Et = nullptr;        // tile-local checksums: boundary terms of the input's tiles
     double* cB = nullptr;
     double* cA = nullptr;
     FlagSlot* slot[2] = {nullptr, nullptr};
@@ -259,6 +261,8 @@ abft_status apply_shape(abft_ctx* c, const SweepShape& shape)
     if (!sweep_shape_supported(c->dtype, s)) return fail(c, ABFT_E_UNSUPPORTED, "launch shape");
     if ((int64_t)s.lpr * s.nch * s.vec < c->nx) return fail(c, ABFT_E_UNSUPPORTED, "row too long");
     if (s.vec > 1 && c->nx % s.vec) return fail(c, ABFT_E_UNSUPPORTED, "row not 16-byte multiple");
+    if (c->tile_x && s.vec != 16 / (int)esize(c->dtype))
+        return fail(c, ABFT_E_UNSUPPORTED, "tile-local checksums need 16-byte accesses");
     if (sweep_lds_bytes(c->dtype, c->nx, s, c->input_check) > kSweepLdsLimit)
         return fail(c, ABFT_E_UNSUPPORTED, "rows too long for the LDS plane buffers");
     const int ty = sweep_rows_per_block(s);
@@ -429,6 +433,7 @@ FixArgs online_fix_args(const abft_ctx* c, int in, int bin, int64_t t, const int
     f.C = c->C;
     f.c_scalar = c->cs;
     f.recompute = c->recompute;
+    f.tile_x = c->tile_x;
     f.st = c->st;
     f.nx = c->nx;
     f.ny = c->ny;
@@ -453,7 +458,13 @@ abft_status enqueue_online(abft_ctx* c, int64_t n, const int64_t* tbase, int64_t
         a.t_base = tbase;
         a.t_off = tbase ? t - t0 : t;
         int mode = MODE_PLAIN;
-        if (c->mode == ABFT_MODE_ONLINE) {
+        if (c->mode == ABFT_MODE_ONLINE && c->tile_x) {
+            mode = MODE_TILE;
+            a.Bn = c->B[c->bcur ^ 1];
+            a.Et = c->Et;
+            a.zero_ptr = &c->slot[(t + 1) & 1]->count;
+            a.zero_n = 2;
+        } else if (c->mode == ABFT_MODE_ONLINE) {
             mode = c->input_check ? MODE_PROTM : MODE_PROT;
             a.Bt = c->B[c->bcur];
             a.Bn = c->B[c->bcur ^ 1];
@@ -470,6 +481,27 @@ abft_status enqueue_online(abft_ctx* c, int64_t n, const int64_t* tbase, int64_t
         }
         e = launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
+        if (mode == MODE_TILE) {
+            TileCheckArgs k{};
+            k.Bt = c->B[c->bcur];
+            k.Bn = c->B[c->bcur ^ 1];
+            k.cB = c->cB;
+            k.Et = c->Et;
+            k.st = c->st;
+            k.nx = c->nx;
+            k.ny = c->ny;
+            k.nz = c->nz;
+            k.tile_x = c->tile_x;
+            k.eps = c->eps;
+            k.slot = c->slot[t & 1];
+            k.cnt = c->cnt;
+            k.ev = c->ev;
+            k.ev_cap = c->ev_cap;
+            k.t_base = tbase;
+            k.t_off = a.t_off;
+            e = launch_tile_check(k, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "tile check launch");
+        }
         if (c->mode == ABFT_MODE_ONLINE && c->auto_correct) {
             const FixArgs f = online_fix_args(c, c->cur, c->bcur, t, tbase, a.t_off);
             e = launch_fixup(c->dtype, f, c->stream);
@@ -920,6 +952,7 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
     c->auto_correct = o->auto_correct ? 1 : 0;
     c->recompute = o->correction == ABFT_CORRECT_RECOMPUTE ? 1 : 0;
     c->input_check = (o->input_check && o->mode == ABFT_MODE_ONLINE) ? 1 : 0;
+    c->tile_x = o->tile_x;
     c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
     if (o->tuning_cache) c->cache_path = o->tuning_cache;
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -940,6 +973,15 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
 
     s = map_taps(c, p);
     if (s) return bail(s);
+    if (c->tile_x != 0) {
+        // tiles are the 16 lanes x 16 bytes one lane group of the sweep holds of a row
+        const int tt = 16 * (16 / (int)esize(c->dtype));
+        if (c->tile_x != tt || c->nx % tt || c->st.box || c->input_check ||
+            c->mode == ABFT_MODE_OFFLINE || c->csum != CS_F64)
+            return bail(fail(c, ABFT_E_UNSUPPORTED, "tile-local checksums: online star "
+                                                    "stencils, T = 64 (fp32) or 32 (fp64), "
+                                                    "T dividing nx, fp64 accumulation"));
+    }
     SweepShape shape{};
     if (c->st.rad == 2) {
         // the shifted-line sums of Theorem 1 (and the periodic wrap) need every axis that
@@ -970,7 +1012,9 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
             return bail(fail(c, ABFT_E_UNSUPPORTED, "offline period too long for this grid"));
     }
 
-    const size_t nrows = (size_t)c->nz * c->ny, ncols = (size_t)c->nz * c->nx;
+    // checksum entries: one per row, or one per tile of each row
+    const size_t nrows = (size_t)c->nz * c->ny * (c->tile_x ? c->nx / c->tile_x : 1),
+                 ncols = (size_t)c->nz * c->nx;
     const size_t gbytes = (size_t)c->nx * c->ny * c->nz * esize(c->dtype);
     if ((s = dalloc(c, &c->B[0], nrows * 8)) || (s = dalloc(c, &c->B[1], nrows * 8)) ||
         (s = dalloc(c, &c->cB, nrows * 8)) || (s = dalloc(c, &c->cA, ncols * 8)) ||
@@ -985,6 +1029,7 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
     if (c->input_check &&
         ((s = dalloc(c, &c->W[0], nrows * 8)) || (s = dalloc(c, &c->W[1], nrows * 8))))
         return bail(s);
+    if (c->tile_x && (s = dalloc(c, &c->Et, nrows * 8))) return bail(s);
     if (c->mode == ABFT_MODE_OFFLINE) {
         if (p->u2 != nullptr) {
             if (p->u2 == p->u0 || p->u2 == p->u1)
@@ -1015,9 +1060,11 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
     INIT_CHK(launch_fill_u32(c->ticket, 0u, 4, c->stream));
     INIT_CHK(launch_set_i64(c->tbase, 0, c->stream));
     // Theorem 1's constant-term checksums and the checksums of u^0
-    INIT_CHK(launch_row_sums(c->dtype, c->C, c->cs, c->nx, (int64_t)nrows, c->cB, c->stream));
+    // a tile is a contiguous run of tile_x points, so tile sums are row sums of that length
+    const int line = c->tile_x ? c->tile_x : c->nx;
+    INIT_CHK(launch_row_sums(c->dtype, c->C, c->cs, line, (int64_t)nrows, c->cB, c->stream));
     INIT_CHK(launch_col_sums(c->dtype, c->C, c->cs, c->nx, c->ny, c->nz, c->cA, c->stream));
-    INIT_CHK(launch_row_sums(c->dtype, c->u[0], 0.0, c->nx, (int64_t)nrows, c->B[0], c->stream));
+    INIT_CHK(launch_row_sums(c->dtype, c->u[0], 0.0, line, (int64_t)nrows, c->B[0], c->stream));
     if (c->W[0] != nullptr)
         INIT_CHK(launch_weighted_row_sums(c->dtype, c->u[0], c->nx, (int64_t)nrows, c->W[0],
                                           c->stream));
@@ -1289,7 +1336,7 @@ abft_status abft_stencil_autotune(abft_ctx* c)
     double* sB = nullptr;
     double* sW = nullptr;
     abft_status s;
-    const size_t nrows = (size_t)c->nz * c->ny;
+    const size_t nrows = (size_t)c->nz * c->ny * (c->tile_x ? c->nx / c->tile_x : 1);
     if ((s = dalloc(c, &sslot, sizeof(FlagSlot))) || (s = dalloc(c, &scnt, sizeof(Counters))) ||
         (s = dalloc(c, &sB, nrows * 8)) || (s = dalloc(c, &sW, nrows * 8)))
         return s;
@@ -1300,6 +1347,7 @@ abft_status abft_stencil_autotune(abft_ctx* c)
     std::vector<SweepShape> cands;
     for (int vec : {vf, 1}) {
         if (vec > 1 && c->nx % vec) continue;
+        if (c->tile_x && vec != vf) continue;  // tiles are 16 lanes of 16-byte accesses
         for (int lpr : {16, 64})
             for (int nch : {1, 2, 4, 8, 16}) {
                 for (int pf : {1, 2})
@@ -1323,7 +1371,7 @@ abft_status abft_stencil_autotune(abft_ctx* c)
     SweepShape best = keep;
     float best_ms = 1e30f;
     const int mode = c->mode != ABFT_MODE_ONLINE ? MODE_PLAIN
-                     : (c->input_check ? MODE_PROTM : MODE_PROT);
+                     : (c->tile_x ? MODE_TILE : (c->input_check ? MODE_PROTM : MODE_PROT));
     for (const SweepShape& sh : cands) {
         if (apply_shape(c, sh)) continue;
         SweepArgs a = base_args(c);
@@ -1338,6 +1386,7 @@ abft_status abft_stencil_autotune(abft_ctx* c)
         a.Bt = c->mode == ABFT_MODE_OFFLINE ? c->B[c->bck] : c->B[c->bcur];
         a.Bn = sB;
         if (mode == MODE_PROTM) a.Wn = sW;
+        if (mode == MODE_TILE) a.Et = sW;  // the sweep's tile boundary terms (scratch)
         a.t_off = c->t;
         bool ok = true;
         for (int w = 0; w < 2 && ok; ++w)

@@ -105,6 +105,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
     using V = VecOps<T, VEC>;
     constexpr bool kProt = MODE == MODE_PROT || MODE == MODE_PROTM;
     constexpr bool kMemChk = MODE == MODE_PROTM;  // also the input-side check (a.Wn set)
+    constexpr bool kRowSum = MODE == MODE_CSUM || kProt;  // whole-row checksums
+    constexpr bool kTile = MODE == MODE_TILE;             // tile-local checksums instead
     constexpr int NT = NW * 64;       // threads per block
     constexpr int RPW = 64 / LPR;     // rows per wavefront
     constexpr int TY = NW * RPW;      // rows per block
@@ -467,9 +469,57 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
         // x-boundary term of Theorem 1 from the input row (its first and last RAD points and
         // the ghosts).  Both go to a small LDS table; the prediction and the comparison for
         // all planes of the tile run after the march, so none of their loads sits in this loop.
-        if constexpr (MODE != MODE_PLAIN) {
+        if constexpr (kRowSum) {
             const double S = row_sum<CS, LPR, NCH, VEC>(o);
             if (row_ok && sl == 0) tabS[r * a.tz + (z - z0)] = S;
+        }
+        if constexpr (kTile) {
+            // Tile-local checksums: a tile is the 16 * VEC consecutive points one 16-lane group
+            // holds of a chunk.  Its output sum (a 16-lane reduction) and its x-boundary term
+            // of Theorem 1 on the tile as a sub-domain, from the input row in LDS: a shift
+            // dx < 0 brings in the points before the tile (a neighbouring tile's, or ghosts)
+            // and drops its last |dx|; dx > 0 brings in the points after it and drops its first
+            // dx.  The group's first lane forms the terms at the tile's start, its last lane
+            // those at the end, and a row mirror adds them.  The prediction and the comparison
+            // run in a separate launch over all tiles.
+            constexpr int TT = 16 * VEC;
+            const int g16 = sl & 15;
+            const int ntx = nx / TT;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                double p = 0.0;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) p += (double)o[c][v];
+                const double ts = row16_sum(p);
+                const int x0 = c * SEGW + (sl - g16) * VEC;
+                double ep = 0.0;
+                if (row_ok && x0 < nx && (g16 == 0 || g16 == 15)) {
+#pragma unroll
+                    for (int d = 1; d <= RAD; ++d) {
+                        const double wm = has(w_slot(0, d, -1)) ? a.st.w[w_slot(0, d, -1)] : 0.0;
+                        const double wp = has(w_slot(0, d, 1)) ? a.st.w[w_slot(0, d, 1)] : 0.0;
+                        double in_m = 0.0, out_m = 0.0, in_p = 0.0, out_p = 0.0;
+                        if (g16 == 0) {
+#pragma unroll
+                            for (int q = 1; q <= d; ++q) in_m += (double)row0[x0 - q];
+#pragma unroll
+                            for (int q = 0; q < d; ++q) out_p += (double)row0[x0 + q];
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < d; ++q) in_p += (double)row0[x0 + TT + q];
+#pragma unroll
+                            for (int q = 1; q <= d; ++q) out_m += (double)row0[x0 + TT - q];
+                        }
+                        ep += wm * (in_m - out_m) + wp * (in_p - out_p);
+                    }
+                }
+                const double e = ep + dpp_d<DPP_ROW_MIRROR>(ep);
+                if (row_ok && x0 < nx && g16 == 0) {
+                    const size_t lt = ((size_t)z * ny + y) * ntx + x0 / TT;
+                    a.Bn[lt] = ts;
+                    a.Et[lt] = e;
+                }
+            }
         }
         if constexpr (kMemChk) {
             // the index-weighted sum of the output row, which places a changed point later
@@ -521,7 +571,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                 }
     }
 
-    if constexpr (MODE == MODE_PLAIN) {
+    if constexpr (!kRowSum) {
         if (a.E == nullptr) return;
     }
     __syncthreads();
@@ -533,7 +583,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             const int z = z0 + pz;
             const size_t l = (size_t)z * ny + y;
             if (a.E != nullptr) a.E[l] = tabE[r * a.tz + pz];
-            if constexpr (MODE != MODE_PLAIN) {
+            if constexpr (kRowSum) {
                 const double S = tabS[r * a.tz + pz];
                 a.Bn[l] = S;
                 if constexpr (kProt) {
@@ -574,6 +624,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                             RowFlag rf;
                             rf.z = z;
                             rf.y = y;
+                            rf.k = 0;
+                            rf.pad = 0;
                             rf.direct = S;
                             rf.pred = bp;
                             a.slot->rows[i] = rf;
@@ -647,8 +699,10 @@ hipError_t launch_sweep_t(const SweepShape& s, const SweepArgs& a, hipStream_t s
     ABFT_SWEEP_CASE(64, 2, VF)
     ABFT_SWEEP_CASE(64, 4, VF)
     ABFT_SWEEP_CASE(64, 8, VF)
-    ABFT_SWEEP_CASE(64, 4, 1)
-    ABFT_SWEEP_CASE(64, 16, 1)
+    if constexpr (MODE != MODE_TILE) {  // tiles are 16 lanes of 16-byte accesses
+        ABFT_SWEEP_CASE(64, 4, 1)
+        ABFT_SWEEP_CASE(64, 16, 1)
+    }
 #undef ABFT_SWEEP_CASE
 #undef ABFT_SWEEP_CASE_PF
 #undef ABFT_SWEEP_CASE_NW

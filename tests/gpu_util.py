@@ -23,7 +23,7 @@ def say(*args):
 def run_gpu(u0, taps, nsweeps, *, C=None, c_scalar=0.0, mode="online", eps=1e-12, period=10,
             csum="f64", auto_correct=True, plan=None, bc="clamp", bc_value=0.0, graph=False,
             chunks=None, max_events=1 << 16, autotune=False, input_check=True,
-            correction="checksum"):
+            correction="checksum", tile_x=0):
     """Returns (final grid as numpy, events, report, stencil-shape)."""
     import torch
     from paper_1909_00709_amd import abft
@@ -34,7 +34,7 @@ def run_gpu(u0, taps, nsweeps, *, C=None, c_scalar=0.0, mode="online", eps=1e-12
         S = abft.Stencil(ut, taps, C=Ct, c_scalar=c_scalar, bc=bc, bc_value=bc_value, mode=mode,
                          period=period, threshold=eps, csum=csum, auto_correct=auto_correct,
                          max_events=max_events, stream=stream, input_check=input_check,
-                         correction=correction)
+                         correction=correction, tile_x=tile_x)
         try:
             if autotune:
                 S.autotune()
@@ -54,14 +54,14 @@ def run_gpu(u0, taps, nsweeps, *, C=None, c_scalar=0.0, mode="online", eps=1e-12
 
 def run_oracle(u0, taps, nsweeps, *, C=None, c_scalar=0.0, mode="online", eps=1e-12, period=10,
                auto_correct=True, plan=None, bc="clamp", bc_value=0.0, dtype=None,
-               input_check=True, recompute=False):
+               input_check=True, recompute=False, tile_x=0):
     bcs = {"clamp": O.BC_CLAMP, "periodic": O.BC_PERIODIC, "constant": O.BC_CONSTANT}
     modes = {"none": O.MODE_NONE, "online": O.MODE_ONLINE, "offline": O.MODE_OFFLINE}
     dt = dtype if dtype is not None else (O.F32 if u0.dtype == np.float32 else O.F64)
     p = O.Problem(u0.shape, dt, taps, bc=bcs[bc], bc_value=bc_value, c_scalar=c_scalar)
     return p.run(u0, nsweeps, C, mode=modes[mode], period=period, eps=eps,
                  auto_correct=auto_correct, faults=plan, input_check=input_check,
-                 recompute=recompute)
+                 recompute=recompute, tile_x=tile_x)
 
 
 def event_keys(ev, kinds=(1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11), skip=None):
