@@ -309,6 +309,47 @@ def bench_radius2(stream, timed, u0, C, tune=True, k=10, steps=10, taps=DIFF4_TA
     return res
 
 
+def bench_tiles(stream, timed, u0, C, tune=True, k=10, steps=10):
+    """Tile-local checksums (64-point tiles) on the large grid against whole-row checksums:
+    the protected sweep with its check (no locate launches) and online ABFT (graph), each
+    autotuned."""
+    import torch
+
+    import workloads as W
+    from paper_1909_00709_amd import abft
+
+    npts = u0.numel()
+    res = {"workload": f"7-point thermal, {tuple(u0.shape)} fp32, 64-point tiles vs rows"}
+    for name, mode, kw in (("plain", "none", {}),
+                           ("rows_prot_kernel", "online", dict(auto_correct=False)),
+                           ("tiles_prot_kernel", "online", dict(auto_correct=False, tile_x=64)),
+                           ("rows_online", "online", {}),
+                           ("tiles_online", "online", dict(tile_x=64))):
+        with torch.cuda.stream(stream):
+            S = abft.Stencil(u0.clone(), W.THERMAL_TAPS, C=C, mode=mode, stream=stream,
+                             threshold=4e-7, input_check=False, **kw)
+            if tune:
+                S.autotune()
+            if name.endswith("online"):
+                S.step_graph(k)
+                ms = timed(lambda: S.step_graph(k), steps) / k
+            else:
+                S.step(k)
+                ms = timed(lambda: S.step(k), steps) / k
+            rep, _ = S.check()
+            assert rep["rows_flagged"] == 0, (name, rep)
+            res[f"{name}_gpts"] = round(npts / (ms * 1e-3) / 1e9, 3)
+            res[f"{name}_ms_per_sweep"] = round(ms, 5)
+            res[f"{name}_shape"] = S.launch_shape()
+            if name != "plain":
+                res[f"{name}_noise"] = rep["max_noise"]
+            S.close()
+    for name in ("rows_prot_kernel", "tiles_prot_kernel", "rows_online", "tiles_online"):
+        res[f"overhead_{name}_pct"] = round(
+            (res[f"{name}_ms_per_sweep"] / res["plain_ms_per_sweep"] - 1) * 100, 2)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +361,7 @@ def main():
     ap.add_argument("--period", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["plain", "prot", "offline", "online", "batch", "configs",
+                                       "tiles",
                                        "periods", "radius2", "box27"],
                     default=None,
                     help="run one measurement only (for profiler runs)")
@@ -460,6 +502,11 @@ def main():
     if args.only == "radius2":
         print(json.dumps({"only": "radius2", "radius2": bench_radius2(stream, timed, u0, C,
                                                                       tune=not args.no_tune)}))
+        return
+
+    if args.only == "tiles":
+        print(json.dumps({"only": "tiles", "tiles": bench_tiles(stream, timed, u0, C,
+                                                                tune=not args.no_tune)}))
         return
 
     if args.only == "box27":

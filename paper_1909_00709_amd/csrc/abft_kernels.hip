@@ -401,59 +401,91 @@ __device__ void fix_tiles_layer(const FixArgs& a, int i, int j, int z, const int
 }
 
 // ------------------------------------------------------------------------------------------
-// Tile-local checksums: Theorem 1 on every tile and the comparison, one thread per tile.
+// Tile-local checksums: Theorem 1 on every tile and the comparison.  A thread owns one tile
+// position (y, k) and marches along a slab of planes, keeping the tile sums of the planes
+// z-2 .. z+2 in registers, so each input tile sum is read about once; the y-neighbours come
+// through the cache.
 // ------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) tile_check_kernel(const TileCheckArgs a)
+__global__ void __launch_bounds__(256) tile_check_kernel(const TileCheckArgs a, int slab)
 {
     const int TT = a.tile_x, ntx = a.nx / TT, ny = a.ny, nz = a.nz, bc = a.st.bc;
-    const int64_t n = (int64_t)nz * ny * ntx;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nyt = (int64_t)ny * ntx;
+    const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int zs = (int)blockIdx.y * slab, ze = min(zs + slab, nz);
     const int64_t t = a.t_off + (a.t_base != nullptr ? *a.t_base : 0);
     const unsigned long long known = noise_known(a.cnt);
     double noise = 0.0;
-    if (i < n) {
-        const int k = (int)(i % ntx);
-        const int y = (int)((i / ntx) % ny), z = (int)(i / ((int64_t)ntx * ny));
+    if (col < nyt) {
+        const int k = (int)(col % ntx), y = (int)(col / ntx);
         const uint32_t m = a.st.mask;
+        const double ghost_sum = (double)TT * a.st.g;
         auto btile = [&](int z2, int y2) -> double {
             const int mz = map_coord(z2, nz, bc), my = map_coord(y2, ny, bc);
-            if (mz < 0 || my < 0) return (double)TT * a.st.g;
+            if (mz < 0 || my < 0) return ghost_sum;
             return a.Bt[((size_t)mz * ny + my) * ntx + k];
         };
-        const double b0 = a.Bt[i];
-        double bp = a.cB[i];
-        if (m & (1u << W_C)) bp += a.st.w[W_C] * b0;
-        for (int d = 1; d <= 2; ++d) {
-            if (m & (1u << w_slot(0, d, -1))) bp += a.st.w[w_slot(0, d, -1)] * b0;
-            if (m & (1u << w_slot(0, d, 1))) bp += a.st.w[w_slot(0, d, 1)] * b0;
-        }
-        bp += a.Et[i];
-        for (int d = 1; d <= 2; ++d) {
-            if (m & (1u << w_slot(1, d, -1))) bp += a.st.w[w_slot(1, d, -1)] * btile(z, y - d);
-            if (m & (1u << w_slot(1, d, 1))) bp += a.st.w[w_slot(1, d, 1)] * btile(z, y + d);
-            if (m & (1u << w_slot(2, d, -1))) bp += a.st.w[w_slot(2, d, -1)] * btile(z - d, y);
-            if (m & (1u << w_slot(2, d, 1))) bp += a.st.w[w_slot(2, d, 1)] * btile(z + d, y);
-        }
-        const double S = a.Bn[i];
-        const double dlt = fabs(S - bp);
-        if (!(dlt <= a.eps * fabs(bp))) {
-            const unsigned f = atomicAdd(&a.slot->count, 1u);
-            if (f < (unsigned)kMaxFlags) {
-                RowFlag rf;
-                rf.z = z;
-                rf.y = y;
-                rf.k = k;
-                rf.pad = 0;
-                rf.direct = S;
-                rf.pred = bp;
-                a.slot->rows[f] = rf;
-            } else {
-                atomicAdd(&a.cnt->overflow, 1ull);
+        auto has = [&](int slot) { return (m >> slot) & 1u; };
+        double win[5];  // tile sums of the planes z-2 .. z+2 at (y, k)
+        for (int q = 0; q < 5; ++q) win[q] = btile(zs - 2 + q, y);
+        // the loads of plane z+1 are issued before plane z is compared, so that they are in
+        // flight while a flag (rare) is recorded
+        struct Plane {
+            double cb, e, s, ym[2], yp[2];
+        };
+        auto load_plane = [&](int z, Plane& P) {
+            const size_t i = ((size_t)z * ny + y) * ntx + k;
+            P.cb = a.cB[i];
+            P.e = a.Et[i];
+            P.s = a.Bn[i];
+            for (int d = 1; d <= 2; ++d) {
+                P.ym[d - 1] = has(w_slot(1, d, -1)) ? btile(z, y - d) : 0.0;
+                P.yp[d - 1] = has(w_slot(1, d, 1)) ? btile(z, y + d) : 0.0;
             }
-            atomicAdd(&a.cnt->rows_flagged, 1ull);
-            emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_ROW_FLAG, z, y, k * TT, S, bp, a.grid);
-        } else if (bp != 0.0) {
-            noise = dlt / fabs(bp);
+        };
+        Plane cur, nxt;
+        load_plane(zs, cur);
+        for (int z = zs; z < ze; ++z) {
+            if (z + 1 < ze) load_plane(z + 1, nxt);
+            const double win_next = btile(z + 3, y);
+            // the order of the terms follows the whole-row prediction of the sweep
+            double bp = cur.cb;
+            if (has(W_C)) bp += a.st.w[W_C] * win[2];
+            for (int d = 1; d <= 2; ++d) {
+                if (has(w_slot(0, d, -1))) bp += a.st.w[w_slot(0, d, -1)] * win[2];
+                if (has(w_slot(0, d, 1))) bp += a.st.w[w_slot(0, d, 1)] * win[2];
+            }
+            bp += cur.e;
+            for (int d = 1; d <= 2; ++d) {
+                if (has(w_slot(1, d, -1))) bp += a.st.w[w_slot(1, d, -1)] * cur.ym[d - 1];
+                if (has(w_slot(1, d, 1))) bp += a.st.w[w_slot(1, d, 1)] * cur.yp[d - 1];
+                if (has(w_slot(2, d, -1))) bp += a.st.w[w_slot(2, d, -1)] * win[2 - d];
+                if (has(w_slot(2, d, 1))) bp += a.st.w[w_slot(2, d, 1)] * win[2 + d];
+            }
+            const double S = cur.s;
+            const double dlt = fabs(S - bp);
+            if (!(dlt <= a.eps * fabs(bp))) {
+                const unsigned f = atomicAdd(&a.slot->count, 1u);
+                if (f < (unsigned)kMaxFlags) {
+                    RowFlag rf;
+                    rf.z = z;
+                    rf.y = y;
+                    rf.k = k;
+                    rf.pad = 0;
+                    rf.direct = S;
+                    rf.pred = bp;
+                    a.slot->rows[f] = rf;
+                } else {
+                    atomicAdd(&a.cnt->overflow, 1ull);
+                }
+                atomicAdd(&a.cnt->rows_flagged, 1ull);
+                emit_event(a.cnt, a.ev, a.ev_cap, t, ABFT_EV_ROW_FLAG, z, y, k * TT, S, bp,
+                           a.grid);
+            } else if (bp != 0.0) {
+                noise = fmax(noise, dlt / fabs(bp));
+            }
+            for (int q = 0; q < 4; ++q) win[q] = win[q + 1];
+            win[4] = win_next;
+            cur = nxt;
         }
     }
     record_noise(a.cnt, noise, known);
@@ -1274,8 +1306,14 @@ hipError_t launch_fixup(int dtype, const FixArgs& a, hipStream_t st)
 hipError_t launch_tile_check(const TileCheckArgs& a, hipStream_t st)
 {
     if (a.tile_x < 1 || a.nx % a.tile_x) return hipErrorInvalidValue;
-    const int64_t n = (int64_t)a.nz * a.ny * (a.nx / a.tile_x);
-    hipLaunchKernelGGL(tile_check_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+    const int64_t nyt = (int64_t)a.ny * (a.nx / a.tile_x);
+    const int64_t bx = (nyt + 255) / 256;
+    // slabs of planes so that the launch holds about 1024 blocks
+    const int nslab = (int)std::min<int64_t>(a.nz, std::max<int64_t>(1, (1024 + bx - 1) / bx));
+    const int slab = (a.nz + nslab - 1) / nslab;
+    const int nby = (a.nz + slab - 1) / slab;
+    hipLaunchKernelGGL(tile_check_kernel, dim3((unsigned)bx, (unsigned)nby), dim3(256), 0, st, a,
+                       slab);
     return hipGetLastError();
 }
 
