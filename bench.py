@@ -74,30 +74,34 @@ def bench_batch(stream, timed, tune=True, chunk=50):
     res = {"workload": f"{len(shapes)} fp32 thermal grids, 64..256 x 64..256 x 4..32 "
                        f"({npts / 1e6:.1f} M points), online threshold {W.C4_EPS}",
            "grids": len(shapes), "points": npts}
-    for mode in ("online", "none"):
+    for name, mode, ic in (("online", "online", False), ("online_input_check", "online", True),
+                           ("none", "none", False)):
         with torch.cuda.stream(stream):
             grids = [(u.clone(), c) for u, c in dev]
-        B = abft.Batch(grids, W.THERMAL_TAPS, mode=mode, threshold=W.C4_EPS, stream=stream)
+        B = abft.Batch(grids, W.THERMAL_TAPS, mode=mode, threshold=W.C4_EPS, stream=stream,
+                       input_check=ic)
         if tune:
             B.autotune()
         B.step_graph(chunk)
         ms = timed(lambda: B.step_graph(chunk), 4) / chunk
         rep, _ = B.check()
-        assert rep["rows_flagged"] == 0, rep
-        res[f"{mode}_ms_per_sweep"] = round(ms, 5)
-        res[f"{mode}_gpts"] = round(npts / (ms * 1e-3) / 1e9, 3)
-        res[f"{mode}_shape"] = B.launch_shape()
+        assert rep["rows_flagged"] == 0 and rep["mem_flagged"] == 0, rep
+        res[f"{name}_ms_per_sweep"] = round(ms, 5)
+        res[f"{name}_gpts"] = round(npts / (ms * 1e-3) / 1e9, 3)
+        res[f"{name}_shape"] = B.launch_shape()
         B.close()
     res["algorithmic_GBs_online"] = round(12.0 * npts / (res["online_ms_per_sweep"] * 1e-3) / 1e9, 1)
     res["overhead_online_pct"] = round((res["online_ms_per_sweep"] / res["none_ms_per_sweep"] - 1)
                                        * 100, 2)
+    res["overhead_online_input_check_pct"] = round(
+        (res["online_input_check_ms_per_sweep"] / res["none_ms_per_sweep"] - 1) * 100, 2)
     # the same grids, one context each, stepped one after another (eager launches)
     ctxs = []
     for u, c in dev:
         with torch.cuda.stream(stream):
             uu = u.clone()
         ctxs.append(abft.Stencil(uu, W.THERMAL_TAPS, C=c, mode="online", threshold=W.C4_EPS,
-                                 stream=stream))
+                                 stream=stream, input_check=False))
     def sweep_all():
         for S in ctxs:
             S.step(1)

@@ -117,13 +117,14 @@ typedef struct {
                                    (offline) on the device without a host sync; 0: detection
                                    only, repair on abft_stencil_correct */
     int32_t max_events;         /* device event log capacity; 0 selects 4096 */
-    int32_t input_check;        /* online, single grids: 1 also checks each sweep's input rows
+    int32_t input_check;        /* online (single grids and batches): 1 also checks each
+                                   sweep's input rows
                                    against the checksums stored when they were written (the
                                    first case in the proof of Theorem 2, faults that arise in
                                    memory between sweeps) and, with auto_correct, repairs a
                                    changed input point and the outputs that read it; keeps an
                                    index-weighted row sum beside each checksum.  0: off.
-                                   Ignored in the other modes and for batches. */
+                                   Ignored in the other modes. */
     const char* tuning_cache;   /* autotuner cache file (read at init, written by autotune),
                                    or NULL */
     int32_t correction;         /* an abft_correction value; online contexts and batches */
@@ -184,7 +185,7 @@ enum {
  * value sweep `sweep` stores, after the update and before the store, so the stored value and
  * its checksum both see it; it fires on the given attempt (0 = first run, 1 = offline
  * recompute after a rollback).  MEMORY: into u^sweep before sweep `sweep` reads it, on the
- * first attempt only (attempt must be 0); single-grid contexts only.  In offline mode the
+ * first attempt only (attempt must be 0).  In offline mode the
  * checkpoint is the window's first input in place, so a MEMORY flip on a window's first sweep
  * also corrupts the checkpoint. */
 typedef struct {

@@ -367,7 +367,7 @@ class Batch:
 
     def __init__(self, grids, taps, *, c_scalar=0.0, bc="clamp", bc_value=0.0, mode="online",
                  threshold=1e-7, csum="f64", auto_correct=True, max_events=4096, stream=None,
-                 correction="checksum"):
+                 correction="checksum", input_check=True):
         import torch
         self.torch = torch
         self.bufs, self.Cs, problems = [], [], []
@@ -386,7 +386,7 @@ class Batch:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.max_events = max_events
         self.options = make_options(mode, 1, threshold, csum, auto_correct, max_events,
-                                    correction=correction)
+                                    correction=correction, input_check=input_check)
         s, ctx = abft_stencil_init_batch(problems, self.options, self.stream.cuda_stream)
         if s != ABFT_OK:
             raise AbftError(s, abft_last_error(None))

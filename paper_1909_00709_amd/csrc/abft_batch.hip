@@ -17,7 +17,10 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_batch_kernel(const BatchArg
     const int p = b.parity;
     if (blockIdx.x == 0) {
         // the next sweep's flag slots start from zero
-        for (int g = threadIdx.x; g < b.ngrids; g += blockDim.x) b.grids[g].slot[p ^ 1]->count = 0u;
+        for (int g = threadIdx.x; g < b.ngrids; g += blockDim.x) {
+            b.grids[g].slot[p ^ 1]->count = 0u;
+            b.grids[g].slot[p ^ 1]->mcount = 0u;
+        }
     }
     int it;
     if (b.persistent) {
@@ -49,6 +52,7 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_batch_kernel(const BatchArg
         a.t_off = b.t_off;
         a.Bt = d.B[p];
         a.Bn = d.B[p ^ 1];
+        a.Wn = d.W[p ^ 1];
         a.cB = d.cB;
         a.eps = b.eps;
         a.slot = d.slot[p];
@@ -128,11 +132,11 @@ bool batch_shape_supported(int dtype, const SweepShape& s)
     return s.vec == 1 && s.lpr == 64 && s.nch == 16;
 }
 
-size_t batch_lds_bytes(int dtype, int maxnx, int maxtz, const SweepShape& s)
+size_t batch_lds_bytes(int dtype, int maxnx, int maxtz, const SweepShape& s, bool input_check)
 {
     SweepShape t = s;
     t.tz = maxtz;
-    return sweep_lds_bytes(dtype, maxnx, t);
+    return sweep_lds_bytes(dtype, maxnx, t, input_check);
 }
 
 hipError_t launch_sweep_batch(int dtype, int mode, int csum, const SweepShape& s,
@@ -141,10 +145,15 @@ hipError_t launch_sweep_batch(int dtype, int mode, int csum, const SweepShape& s
     if (!batch_shape_supported(dtype, s) || nblocks < 1) return hipErrorInvalidValue;
     if (dtype == ABFT_F32) {
         if (mode == MODE_PLAIN) return launch_batch_t<float, MODE_PLAIN, CS_F64>(s, b, nblocks, lds, st);
+        if (mode == MODE_PROTM) {
+            if (csum == CS_F32C) return launch_batch_t<float, MODE_PROTM, CS_F32C>(s, b, nblocks, lds, st);
+            return launch_batch_t<float, MODE_PROTM, CS_F64>(s, b, nblocks, lds, st);
+        }
         if (csum == CS_F32C) return launch_batch_t<float, MODE_PROT, CS_F32C>(s, b, nblocks, lds, st);
         return launch_batch_t<float, MODE_PROT, CS_F64>(s, b, nblocks, lds, st);
     }
     if (mode == MODE_PLAIN) return launch_batch_t<double, MODE_PLAIN, CS_F64>(s, b, nblocks, lds, st);
+    if (mode == MODE_PROTM) return launch_batch_t<double, MODE_PROTM, CS_F64>(s, b, nblocks, lds, st);
     return launch_batch_t<double, MODE_PROT, CS_F64>(s, b, nblocks, lds, st);
 }
 
@@ -152,10 +161,15 @@ int batch_blocks_per_cu(int dtype, int mode, int csum, const SweepShape& s, size
 {
     if (dtype == ABFT_F32) {
         if (mode == MODE_PLAIN) return occupancy_t<float, MODE_PLAIN, CS_F64>(s, lds);
+        if (mode == MODE_PROTM) {
+            if (csum == CS_F32C) return occupancy_t<float, MODE_PROTM, CS_F32C>(s, lds);
+            return occupancy_t<float, MODE_PROTM, CS_F64>(s, lds);
+        }
         if (csum == CS_F32C) return occupancy_t<float, MODE_PROT, CS_F32C>(s, lds);
         return occupancy_t<float, MODE_PROT, CS_F64>(s, lds);
     }
     if (mode == MODE_PLAIN) return occupancy_t<double, MODE_PLAIN, CS_F64>(s, lds);
+    if (mode == MODE_PROTM) return occupancy_t<double, MODE_PROTM, CS_F64>(s, lds);
     return occupancy_t<double, MODE_PROT, CS_F64>(s, lds);
 }
 

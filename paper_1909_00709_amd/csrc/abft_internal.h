@@ -201,6 +201,7 @@ struct GridDesc {
     int32_t nx, ny, nz;
     int32_t tz, nyb, ntiles;
     double* B[2];           // B[t & 1] holds the row checksums of u^t
+    double* W[2];           // index-weighted row sums beside B (input-side check), or null
     const double* cB;
     const double* cA;
     FlagSlot* slot[2];      // flagged rows of sweeps with t & 1 == index
@@ -252,7 +253,12 @@ hipError_t launch_fixup_batch(int dtype, const BatchArgs& b, int maxnx, hipStrea
 bool batch_shape_supported(int dtype, const SweepShape& s);
 hipError_t launch_sweep_batch(int dtype, int mode, int csum, const SweepShape& s,
                               const BatchArgs& b, int nblocks, size_t lds, hipStream_t st);
-size_t batch_lds_bytes(int dtype, int maxnx, int maxtz, const SweepShape& s);
+size_t batch_lds_bytes(int dtype, int maxnx, int maxtz, const SweepShape& s, bool input_check);
+// Memory-resident faults of the plan for one batched sweep, each in its grid's input buffer.
+hipError_t launch_mem_flip_batch(int dtype, const GridDesc* grids, int parity,
+                                 const abft_fault* faults, const int32_t* fault_first,
+                                 int64_t fault_tmax, const int64_t* t_base, int64_t t_off,
+                                 hipStream_t st);
 int batch_blocks_per_cu(int dtype, int mode, int csum, const SweepShape& s, size_t lds);
 size_t fixup_lds_bytes(int nx, bool box);
 hipError_t launch_check(const CheckArgs& a, hipStream_t st);

@@ -859,7 +859,7 @@ __global__ void __launch_bounds__(kFixBlock) fixup_batch_kernel(const BatchArgs 
     const int g = blockIdx.x;
     const GridDesc& d = b.grids[g];
     const int p = b.parity;
-    if (d.slot[p]->count == 0u) return;
+    if (d.slot[p]->count == 0u && d.slot[p]->mcount == 0u) return;
     FixArgs a{};
     a.uin = d.u[p];
     a.uout = d.u[p ^ 1];
@@ -880,6 +880,10 @@ __global__ void __launch_bounds__(kFixBlock) fixup_batch_kernel(const BatchArgs 
     a.C = d.C;
     a.c_scalar = d.c_scalar;
     a.recompute = b.recompute;
+    a.Bt = d.B[p];
+    a.Wt = d.W[p];
+    a.Wn = d.W[p ^ 1];
+    a.cB = d.cB;
     fixup_body<T, 1, 0>(a, smem_raw, red, sh_K);
 }
 
@@ -1120,6 +1124,28 @@ __global__ void __launch_bounds__(64) mem_flip_kernel(T* u, int nx, int ny,
         const abft_fault F = faults[f];
         if (F.kind != ABFT_FAULT_MEMORY || F.attempt != 0 || F.grid != 0) continue;
         T* p = u + ((size_t)F.z * ny + F.y) * nx + F.x;
+        if constexpr (sizeof(T) == 4)
+            *p = __builtin_bit_cast(T, __builtin_bit_cast(uint32_t, *p) ^ (1u << F.bit));
+        else
+            *p = __builtin_bit_cast(T, __builtin_bit_cast(uint64_t, *p) ^ (1ull << F.bit));
+    }
+}
+
+// The same for a batch: each entry flips the input buffer of its own grid.
+template <typename T>
+__global__ void __launch_bounds__(64) mem_flip_batch_kernel(const GridDesc* grids, int parity,
+                                                             const abft_fault* faults,
+                                                             const int32_t* first, int64_t tmax,
+                                                             const int64_t* t_base,
+                                                             int64_t t_off)
+{
+    const int64_t t = t_off + (t_base != nullptr ? *t_base : 0);
+    if (t < 0 || t >= tmax) return;
+    for (int f = first[t] + (int)threadIdx.x; f < first[t + 1]; f += 64) {
+        const abft_fault F = faults[f];
+        if (F.kind != ABFT_FAULT_MEMORY || F.attempt != 0) continue;
+        const GridDesc& d = grids[F.grid];
+        T* p = static_cast<T*>(d.u[parity]) + ((size_t)F.z * d.ny + F.y) * d.nx + F.x;
         if constexpr (sizeof(T) == 4)
             *p = __builtin_bit_cast(T, __builtin_bit_cast(uint32_t, *p) ^ (1u << F.bit));
         else
@@ -1378,6 +1404,21 @@ hipError_t launch_mem_flip(int dtype, void* u, int nx, int ny, const abft_fault*
         hipLaunchKernelGGL(mem_flip_kernel<double>, dim3(1), dim3(64), 0, st,
                            static_cast<double*>(u), nx, ny, faults, fault_first, fault_tmax,
                            t_base, t_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_mem_flip_batch(int dtype, const GridDesc* grids, int parity,
+                                 const abft_fault* faults, const int32_t* fault_first,
+                                 int64_t fault_tmax, const int64_t* t_base, int64_t t_off,
+                                 hipStream_t st)
+{
+    if (faults == nullptr || fault_first == nullptr || fault_tmax <= 0) return hipSuccess;
+    if (dtype == ABFT_F32)
+        hipLaunchKernelGGL(mem_flip_batch_kernel<float>, dim3(1), dim3(64), 0, st, grids, parity,
+                           faults, fault_first, fault_tmax, t_base, t_off);
+    else
+        hipLaunchKernelGGL(mem_flip_batch_kernel<double>, dim3(1), dim3(64), 0, st, grids,
+                           parity, faults, fault_first, fault_tmax, t_base, t_off);
     return hipGetLastError();
 }
 

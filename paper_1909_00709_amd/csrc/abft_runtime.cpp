@@ -97,6 +97,7 @@ struct abft_ctx {
         double cs;
         Stencil st;
         double* B[2];
+        double* W[2];
         double* cB;
         double* cA;
         FlagSlot* slot[2];
@@ -733,6 +734,13 @@ abft_status validate_options(const abft_problem* p, const abft_options* o)
     return ABFT_OK;
 }
 
+// Sweep variant of a batch: plain, protected, or protected with the input-side check.
+int batch_mode(const abft_ctx* c)
+{
+    if (c->mode != ABFT_MODE_ONLINE) return MODE_PLAIN;
+    return c->input_check ? MODE_PROTM : MODE_PROT;
+}
+
 // ---- batches of grids ------------------------------------------------------------------------
 // Tile layout of every grid for a slab depth (planes per tile), the processing order (largest
 // tiles first, so that the tail of a sweep is made of small tiles), and the launch size.
@@ -768,6 +776,8 @@ abft_status batch_layout(abft_ctx* c, int tz_choice, int persistent)
         d.ntiles = G.ntiles;
         d.B[0] = G.B[0];
         d.B[1] = G.B[1];
+        d.W[0] = G.W[0];
+        d.W[1] = G.W[1];
         d.cB = G.cB;
         d.cA = G.cA;
         d.slot[0] = G.slot[0];
@@ -778,7 +788,7 @@ abft_status batch_layout(abft_ctx* c, int tz_choice, int persistent)
     std::vector<int2> order;
     order.reserve(tiles.size());
     for (auto& t : tiles) order.push_back(t.second);
-    const size_t lds = batch_lds_bytes(c->dtype, c->maxnx, maxtz, c->shape);
+    const size_t lds = batch_lds_bytes(c->dtype, c->maxnx, maxtz, c->shape, c->input_check);
     if (lds > kSweepLdsLimit) return fail(c, ABFT_E_UNSUPPORTED, "batch tiles exceed the LDS");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (c->d_order) {
@@ -797,7 +807,7 @@ abft_status batch_layout(abft_ctx* c, int tz_choice, int persistent)
     c->batch_lds = lds;
     c->batch_tz = tz_choice;
     c->persistent = persistent;
-    const int mode = c->mode == ABFT_MODE_ONLINE ? MODE_PROT : MODE_PLAIN;
+    const int mode = batch_mode(c);
     const int per_cu = batch_blocks_per_cu(c->dtype, mode, c->csum, c->shape, lds);
     c->nblocks = persistent ? std::min(c->total_tiles, per_cu * c->num_cus) : c->total_tiles;
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -830,12 +840,18 @@ BatchArgs batch_args(const abft_ctx* c, int64_t t, const int64_t* tbase, int64_t
 
 abft_status enqueue_batch(abft_ctx* c, int64_t n, const int64_t* tbase, int64_t t0)
 {
-    const int mode = c->mode == ABFT_MODE_ONLINE ? MODE_PROT : MODE_PLAIN;
+    const int mode = batch_mode(c);
     for (int64_t i = 0; i < n; ++i) {
         const int64_t t = c->t + i;
         const BatchArgs b = batch_args(c, t, tbase, t0);
-        hipError_t e = launch_sweep_batch(c->dtype, mode, c->csum, c->shape, b, c->nblocks,
-                                          c->batch_lds, c->stream);
+        hipError_t e;
+        if (c->mem_faults) {
+            e = launch_mem_flip_batch(c->dtype, c->d_grids, b.parity, c->faults, c->fault_first,
+                                      c->fault_tmax, tbase, b.t_off, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "memory fault launch");
+        }
+        e = launch_sweep_batch(c->dtype, mode, c->csum, c->shape, b, c->nblocks, c->batch_lds,
+                               c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "batched sweep launch");
         if (c->mode == ABFT_MODE_ONLINE && c->auto_correct) {
             e = launch_fixup_batch(c->dtype, b, c->maxnx, c->stream);
@@ -854,7 +870,7 @@ abft_status batch_autotune(abft_ctx* c)
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    const int mode = c->mode == ABFT_MODE_ONLINE ? MODE_PROT : MODE_PLAIN;
+    const int mode = batch_mode(c);
     int best_tz = c->batch_tz, best_p = c->persistent;
     float best_ms = 1e30f;
     abft_status s = ABFT_OK;
@@ -1152,9 +1168,9 @@ abft_status abft_stencil_check(abft_ctx* c, abft_report* out)
     int64_t pending = 0;
     if (c->batch && c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
         for (auto& G : c->grids) {
-            uint32_t n = 0;
-            HIPCHK(c, hipMemcpy(&n, &G.slot[(c->t - 1) & 1]->count, 4, hipMemcpyDeviceToHost));
-            pending += n;
+            uint32_t n[2] = {0, 0};
+            HIPCHK(c, hipMemcpy(n, &G.slot[(c->t - 1) & 1]->count, 8, hipMemcpyDeviceToHost));
+            pending += (int64_t)n[0] + n[1];
         }
     } else if (c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
         uint32_t n[2] = {0, 0};  // flagged output rows, flagged input rows
@@ -1279,8 +1295,8 @@ abft_status abft_stencil_inject(abft_ctx* c, const abft_fault* f, int32_t n)
             x.x >= nx || x.bit < 0 || x.bit >= bits || x.attempt < 0 || x.attempt > 1 ||
             (x.kind != ABFT_FAULT_STORE && x.kind != ABFT_FAULT_MEMORY))
             return fail(c, ABFT_E_INVAL, "fault outside the grid or word");
-        if (x.kind == ABFT_FAULT_MEMORY && (c->batch || x.attempt != 0))
-            return fail(c, ABFT_E_UNSUPPORTED, "memory faults: single grids, first attempt");
+        if (x.kind == ABFT_FAULT_MEMORY && x.attempt != 0)
+            return fail(c, ABFT_E_UNSUPPORTED, "memory faults fire on the first attempt");
     }
     std::stable_sort(v.begin(), v.end(),
                      [](const abft_fault& a, const abft_fault& b) { return a.sweep < b.sweep; });
@@ -1469,8 +1485,11 @@ abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft
     c->csum = o->csum == ABFT_CSUM_F32_COMP ? CS_F32C : CS_F64;
     c->auto_correct = o->auto_correct ? 1 : 0;
     c->recompute = o->correction == ABFT_CORRECT_RECOMPUTE ? 1 : 0;
+    c->input_check = (o->input_check && o->mode == ABFT_MODE_ONLINE) ? 1 : 0;
     c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    if (o->tile_x != 0)
+        return fail(nullptr, ABFT_E_UNSUPPORTED, "batches keep whole-row checksums");
     auto bail = [&](abft_status st) {
         g_init_error = c->err;
         free_all(c);
@@ -1523,6 +1542,10 @@ abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft
             (s = dalloc(c, &G.slot[0], sizeof(FlagSlot))) ||
             (s = dalloc(c, &G.slot[1], sizeof(FlagSlot))))
             return bail(s);
+        G.W[0] = G.W[1] = nullptr;
+        if (c->input_check &&
+            ((s = dalloc(c, &G.W[0], nrows * 8)) || (s = dalloc(c, &G.W[1], nrows * 8))))
+            return bail(s);
     }
     if ((s = dalloc(c, &c->cnt, sizeof(Counters))) ||
         (s = dalloc(c, &c->ev, (size_t)c->ev_cap * sizeof(abft_event))) ||
@@ -1548,6 +1571,8 @@ abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft
         INIT_CHK(launch_row_sums(c->dtype, G.C, G.cs, G.nx, nrows, G.cB, c->stream));
         INIT_CHK(launch_col_sums(c->dtype, G.C, G.cs, G.nx, G.ny, G.nz, G.cA, c->stream));
         INIT_CHK(launch_row_sums(c->dtype, G.u[0], 0.0, G.nx, nrows, G.B[0], c->stream));
+        if (G.W[0] != nullptr)
+            INIT_CHK(launch_weighted_row_sums(c->dtype, G.u[0], G.nx, nrows, G.W[0], c->stream));
     }
     INIT_CHK(hipStreamSynchronize(c->stream));
 #undef INIT_CHK

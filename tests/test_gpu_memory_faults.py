@@ -174,13 +174,6 @@ def test_memory_flip_fullsize():
 def test_memory_faults_rejected_where_unsupported():
     import torch
     from paper_1909_00709_amd import abft
-    u = torch.zeros((2, 8, 64), device="cuda")
-    B = abft.Batch([(u, None)], W.THERMAL_TAPS)
-    try:
-        with pytest.raises(abft.AbftError):
-            B.inject(W.make_plan([(0, 0, 0, 0, 3, 0, MEM)]))
-    finally:
-        B.close()
     S = abft.Stencil(torch.zeros((2, 8, 64), device="cuda"), W.THERMAL_TAPS)
     try:
         with pytest.raises(abft.AbftError):
@@ -204,3 +197,35 @@ def test_memory_flip_without_input_check():
     assert grep["mem_flagged"] == 0 and grep["checksum_faults"] == ocnt["checksum_faults"] > 0
     none = run_gpu(u0, W.THERMAL_TAPS, 6, C=C, mode="none", plan=plan)[0]
     assert np.array_equal(g, none)
+
+
+def test_memory_flips_in_a_batch():
+    """Batches: each grid's input rows checked and repaired in its own locate block; every
+    grid against its own oracle run."""
+    from tests.test_gpu_batch import _run_batch
+    shapes = W.c4_shapes(10, seed=47)
+    inputs = W.c4_inputs(shapes)
+    per_grid = {0: W.make_plan([(2, 0, 1, 2, 29, 0, MEM)]),
+                3: W.make_plan([(5, 1, 3, 3, 28, 0, MEM), (7, 2, 10, 40, 29)]),
+                9: W.make_plan([(8, 0, 0, 0, 27, 0, MEM)])}
+    rows = []
+    for g, p in per_grid.items():
+        for f in p:
+            rows.append((int(f["sweep"]), int(f["z"]), int(f["y"]), int(f["x"]), int(f["bit"]),
+                         0, int(f["kind"]), g))
+    plan = W.empty_plan(len(rows))
+    for i, r in enumerate(rows):
+        for k, name in enumerate(("sweep", "z", "y", "x", "bit", "attempt", "kind", "grid")):
+            plan[i][name] = r[k]
+    plan.sort(order="sweep", kind="stable")
+    say("memory flips in a batch")
+    clean = _run_batch(shapes, inputs, 10, None)[0]
+    outs, ev, rep, _ = _run_batch(shapes, inputs, 10, plan)
+    assert rep["mem_corrected"] == 3 and rep["corrected"] == 1
+    for g in range(len(shapes)):
+        u0, C = inputs[g]
+        o, oev, _ = run_oracle(u0, W.THERMAL_TAPS, 10, C=C, eps=1e-7, plan=per_grid.get(g))
+        assert event_keys(ev[ev["grid"] == g]) == event_keys(oev), g
+        if g in (0, 9):
+            assert np.array_equal(outs[g], clean[g]), g
+        assert_grid_close(outs[g], o, 1e-5, f"grid {g}")
