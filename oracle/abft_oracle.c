@@ -630,30 +630,61 @@ static int64_t window_coord(int bc, int64_t c, int64_t n)
  * Eq.(10)); the outputs of sweep t that read it (the window of the stencil's reach around it)
  * are evaluated again, and the row checksums of the output rows in that window recomputed.
  * Returns 1 when the point was repaired. */
-static int repair_input_row(run_state* S, int64_t sweep, void* uin, void* uout, int z, int y)
+/* Places the single changed point of row (z, y) of u, whose sum read is `sum_read` against
+ * the stored checksum B and weighted sum W, and restores it from B (the partial-sum form of
+ * Eq.(10)).  Returns its x, or -1 (reported as unplaced). */
+static int place_and_restore(run_state* S, int64_t sweep, void* u, int z, int y,
+                             double sum_read, double B, double W)
 {
     const orc_problem* p = S->p;
-    const int64_t l = (int64_t)z * p->ny + y;
     csum ws = {0.0, 0.0};
     for (int64_t q = 0; q < p->nx; q++)
-        cs_add(&ws, (double)(q + 1) * ld(p->dtype, uin, idx(p, q, y, z)));
-    const double d = S->Bi[l] - S->B[l];
-    const double ratio = (cs_val(ws) - S->W[l]) / d;
+        cs_add(&ws, (double)(q + 1) * ld(p->dtype, u, idx(p, q, y, z)));
+    const double d = sum_read - B;
+    const double ratio = (cs_val(ws) - W) / d;
     const double pos = nearbyint(ratio);
     if (!isfinite(ratio) || fabs(ratio - pos) > 0.25 || pos < 1.0 || pos > (double)p->nx) {
         S->cnt->mem_unlocated++;
         emit(S, sweep, ORC_EV_MEM_UNLOCATED, z, y, -1, d, ratio);
-        return 0;
+        return -1;
     }
     const int x = (int)pos - 1;
     const int64_t c = idx(p, x, y, z);
-    const double old = ld(p->dtype, uin, c);
+    const double old = ld(p->dtype, u, c);
     csum rest = {0.0, 0.0};
     for (int64_t q = 0; q < p->nx; q++)
-        if (q != x) cs_add(&rest, ld(p->dtype, uin, idx(p, q, y, z)));
-    st(p->dtype, uin, c, S->B[l] - cs_val(rest));
+        if (q != x) cs_add(&rest, ld(p->dtype, u, idx(p, q, y, z)));
+    st(p->dtype, u, c, B - cs_val(rest));
     S->cnt->mem_corrected++;
-    emit(S, sweep, ORC_EV_MEM_CORRECTED, z, y, x, old, ld(p->dtype, uin, c));
+    emit(S, sweep, ORC_EV_MEM_CORRECTED, z, y, x, old, ld(p->dtype, u, c));
+    return x;
+}
+
+/* Offline, before a rollback: the checkpoint's rows against the checksums stored when it was
+ * formed; a changed point is placed with the weighted sums and restored in place, so that the
+ * recompute starts from the checkpoint as it was written.  sweep = the window's first. */
+static void verify_checkpoint(run_state* S, int64_t sweep, void* ckpt, const double* Bck,
+                              const double* Wck)
+{
+    const orc_problem* p = S->p;
+    const int64_t nrows = (int64_t)p->nz * p->ny;
+    orc_row_checksums(p, ckpt, S->Bi);
+    orc_detect(nrows, S->Bi, Bck, S->eps, S->mflag);
+    for (int64_t l = 0; l < nrows; l++)
+        if (S->mflag[l]) {
+            const int z = (int)(l / p->ny), y = (int)(l % p->ny);
+            S->cnt->mem_flagged++;
+            emit(S, sweep, ORC_EV_MEM_FLAG, z, y, -1, S->Bi[l], Bck[l]);
+            place_and_restore(S, sweep, ckpt, z, y, S->Bi[l], Bck[l], Wck[l]);
+        }
+}
+
+static int repair_input_row(run_state* S, int64_t sweep, void* uin, void* uout, int z, int y)
+{
+    const orc_problem* p = S->p;
+    const int64_t l = (int64_t)z * p->ny + y;
+    const int x = place_and_restore(S, sweep, uin, z, y, S->Bi[l], S->B[l], S->W[l]);
+    if (x < 0) return 0;
     const int R = S->reach;
     for (int oz = -R; oz <= R; oz++)
         for (int oy = -R; oy <= R; oy++) {
@@ -932,7 +963,7 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
     S.C = C;
     S.eps = eps;
     S.auto_correct = auto_correct;
-    S.input_check = (flags & ORC_INPUT_CHECK) && mode == ORC_MODE_ONLINE;
+    S.input_check = (flags & ORC_INPUT_CHECK) && mode != ORC_MODE_NONE;
     S.recompute = (flags & ORC_RECOMPUTE) != 0;
     S.tile = tile_x;
     S.faults = faults;
@@ -1010,10 +1041,12 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
          * The checkpoint is a copy of the grid and of its row checksums. */
         void* ckpt = malloc(bytes);
         double* Bck = (double*)malloc(sizeof(double) * (size_t)nrows);
+        double* Wck = (double*)malloc(sizeof(double) * (size_t)nrows);  /* input check */
         double* hist = (double*)malloc(sizeof(double) * (size_t)nrows * 2 * (rx ? rx : 1) *
                                        (size_t)period);
         memcpy(ckpt, u_a, bytes);
         orc_row_checksums(p, u_a, Bck);
+        if (S.input_check) orc_weighted_row_checksums(p, u_a, Wck);
         int64_t t0 = 0;
         while (t0 < nsweeps) {
             const int64_t k = (nsweeps - t0 < period) ? nsweeps - t0 : period;
@@ -1061,6 +1094,7 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
                 }
                 counters->rollbacks++;
                 emit(&S, t0, ORC_EV_ROLLBACK, -1, -1, (int)k, 0.0, 0.0);
+                if (S.input_check) verify_checkpoint(&S, t0, ckpt, Bck, Wck);
                 memcpy(u_a, ckpt, bytes);
                 attempt = 1;
             }
@@ -1068,10 +1102,12 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
             if (halt) break;
             memcpy(ckpt, u_a, bytes);
             memcpy(Bck, S.Bn, sizeof(double) * (size_t)nrows);
+            if (S.input_check) orc_weighted_row_checksums(p, u_a, Wck);
             t0 += k;
         }
         free(ckpt);
         free(Bck);
+        free(Wck);
         free(hist);
     }
 

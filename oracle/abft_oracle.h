@@ -156,7 +156,9 @@ int64_t orc_detect(int64_t n, const double* direct, const double* pred, double e
  * negative code. */
 /* Options of orc_run (flags). */
 enum {
-    ORC_INPUT_CHECK = 1, /* online: check each sweep's input rows against the stored checksums */
+    ORC_INPUT_CHECK = 1, /* online: check each sweep's input rows against the stored checksums;
+                            offline: before a rollback, check the checkpoint's rows against
+                            its stored checksums and restore a changed point */
     ORC_RECOMPUTE = 2    /* online: correct a located point by evaluating it again from the
                             sweep's input (stencil locality) instead of Eq.(10) */
 };

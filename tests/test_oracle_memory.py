@@ -170,21 +170,31 @@ def test_memory_and_store_flips_in_one_sweep(orc):
 
 
 def test_offline_memory_flip(orc):
-    """Offline: a flip inside a window is undone by the rollback; a flip of a window's first
-    input hits the checkpoint as well, so the recompute repeats it and the window stays
-    flagged (persistent), and the run equals the unprotected run with that flip."""
+    """Offline: a flip inside a window is undone by the rollback.  A flip of a window's first
+    input hits the checkpoint as well: without the input check the recompute repeats it and the
+    window stays flagged (persistent), the run equal to the unprotected run with that flip; with
+    it, the checkpoint's rows are checked against their stored checksums before the rollback,
+    the point is restored, and the run equals the fault-free run."""
     shape = (4, 16, 32)
     u0, C = _thermal(shape)
     p = orc.Problem(shape, orc.F32, W.THERMAL_TAPS)
     clean, _, _ = p.run(u0, 12, C, mode=orc.MODE_NONE)
+    kw = dict(mode=orc.MODE_OFFLINE, period=4, eps=3e-7)
     inside = W.make_plan([(6, 1, 3, 30, 29, 0, MEM)])
-    fin, ev, cnt = p.run(u0, 12, C, mode=orc.MODE_OFFLINE, period=4, eps=3e-7, faults=inside)
-    assert cnt["rollbacks"] == 1 and cnt["persistent"] == 0 and np.array_equal(fin, clean)
+    fin, ev, cnt = p.run(u0, 12, C, faults=inside, **kw)
+    assert cnt["rollbacks"] == 1 and cnt["persistent"] == 0 and cnt["mem_flagged"] == 0
+    assert np.array_equal(fin, clean)
     first = W.make_plan([(4, 1, 3, 30, 29, 0, MEM)])
-    fin, ev, cnt = p.run(u0, 12, C, mode=orc.MODE_OFFLINE, period=4, eps=3e-7, faults=first)
+    fin, ev, cnt = p.run(u0, 12, C, faults=first, input_check=False, **kw)
     assert cnt["rollbacks"] == 1 and cnt["persistent"] == 1
     none, _, _ = p.run(u0, 12, C, mode=orc.MODE_NONE, faults=first)
     assert np.array_equal(fin, none)
+    fin, ev, cnt = p.run(u0, 12, C, faults=first, **kw)
+    assert cnt["rollbacks"] == 1 and cnt["persistent"] == 0
+    assert cnt["mem_flagged"] == 1 and cnt["mem_corrected"] == 1
+    mc = ev[ev["kind"] == orc.EV_MEM_CORRECTED][0]
+    assert (mc["sweep"], mc["z"], mc["y"], mc["x"]) == (4, 1, 3, 30)
+    assert np.array_equal(fin, clean)
 
 
 def test_bad_fault_kind_rejected(orc):
