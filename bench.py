@@ -229,7 +229,7 @@ def bench_periods(stream, timed, u0, C, tune=True, prerun=300, nsweeps=640):
         for faulty in (False, True):
             with torch.cuda.stream(stream):
                 S = abft.Stencil(start.clone(), W.THERMAL_TAPS, C=C, mode="offline", period=k,
-                                 threshold=eps, stream=stream)
+                                 threshold=eps, stream=stream, input_check=False)
                 if tune and not faulty:
                     S.autotune()
                 S.step(k)
@@ -286,7 +286,8 @@ def bench_radius2(stream, timed, u0, C, tune=True, k=10, steps=10, taps=DIFF4_TA
                             dict(threshold=2e-7, auto_correct=False, input_check=True)),
                            ("online_input_check", "online", dict(threshold=2e-7,
                                                                  input_check=True)),
-                           ("offline", "offline", dict(threshold=2e-6, period=k))):
+                           ("offline", "offline", dict(threshold=2e-6, period=k,
+                                                       input_check=False))):
         with torch.cuda.stream(stream):
             S = abft.Stencil(u0.clone(), taps, C=C, mode=mode, stream=stream, **kw)
             if tune:
@@ -477,7 +478,17 @@ def main():
     # ---- headline: offline ABFT windows ---------------------------------------------------
     offline_ms = None
     if args.only in (None, "offline"):
-        S = make("offline", period=k, threshold=W.C5.eps, csum=args.csum, auto_correct=True)
+        # the windows with the checkpoint check armed (weighted sums at each window end and a
+        # guarded check launch per window), then the headline form without it
+        S = make("offline", period=k, threshold=W.C5.eps, csum=args.csum, auto_correct=True,
+                 input_check=True)
+        S.step(k)
+        out["offline_ms_input_check"] = timed(lambda: S.step(k), args.steps)
+        rep, _ = S.check()
+        assert rep["windows_flagged"] == 0 and rep["mem_flagged"] == 0, rep
+        S.close()
+        S = make("offline", period=k, threshold=W.C5.eps, csum=args.csum, auto_correct=True,
+                 input_check=False)
         for _ in range(args.warmup):
             S.step(k)
         torch.cuda.synchronize()
@@ -534,7 +545,9 @@ def main():
                           "prot_ms_input_check": out.get("prot_ms_input_check"),
                           "online_ms_per_sweep": online_ms,
                           "online_ms_input_check": out.get("online_ms_input_check"),
-                          "offline_ms_per_window": offline_ms, "batch": batch}))
+                          "offline_ms_per_window": offline_ms,
+                          "offline_ms_input_check": out.get("offline_ms_input_check"),
+                          "batch": batch}))
         return
 
     gpts = lambda ms, sweeps=1: npts * sweeps / (ms * 1e-3) / 1e9
@@ -605,6 +618,8 @@ def main():
         "launch_shapes": {"plain": out.get("plain_shape"),
                           "prot": out.get(f"prot_shape_{args.csum}")},
         "overhead_offline_pct": round((offline_ms / (k * plain_ms) - 1) * 100, 2),
+        "overhead_offline_input_check_pct": round(
+            (out["offline_ms_input_check"] / (k * plain_ms) - 1) * 100, 2),
         "overhead_online_pct": round((online_ms / plain_ms - 1) * 100, 2),
         "overhead_prot_kernel_pct": round((prot_ms / plain_ms - 1) * 100, 2),
         "overhead_online_input_check_pct": round(

@@ -328,6 +328,12 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
                 tabW[r * a.tz + (z - z0)] = Sw;
             }
         }
+        if constexpr (MODE == MODE_CSUM) {
+            if (a.Wn != nullptr) {  // offline: the weighted sums of the checkpoint to be
+                const double Sw = weighted_row_sum<LPR, NCH, VEC>(o, (double)(sl * VEC + 1));
+                if (row_ok && sl == 0) tabW[r * a.tz + (z - z0)] = Sw;
+            }
+        }
         if (keep_e) {
             // x-boundary terms of the nine input rows around (z, y): a shift dx = -1 reads
             // G(-1) and drops u(nx-1); dx = +1 reads G(nx) and drops u(0).  Lane j < 9 of
@@ -361,6 +367,9 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
             if constexpr (MODE != MODE_PLAIN) {
                 const double S = tabS[r * a.tz + pz];
                 a.Bn[l] = S;
+                if constexpr (MODE == MODE_CSUM) {
+                    if (a.Wn != nullptr) a.Wn[l] = tabW[r * a.tz + pz];
+                }
                 if constexpr (kProt) {
                     // Theorem 1 for the box: the weight sums over dx times the nine input
                     // row sums, plus the boundary terms formed in the march

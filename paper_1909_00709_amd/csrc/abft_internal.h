@@ -254,6 +254,11 @@ bool batch_shape_supported(int dtype, const SweepShape& s);
 hipError_t launch_sweep_batch(int dtype, int mode, int csum, const SweepShape& s,
                               const BatchArgs& b, int nblocks, size_t lds, hipStream_t st);
 size_t batch_lds_bytes(int dtype, int maxnx, int maxtz, const SweepShape& s, bool input_check);
+// Offline, before a rollback recompute (guarded by the window's flag count): the checkpoint's
+// rows against their stored checksums, a changed point placed and restored in place.
+hipError_t launch_verify_ckpt(int dtype, void* u, const double* Bck, const double* Wck, int nx,
+                              int ny, int nz, double eps, const uint32_t* guard, Counters* cnt,
+                              abft_event* ev, int cap, int64_t t_first, hipStream_t st);
 // Memory-resident faults of the plan for one batched sweep, each in its grid's input buffer.
 hipError_t launch_mem_flip_batch(int dtype, const GridDesc* grids, int parity,
                                  const abft_fault* faults, const int32_t* fault_first,

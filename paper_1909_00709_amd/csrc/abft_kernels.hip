@@ -1131,6 +1131,64 @@ __global__ void __launch_bounds__(64) mem_flip_kernel(T* u, int nx, int ny,
     }
 }
 
+// Offline, before a rollback (only when the window check flagged, *guard != 0): the
+// checkpoint's rows against the checksums stored when it was formed.  A mismatched row's
+// single changed point is placed with the weighted sums kept with the checkpoint and restored
+// from the row checksum and the row's other points, so that the recompute starts from the
+// checkpoint as it was written.  One wavefront per row; a fixed grid of blocks walks the rows,
+// so that an unflagged window costs one short launch.
+template <typename T>
+__global__ void __launch_bounds__(256) verify_ckpt_kernel(T* u, const double* Bck,
+                                                           const double* Wck, int nx, int ny,
+                                                           int64_t nrows, double eps,
+                                                           const uint32_t* guard, Counters* cnt,
+                                                           abft_event* ev, int cap,
+                                                           int64_t t_first)
+{
+    if (guard != nullptr && *guard == 0u) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < nrows; row += nw) {
+        T* r = u + row * nx;
+        double ps = 0.0, pw = 0.0;
+        for (int x = lane; x < nx; x += 64) {
+            const double v = (double)r[x];
+            ps += v;
+            pw = fma((double)(x + 1), v, pw);
+        }
+        const double S = wave_sum(ps), Wr = wave_sum(pw);
+        const double B = Bck[row];
+        if (fabs(S - B) <= eps * fabs(B)) continue;  // the row is as it was written
+        const int z = (int)(row / ny), y = (int)(row % ny);
+        if (lane == 0) {
+            atomicAdd(&cnt->mem_flagged, 1ull);
+            emit_event(cnt, ev, cap, t_first, ABFT_EV_MEM_FLAG, z, y, -1, S, B, 0);
+        }
+        const double d = S - B;
+        const double ratio = (Wr - Wck[row]) / d;
+        const double pos = rint(ratio);
+        if (!isfinite(ratio) || fabs(ratio - pos) > 0.25 || pos < 1.0 || pos > (double)nx) {
+            if (lane == 0) {
+                atomicAdd(&cnt->mem_unlocated, 1ull);
+                emit_event(cnt, ev, cap, t_first, ABFT_EV_MEM_UNLOCATED, z, y, -1, d, ratio, 0);
+            }
+            continue;
+        }
+        const int xp = (int)pos - 1;
+        double pr = 0.0;
+        for (int x = lane; x < nx; x += 64)
+            if (x != xp) pr += (double)r[x];
+        const double rest = wave_sum(pr);
+        if (lane == 0) {
+            const T old = r[xp];
+            r[xp] = (T)(B - rest);
+            atomicAdd(&cnt->mem_corrected, 1ull);
+            emit_event(cnt, ev, cap, t_first, ABFT_EV_MEM_CORRECTED, z, y, xp, (double)old,
+                       (double)r[xp], 0);
+        }
+    }
+}
+
 // The same for a batch: each entry flips the input buffer of its own grid.
 template <typename T>
 __global__ void __launch_bounds__(64) mem_flip_batch_kernel(const GridDesc* grids, int parity,
@@ -1216,7 +1274,8 @@ hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, cons
                         hipStream_t st)
 {
     if (!sweep_shape_supported(dtype, s)) return hipErrorInvalidValue;
-    const size_t lds = sweep_lds_bytes(dtype, a.nx, s, mode == MODE_PROTM);
+    const size_t lds = sweep_lds_bytes(dtype, a.nx, s,
+                                       mode == MODE_PROTM || (mode == MODE_CSUM && a.Wn));
     if (mode == MODE_PLAIN) csum = CS_F64;  // no checksum in the plain variant
     if (mode == MODE_TILE) {
         if (s.box || s.vec != 16 / (dtype == ABFT_F32 ? 4 : 8) || a.Bn == nullptr ||
@@ -1272,7 +1331,7 @@ hipError_t launch_recover(int dtype, int csum, const SweepShape& s, const Recove
 {
     if (!recover_shape_supported(dtype, s) || r.k < 1 || r.k > kMaxPeriod || num_cus < 1)
         return hipErrorInvalidValue;
-    const size_t lds = sweep_lds_bytes(dtype, r.a.nx, s);
+    const size_t lds = sweep_lds_bytes(dtype, r.a.nx, s, r.a.Wn != nullptr);
     if (s.box) {
         if (dtype == ABFT_F32) return launch_recover_box_f32(csum, s, r, lds, num_cus, st);
         return launch_recover_box_f64(csum, s, r, lds, num_cus, st);
@@ -1404,6 +1463,23 @@ hipError_t launch_mem_flip(int dtype, void* u, int nx, int ny, const abft_fault*
         hipLaunchKernelGGL(mem_flip_kernel<double>, dim3(1), dim3(64), 0, st,
                            static_cast<double*>(u), nx, ny, faults, fault_first, fault_tmax,
                            t_base, t_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify_ckpt(int dtype, void* u, const double* Bck, const double* Wck, int nx,
+                              int ny, int nz, double eps, const uint32_t* guard, Counters* cnt,
+                              abft_event* ev, int cap, int64_t t_first, hipStream_t st)
+{
+    const int64_t nrows = (int64_t)ny * nz;
+    const unsigned nb = (unsigned)std::min<int64_t>((nrows + 3) / 4, 1024);
+    if (dtype == ABFT_F32)
+        hipLaunchKernelGGL(verify_ckpt_kernel<float>, dim3(nb), dim3(256), 0, st,
+                           static_cast<float*>(u), Bck, Wck, nx, ny, nrows, eps, guard, cnt, ev,
+                           cap, t_first);
+    else
+        hipLaunchKernelGGL(verify_ckpt_kernel<double>, dim3(nb), dim3(256), 0, st,
+                           static_cast<double*>(u), Bck, Wck, nx, ny, nrows, eps, guard, cnt, ev,
+                           cap, t_first);
     return hipGetLastError();
 }
 

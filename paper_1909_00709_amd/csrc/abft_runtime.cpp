@@ -531,6 +531,9 @@ abft_status offline_sweep(abft_ctx* c, int j, int k, int attempt, const uint32_t
         a.zero_n = 2;
     }
     const int mode = (j == k - 1) ? MODE_CSUM : MODE_PLAIN;
+    // with the input check, the window's last sweep also keeps the weighted sums of the
+    // checkpoint it forms
+    if (mode == MODE_CSUM && c->input_check) a.Wn = c->W[c->bck ^ 1];
     hipError_t e;
     if (c->mem_faults && attempt == 0) {
         // the window's first input is the checkpoint itself
@@ -606,12 +609,20 @@ void offline_rotate(abft_ctx* c, int k)
 // kernel's own few bytes, k guarded sweep launches do the same work.
 abft_status offline_recompute(abft_ctx* c, int k, const uint32_t* guard)
 {
+    if (c->input_check) {
+        // the checkpoint as it was written, before the window is run again from it
+        hipError_t e = launch_verify_ckpt(c->dtype, c->u[buf_of(c, 0)], c->B[c->bck],
+                                          c->W[c->bck], c->nx, c->ny, c->nz, c->eps, guard,
+                                          c->cnt, c->ev, c->ev_cap, c->win_t0, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "checkpoint check launch");
+    }
     if (c->num_cus > 0 && recover_shape_supported(c->dtype, c->shape) &&
-        sweep_lds_bytes(c->dtype, c->nx, c->shape) + 256 <= kSweepLdsLimit) {
+        sweep_lds_bytes(c->dtype, c->nx, c->shape, c->input_check) + 256 <= kSweepLdsLimit) {
         RecoverArgs r{};
         r.a = base_args(c);
         r.a.attempt = 1;
         r.a.Bn = c->B[c->bck ^ 1];
+        if (c->input_check) r.a.Wn = c->W[c->bck ^ 1];
         r.ckpt = c->u[buf_of(c, 0)];
         r.odd = c->u[buf_of(c, 1)];
         r.even = c->u[buf_of(c, 2)];
@@ -967,7 +978,7 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
     c->csum = o->csum == ABFT_CSUM_F32_COMP ? CS_F32C : CS_F64;
     c->auto_correct = o->auto_correct ? 1 : 0;
     c->recompute = o->correction == ABFT_CORRECT_RECOMPUTE ? 1 : 0;
-    c->input_check = (o->input_check && o->mode == ABFT_MODE_ONLINE) ? 1 : 0;
+    c->input_check = (o->input_check && o->mode != ABFT_MODE_NONE) ? 1 : 0;
     c->tile_x = o->tile_x;
     c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
     if (o->tuning_cache) c->cache_path = o->tuning_cache;

@@ -521,8 +521,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                 }
             }
         }
-        if constexpr (kMemChk) {
+        if (kMemChk || (MODE == MODE_CSUM && a.Wn != nullptr)) {
             // the index-weighted sum of the output row, which places a changed point later
+            // (with the input-side check; offline, for the checkpoint the window ends on)
             const double Sw = weighted_row_sum<LPR, NCH, VEC>(o, (double)(sl * VEC + 1));
             if (row_ok && sl == 0) tabW[r * a.tz + (z - z0)] = Sw;
         }
@@ -586,6 +587,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             if constexpr (kRowSum) {
                 const double S = tabS[r * a.tz + pz];
                 a.Bn[l] = S;
+                if constexpr (MODE == MODE_CSUM) {
+                    if (a.Wn != nullptr) a.Wn[l] = tabW[r * a.tz + pz];
+                }
                 if constexpr (kProt) {
                     // Theorem 1 (Eq.(5)) on the checksum plane: the x shifts become the
                     // boundary term e of the input row, the y and z shifts read the

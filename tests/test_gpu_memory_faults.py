@@ -151,8 +151,8 @@ def test_offline_memory_flips():
     o, oev, _ = run_oracle(u0, W.THERMAL_TAPS, 12, plan=inside, **kw)
     assert event_keys(gev) == event_keys(oev) and grep["rollbacks"] == 1
     assert np.array_equal(g, clean)
-    g, gev, grep, _ = run_gpu(u0, W.THERMAL_TAPS, 12, plan=first, **kw)
-    o, oev, _ = run_oracle(u0, W.THERMAL_TAPS, 12, plan=first, **kw)
+    g, gev, grep, _ = run_gpu(u0, W.THERMAL_TAPS, 12, plan=first, input_check=False, **kw)
+    o, oev, _ = run_oracle(u0, W.THERMAL_TAPS, 12, plan=first, input_check=False, **kw)
     assert event_keys(gev) == event_keys(oev) and grep["persistent"] == 1
     none = run_gpu(u0, W.THERMAL_TAPS, 12, C=C, mode="none", plan=first)[0]
     assert np.array_equal(g, none)
@@ -229,3 +229,27 @@ def test_memory_flips_in_a_batch():
         if g in (0, 9):
             assert np.array_equal(outs[g], clean[g]), g
         assert_grid_close(outs[g], o, 1e-5, f"grid {g}")
+
+
+@pytest.mark.parametrize("taps", [None, STAR2, BOX], ids=["thermal", "star2", "box"])
+def test_offline_checkpoint_check(taps):
+    """Offline with the input check: a flip of a window's first input (the checkpoint itself)
+    is found before the rollback, restored, and the recompute gives the fault-free run."""
+    shape = (6, 24, 64)
+    if taps is None:
+        u0, C = _thermal(shape)
+        taps, eps = W.THERMAL_TAPS, 3e-7
+    else:
+        rng = np.random.default_rng(53)
+        u0 = (20 + 5 * rng.random(shape)).astype(np.float32)
+        C = rng.random(shape).astype(np.float32)
+        eps = 1e-6
+    first = W.make_plan([(4, 1, 3, 30, 29, 0, MEM), (8, 5, 23, 63, 28, 0, MEM)])
+    kw = dict(C=C, mode="offline", period=4, eps=eps)
+    say("offline checkpoint check", len(taps), "taps")
+    clean = run_gpu(u0, taps, 12, C=C, mode="none")[0]
+    g, gev, grep, _ = run_gpu(u0, taps, 12, plan=first, **kw)
+    o, oev, ocnt = run_oracle(u0, taps, 12, plan=first, **kw)
+    assert event_keys(gev) == event_keys(oev)
+    assert grep["rollbacks"] == 2 and grep["persistent"] == 0 and grep["mem_corrected"] == 2
+    assert np.array_equal(g, clean)
