@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cctype>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -286,7 +287,30 @@ std::string cache_key(const abft_ctx* c)
       << c->csum;
     if (c->st.rad != 1) o << " r" << c->st.rad;
     if (c->st.box) o << " box";
+    if (c->input_check) o << " ic";
+    if (c->tile_x) o << " t" << c->tile_x;
     return o.str();
+}
+
+// A tuning-cache line: six numbers and the variant's tags (words) form its key, the shape
+// follows.  Returns the key and the index of the first shape token.
+std::string cache_line_key(const std::vector<std::string>& tok, size_t* first)
+{
+    size_t i = 0;
+    std::string k;
+    for (; i < tok.size() && i < 6; ++i) k += (i ? " " : "") + tok[i];
+    for (; i < tok.size() && !tok[i].empty() && std::isalpha((unsigned char)tok[i][0]); ++i)
+        k += " " + tok[i];
+    *first = i;
+    return k;
+}
+
+std::vector<std::string> split_words(const std::string& line)
+{
+    std::istringstream in(line);
+    std::vector<std::string> tok;
+    for (std::string w; in >> w;) tok.push_back(w);
+    return tok;
 }
 
 bool cache_lookup(const abft_ctx* c, SweepShape* s)
@@ -298,18 +322,22 @@ bool cache_lookup(const abft_ctx* c, SweepShape* s)
     std::string line;
     bool found = false;
     while (std::getline(f, line)) {
-        std::istringstream in(line);
-        int d, nx, ny, nz, m, cs;
+        const std::vector<std::string> tok = split_words(line);
+        size_t i = 0;
+        if (cache_line_key(tok, &i) != key || tok.size() < i + 4) continue;
         SweepShape r{};
-        if (!(in >> d >> nx >> ny >> nz >> m >> cs >> r.lpr >> r.nch >> r.vec >> r.tz)) continue;
-        if (!(in >> r.pf)) r.pf = 1;
-        if (!(in >> r.nw)) r.nw = 4;
-        std::ostringstream k;
-        k << d << ' ' << nx << ' ' << ny << ' ' << nz << ' ' << m << ' ' << cs;
-        if (k.str() == key) {
-            *s = r;
-            found = true;
+        try {
+            r.lpr = std::stoi(tok[i]);
+            r.nch = std::stoi(tok[i + 1]);
+            r.vec = std::stoi(tok[i + 2]);
+            r.tz = std::stoi(tok[i + 3]);
+            r.pf = tok.size() > i + 4 ? std::stoi(tok[i + 4]) : 1;
+            r.nw = tok.size() > i + 5 ? std::stoi(tok[i + 5]) : 4;
+        } catch (...) {
+            continue;
         }
+        *s = r;
+        found = true;
     }
     return found;
 }
@@ -322,9 +350,11 @@ void cache_store(const abft_ctx* c)
         std::ifstream f(c->cache_path);
         std::string line;
         const std::string key = cache_key(c);
-        while (f && std::getline(f, line))
-            if (line.compare(0, key.size() + 1, key + " ") != 0 && !line.empty())
+        while (f && std::getline(f, line)) {
+            size_t i = 0;
+            if (!line.empty() && cache_line_key(split_words(line), &i) != key)
                 keep.push_back(line);
+        }
     }
     std::ofstream f(c->cache_path, std::ios::trunc);
     for (auto& l : keep) f << l << '\n';
