@@ -1429,8 +1429,10 @@ abft_status abft_stencil_autotune(abft_ctx* c)
     float best_ms = 1e30f;
     const int mode = c->mode != ABFT_MODE_ONLINE ? MODE_PLAIN
                      : (c->tile_x ? MODE_TILE : (c->input_check ? MODE_PROTM : MODE_PROT));
-    for (const SweepShape& sh : cands) {
-        if (apply_shape(c, sh)) continue;
+    // one candidate: `groups` timed groups of `reps` launches, the best group's mean; a
+    // negative value when the shape does not launch
+    auto time_shape = [&](const SweepShape& sh, int groups, int reps) -> float {
+        if (apply_shape(c, sh)) return -1.f;
         SweepArgs a = base_args(c);
         a.uin = c->u[c->cur];
         a.uout = c->u[c->cur ^ (c->mode == ABFT_MODE_OFFLINE ? 0 : 1)];
@@ -1445,31 +1447,47 @@ abft_status abft_stencil_autotune(abft_ctx* c)
         if (mode == MODE_PROTM) a.Wn = sW;
         if (mode == MODE_TILE) a.Et = sW;  // the sweep's tile boundary terms (scratch)
         a.t_off = c->t;
-        bool ok = true;
-        for (int w = 0; w < 2 && ok; ++w)
-            ok = launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream) == hipSuccess;
-        if (!ok) {
-            (void)hipGetLastError();
-            continue;
-        }
-        // best of three timed groups of five launches
+        for (int w = 0; w < 2; ++w)
+            if (launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream) != hipSuccess) {
+                (void)hipGetLastError();
+                return -1.f;
+            }
         float ms = 1e30f;
-        for (int g = 0; g < 3; ++g) {
-            const int reps = 5;
-            HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int g = 0; g < groups; ++g) {
+            if (hipEventRecord(e0, c->stream) != hipSuccess) return -1.f;
             for (int r = 0; r < reps; ++r)
                 (void)launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream);
-            HIPCHK(c, hipEventRecord(e1, c->stream));
-            HIPCHK(c, hipEventSynchronize(e1));
             float gms = 0.f;
-            HIPCHK(c, hipEventElapsedTime(&gms, e0, e1));
+            if (hipEventRecord(e1, c->stream) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&gms, e0, e1) != hipSuccess)
+                return -1.f;
             ms = std::min(ms, gms / reps);
         }
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = sh;
-        }
+        return ms;
+    };
+    // every candidate briefly (best of three groups of five launches), then the three fastest
+    // again in alternation (five rounds of ten launches each), so that a shape is not chosen
+    // on one lucky group
+    std::vector<std::pair<float, SweepShape>> timed;
+    for (const SweepShape& sh : cands) {
+        const float ms = time_shape(sh, 3, 5);
+        if (ms > 0.f) timed.push_back({ms, sh});
     }
+    std::stable_sort(timed.begin(), timed.end(),
+                     [](const auto& x, const auto& y) { return x.first < y.first; });
+    if (timed.size() > 3) timed.resize(3);
+    std::vector<float> fine(timed.size(), 1e30f);
+    for (int round = 0; round < 5; ++round)
+        for (size_t q = 0; q < timed.size(); ++q) {
+            const float ms = time_shape(timed[q].second, 1, 10);
+            if (ms > 0.f) fine[q] = std::min(fine[q], ms);
+        }
+    for (size_t q = 0; q < timed.size(); ++q)
+        if (fine[q] < best_ms) {
+            best_ms = fine[q];
+            best = timed[q].second;
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     for (void* p : {static_cast<void*>(sslot), static_cast<void*>(scnt), static_cast<void*>(sB),
