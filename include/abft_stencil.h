@@ -96,8 +96,9 @@ typedef struct {
                                    (the centre and points at distance 1 or 2 along one axis;
                                    an axis carrying a distance-2 tap must be at least 2 long)
                                    or in the 3 x 3 x 3 box (every offset in -1..1 per axis,
-                                   diagonal taps included).  Batches
-                                   (abft_stencil_init_batch) take radius-1 stars only. */
+                                   diagonal taps included).  All grids of a batch
+                                   (abft_stencil_init_batch) share the form: radius-1 star,
+                                   radius-2 star or box. */
     double bc_value;            /* ghost value for ABFT_BC_CONSTANT, rounded to dtype */
     const void* cterm;          /* device [nz][ny][nx] constant term C of Eq.(1), or NULL */
     double cterm_scalar;        /* constant term used when cterm is NULL, rounded to dtype */

@@ -248,12 +248,20 @@ int sweep_rows_per_block(const SweepShape& s);
 hipError_t launch_sweep(int dtype, int mode, int csum, const SweepShape& s, const SweepArgs& a,
                         hipStream_t st);
 hipError_t launch_fixup(int dtype, const FixArgs& a, hipStream_t st);
-hipError_t launch_fixup_batch(int dtype, const BatchArgs& b, int maxnx, hipStream_t st);
+hipError_t launch_fixup_batch(int dtype, const BatchArgs& b, int maxnx, int rad, int box,
+                              hipStream_t st);
 // Batched sweep (abft_batch.hip): one launch sweeps every grid of the batch.
 bool batch_shape_supported(int dtype, const SweepShape& s);
 hipError_t launch_sweep_batch(int dtype, int mode, int csum, const SweepShape& s,
                               const BatchArgs& b, int nblocks, size_t lds, hipStream_t st);
 size_t batch_lds_bytes(int dtype, int maxnx, int maxtz, const SweepShape& s, bool input_check);
+// Batched sweeps of radius-2 stars and 27-point boxes (their own translation units).
+hipError_t launch_batch_r2(int dtype, int mode, int csum, const SweepShape& s, const BatchArgs& b,
+                           int nblocks, size_t lds, hipStream_t st);
+hipError_t launch_batch_box(int dtype, int mode, int csum, const SweepShape& s,
+                            const BatchArgs& b, int nblocks, size_t lds, hipStream_t st);
+int batch_occupancy_r2(int dtype, int mode, int csum, const SweepShape& s, size_t lds);
+int batch_occupancy_box(int dtype, int mode, int csum, const SweepShape& s, size_t lds);
 // Offline, before a rollback recompute (guarded by the window's flag count): the checkpoint's
 // rows against their stored checksums, a changed point placed and restored in place.
 hipError_t launch_verify_ckpt(int dtype, void* u, const double* Bck, const double* Wck, int nx,

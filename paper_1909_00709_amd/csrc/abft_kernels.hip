@@ -850,7 +850,7 @@ __global__ void __launch_bounds__(kFixBlock) fixup_kernel(const FixArgs a)
 }
 
 // One block per grid of a batch; each exits at once unless its grid flagged a row.
-template <typename T>
+template <typename T, int RAD, int BOX>
 __global__ void __launch_bounds__(kFixBlock) fixup_batch_kernel(const BatchArgs b)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -884,7 +884,7 @@ __global__ void __launch_bounds__(kFixBlock) fixup_batch_kernel(const BatchArgs 
     a.Wt = d.W[p];
     a.Wn = d.W[p ^ 1];
     a.cB = d.cB;
-    fixup_body<T, 1, 0>(a, smem_raw, red, sh_K);
+    fixup_body<T, RAD, BOX>(a, smem_raw, red, sh_K);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1351,16 +1351,28 @@ size_t fixup_lds_bytes(int nx, bool box)
                     (size_t)kMaxFlags * sizeof(int));
 }
 
-hipError_t launch_fixup_batch(int dtype, const BatchArgs& b, int maxnx, hipStream_t st)
+hipError_t launch_fixup_batch(int dtype, const BatchArgs& b, int maxnx, int rad, int box,
+                              hipStream_t st)
 {
-    const size_t lds = fixup_lds_bytes(maxnx, false);
-    if (dtype == ABFT_F32)
-        hipLaunchKernelGGL(fixup_batch_kernel<float>, dim3(b.ngrids), dim3(kFixBlock), lds, st,
-                           b);
-    else
-        hipLaunchKernelGGL(fixup_batch_kernel<double>, dim3(b.ngrids), dim3(kFixBlock), lds, st,
-                           b);
-    return hipGetLastError();
+    const size_t lds = fixup_lds_bytes(maxnx, box != 0);
+    auto go = [&](auto kern) -> hipError_t {
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(kern, dim3(b.ngrids), dim3(kFixBlock), lds, st, b);
+        return hipGetLastError();
+    };
+    if (dtype == ABFT_F32) {
+        if (box) return go(fixup_batch_kernel<float, 1, 1>);
+        if (rad == 2) return go(fixup_batch_kernel<float, 2, 0>);
+        return go(fixup_batch_kernel<float, 1, 0>);
+    }
+    if (box) return go(fixup_batch_kernel<double, 1, 1>);
+    if (rad == 2) return go(fixup_batch_kernel<double, 2, 0>);
+    return go(fixup_batch_kernel<double, 1, 0>);
 }
 
 hipError_t launch_fixup(int dtype, const FixArgs& a, hipStream_t st)

@@ -895,7 +895,7 @@ abft_status enqueue_batch(abft_ctx* c, int64_t n, const int64_t* tbase, int64_t 
                                c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "batched sweep launch");
         if (c->mode == ABFT_MODE_ONLINE && c->auto_correct) {
-            e = launch_fixup_batch(c->dtype, b, c->maxnx, c->stream);
+            e = launch_fixup_batch(c->dtype, b, c->maxnx, c->shape.rad, c->shape.box, c->stream);
             if (e != hipSuccess) return hip_fail(c, e, "batched locate/correct launch");
         }
     }
@@ -1264,7 +1264,7 @@ abft_status abft_stencil_correct(abft_ctx* c, abft_report* inout)
     if (s) return s;
     if (c->batch && c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
         const BatchArgs b = batch_args(c, c->t - 1, nullptr, 0);
-        hipError_t e = launch_fixup_batch(c->dtype, b, c->maxnx, c->stream);
+        hipError_t e = launch_fixup_batch(c->dtype, b, c->maxnx, c->shape.rad, c->shape.box, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "batched locate/correct launch");
     } else if (c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
         const int64_t t = c->t - 1;
@@ -1576,17 +1576,27 @@ abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft
     else if (c->maxnx <= 64 * 16) sh = SweepShape{64, 16, 1, 1, 1};
     else return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the batched kernel"));
     c->shape = sh;
-    if (fixup_lds_bytes(c->maxnx, false) > kLdsLimit || c->maxnx > 4 * kFixBlock)
-        return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
-
     c->grids.resize(n);
     for (int i = 0; i < n; ++i) {
         auto& G = c->grids[i];
         // per-grid stencil: reuse the single-grid tap mapping on a scratch context
         abft_ctx tmp;
         if ((s = map_taps(&tmp, &p[i]))) return bail(fail(c, s, tmp.err));
-        if (tmp.st.rad != 1 || tmp.st.box)
-            return bail(fail(c, ABFT_E_UNSUPPORTED, "batched grids take radius-1 stars"));
+        // one kernel form per batch: every grid has the first grid's radius and form
+        if (i == 0) {
+            c->shape.rad = tmp.st.rad;
+            c->shape.box = tmp.st.box;
+        } else if (tmp.st.rad != c->shape.rad || tmp.st.box != c->shape.box) {
+            return bail(fail(c, ABFT_E_UNSUPPORTED, "batched grids share the stencil form"));
+        }
+        if (tmp.st.rad == 2)
+            for (int ax = 0; ax < 3; ++ax) {
+                const int len = ax == 0 ? p[i].nx : ax == 1 ? p[i].ny : p[i].nz;
+                const uint32_t m2 = (1u << w_slot(ax, 2, -1)) | (1u << w_slot(ax, 2, 1));
+                if ((tmp.st.mask & m2) && len < 2)
+                    return bail(fail(c, ABFT_E_UNSUPPORTED, "distance-2 taps along an axis of "
+                                                            "length 1"));
+            }
         G.st = tmp.st;
         G.nx = p[i].nx;
         G.ny = p[i].ny;
@@ -1602,6 +1612,10 @@ abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft
             (s = dalloc(c, &G.slot[1], sizeof(FlagSlot))))
             return bail(s);
         G.W[0] = G.W[1] = nullptr;
+        if (i == n - 1 &&
+            (fixup_lds_bytes(c->maxnx, c->shape.box) > (c->shape.box ? kSweepLdsLimit : kLdsLimit) ||
+             c->maxnx > 4 * kFixBlock))
+            return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
         if (c->input_check &&
             ((s = dalloc(c, &G.W[0], nrows * 8)) || (s = dalloc(c, &G.W[1], nrows * 8))))
             return bail(s);

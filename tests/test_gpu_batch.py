@@ -10,13 +10,14 @@ pytestmark = pytest.mark.gpu
 
 
 def _run_batch(shapes, inputs, nsweeps, plan, *, eps=1e-7, graph=False, persistent=None,
-               autotune=False, chunks=None, csum="f64", correction="checksum"):
+               autotune=False, chunks=None, csum="f64", correction="checksum",
+               taps=W.THERMAL_TAPS):
     import torch
     from paper_1909_00709_amd import abft
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         grids = [(torch.from_numpy(u).cuda(), torch.from_numpy(c).cuda()) for u, c in inputs]
-        B = abft.Batch(grids, W.THERMAL_TAPS, threshold=eps, csum=csum, stream=stream,
+        B = abft.Batch(grids, taps, threshold=eps, csum=csum, stream=stream,
                        max_events=1 << 14, correction=correction)
         try:
             if autotune:
@@ -56,6 +57,38 @@ def _check_grids(shapes, inputs, outs, ev, nsweeps, per_grid, eps, which):
         gev = ev[ev["grid"] == g]
         assert event_keys(gev) == event_keys(oev), g
         assert_grid_close(outs[g], o, 1e-5, f"grid {g} {shapes[g]}")
+
+
+@pytest.mark.parametrize("form", ["star2", "box"])
+def test_batch_radius2_and_box(form):
+    """Batches of radius-2 stars and of 27-point boxes: every grid against its own oracle run,
+    with flips of the stored values and of the inputs in memory."""
+    from tests.test_gpu_memory_faults import BOX, STAR2
+    taps = {"star2": STAR2, "box": BOX}[form]
+    shapes = W.c4_shapes(10, seed=48)
+    inputs = W.c4_inputs(shapes)
+    per_grid = {1: W.make_plan([(3, 0, 1, 2, 29)]),
+                4: W.make_plan([(5, 1, 3, 3, 28, 0, W.FAULT_MEMORY)]),
+                7: W.make_plan([(8, 2, 10, 40, 30)])}
+    rows = []
+    for g, p in per_grid.items():
+        for f in p:
+            rows.append((int(f["sweep"]), int(f["z"]), int(f["y"]), int(f["x"]), int(f["bit"]),
+                         0, int(f["kind"]), g))
+    plan = W.empty_plan(len(rows))
+    for i, r in enumerate(rows):
+        for k, name in enumerate(("sweep", "z", "y", "x", "bit", "attempt", "kind", "grid")):
+            plan[i][name] = r[k]
+    plan.sort(order="sweep", kind="stable")
+    say("batch", form)
+    outs, ev, rep, _ = _run_batch(shapes, inputs, 10, plan, eps=3e-7, taps=taps,
+                                  autotune=True)
+    assert rep["corrected"] == 2 and rep["mem_corrected"] == 1 and rep["uncorrectable"] == 0
+    for g in range(len(shapes)):
+        u0, C = inputs[g]
+        o, oev, _ = run_oracle(u0, taps, 10, C=C, eps=3e-7, plan=per_grid.get(g))
+        assert event_keys(ev[ev["grid"] == g]) == event_keys(oev), g
+        assert_grid_close(outs[g], o, 1e-5, f"{form} grid {g}")
 
 
 def test_batch_small_mixed():
