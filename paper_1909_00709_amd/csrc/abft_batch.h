@@ -6,15 +6,28 @@
 // hardware dispatcher does the balancing.  Every tile runs the same fused sweep/checksum code
 // as a single grid (sweep_tile, or sweep_box_tile for box stencils), with that grid's
 // descriptor; all grids of a batch share the stencil form (radius and box), each has its own
-// weights.
+// weights.  Blocks of 4 wavefronts loading one plane ahead (8 wavefronts or two planes ahead
+// were slower on batches of small grids).
 #pragma once
 
 #include "abft_box.h"
 
 namespace abft {
 
+// A value that no lane writes during the launch, read through the constant address space: with
+// a uniform address the load is scalar and the value lives in scalar registers.
+template <typename S>
+__device__ __forceinline__ S load_const(const S* src)
+{
+    return *(const __attribute__((address_space(4))) S*)src;
+}
+
+// The plain radius-1 variant fits three wavefronts per SIMD with no spill when asked to (168
+// registers instead of 172); the checksum variants would spill, and run slower, at that limit.
 template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int RAD, int BOX>
-__global__ void __launch_bounds__(kSweepBlock) sweep_batch_kernel(const BatchArgs b)
+__global__ void __launch_bounds__(kBatchWaves * 64)
+    __attribute__((amdgpu_waves_per_eu(MODE == MODE_PLAIN && RAD == 1 && !BOX && VEC > 1 ? 3 : 1)))
+    sweep_batch_kernel(const BatchArgs b)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ int sh_next;
@@ -30,50 +43,65 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_batch_kernel(const BatchArg
     if (b.persistent) {
         if (threadIdx.x == 0) sh_next = (int)atomicAdd(&b.queue[0], 1u);
         __syncthreads();
-        it = sh_next;
+        // the index is the same in every lane: keeping it (and so the tile's descriptor) in
+        // scalar registers leaves the vector registers to the sweep
+        it = __builtin_amdgcn_readfirstlane(sh_next);
     } else {
         it = blockIdx.x;
     }
     while (it < b.ntiles) {
         __syncthreads();  // everyone has read sh_next; the previous tile's LDS use is over
         if (b.persistent && threadIdx.x == 0) sh_next = (int)atomicAdd(&b.queue[0], 1u);
-        const int2 gt = b.order[it];
-        const GridDesc& d = b.grids[gt.x];
+        // the tile list and the descriptors do not change during the launch, and the index is
+        // uniform: the descriptor's pointers, sizes and weights come in by scalar loads
+        const int gx = load_const(&b.order[it].x), gy = load_const(&b.order[it].y);
+        const GridDesc* d = b.grids + gx;
         SweepArgs a{};
-        a.uin = d.u[p];
-        a.uout = d.u[p ^ 1];
-        a.C = d.C;
-        a.c_scalar = d.c_scalar;
-        a.st = d.st;
-        a.nx = d.nx;
-        a.ny = d.ny;
-        a.nz = d.nz;
-        a.tz = d.tz;
-        a.nyb = d.nyb;
-        a.ntiles = d.ntiles;
+        a.uin = load_const(&d->u[p]);
+        a.uout = load_const(&d->u[p ^ 1]);
+        a.C = load_const(&d->C);
+        a.c_scalar = load_const(&d->c_scalar);
+#pragma unroll
+        for (int k = 0; k < W_COUNT; ++k) a.st.w[k] = load_const(&d->st.w[k]);
+        a.st.mask = load_const(&d->st.mask);
+        a.st.bc = load_const(&d->st.bc);
+        a.st.g = load_const(&d->st.g);
+        a.st.rad = RAD;
+        a.st.box = BOX;
+        if constexpr (BOX) {
+#pragma unroll
+            for (int k = 0; k < 27; ++k) a.st.wb[k] = load_const(&d->st.wb[k]);
+            a.st.bmask = load_const(&d->st.bmask);
+        }
+        a.nx = load_const(&d->nx);
+        a.ny = load_const(&d->ny);
+        a.nz = load_const(&d->nz);
+        a.tz = load_const(&d->tz);
+        a.nyb = load_const(&d->nyb);
+        a.ntiles = load_const(&d->ntiles);
         a.attempt = b.attempt;
         a.t_base = b.t_base;
         a.t_off = b.t_off;
-        a.Bt = d.B[p];
-        a.Bn = d.B[p ^ 1];
-        a.Wn = d.W[p ^ 1];
-        a.cB = d.cB;
+        a.Bt = load_const(&d->B[p]);
+        a.Bn = load_const(&d->B[p ^ 1]);
+        a.Wn = load_const(&d->W[p ^ 1]);
+        a.cB = load_const(&d->cB);
         a.eps = b.eps;
-        a.slot = d.slot[p];
+        a.slot = load_const(&d->slot[p]);
         a.cnt = b.cnt;
         a.ev = b.ev;
         a.ev_cap = b.ev_cap;
-        a.grid = gt.x;
+        a.grid = gx;
         a.faults = b.faults;
         a.fault_first = b.fault_first;
         a.fault_tmax = b.fault_tmax;
         if constexpr (BOX)
-            sweep_box_tile<T, MODE, CS, LPR, NCH, VEC, kSweepBlock / 64>(a, gt.y, smem_raw);
+            sweep_box_tile<T, MODE, CS, LPR, NCH, VEC, kBatchWaves>(a, gy, smem_raw);
         else
-            sweep_tile<T, MODE, CS, LPR, NCH, VEC, 1, kSweepBlock / 64, RAD>(a, gt.y, smem_raw);
+            sweep_tile<T, MODE, CS, LPR, NCH, VEC, 1, kBatchWaves, RAD>(a, gy, smem_raw);
         if (!b.persistent) break;
         __syncthreads();
-        it = sh_next;
+        it = __builtin_amdgcn_readfirstlane(sh_next);
     }
     if (b.persistent && threadIdx.x == 0) {
         // every block has drawn past the end of the list before it leaves, so the last one to
@@ -84,6 +112,14 @@ __global__ void __launch_bounds__(kSweepBlock) sweep_batch_kernel(const BatchArg
         }
     }
 }
+
+// Instantiated shapes: 16 or 64 lanes per row with 16-byte accesses, or 64 lanes of single
+// elements for rows that are not 16-byte multiples.
+#define ABFT_BATCH_SHAPES(X)                                                                   \
+    constexpr int VF = 16 / (int)sizeof(T);                                                    \
+    X(16, 4, VF)                                                                               \
+    X(64, 4, VF)                                                                               \
+    X(64, 16, 1)
 
 template <typename T, int MODE, int CS, int RAD, int BOX>
 hipError_t launch_batch_t(const SweepShape& s, const BatchArgs& b, int nblocks, size_t lds,
@@ -100,13 +136,10 @@ hipError_t launch_batch_t(const SweepShape& s, const BatchArgs& b, int nblocks, 
             if (e != hipSuccess) return e;                                                     \
             lds_set = (int)lds;                                                                \
         }                                                                                      \
-        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kSweepBlock), lds, st, b);                \
+        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kBatchWaves * 64), lds, st, b);           \
         return hipGetLastError();                                                              \
     }
-    constexpr int VF = 16 / (int)sizeof(T);
-    ABFT_BATCH_CASE(16, 4, VF)
-    ABFT_BATCH_CASE(64, 4, VF)
-    ABFT_BATCH_CASE(64, 16, 1)
+    ABFT_BATCH_SHAPES(ABFT_BATCH_CASE)
 #undef ABFT_BATCH_CASE
     return hipErrorInvalidValue;
 }
@@ -118,18 +151,16 @@ int occupancy_t(const SweepShape& s, size_t lds)
 #define ABFT_OCC_CASE(LPR_, NCH_, VEC_)                                                        \
     if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_) {                                     \
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                      \
-                &n, sweep_batch_kernel<T, MODE, CS, LPR_, NCH_, VEC_, RAD, BOX>, kSweepBlock,   \
-                lds) != hipSuccess)                                                            \
+                &n, sweep_batch_kernel<T, MODE, CS, LPR_, NCH_, VEC_, RAD, BOX>,               \
+                kBatchWaves * 64, lds) != hipSuccess)                                          \
             n = 1;                                                                             \
         return n > 0 ? n : 1;                                                                  \
     }
-    constexpr int VF = 16 / (int)sizeof(T);
-    ABFT_OCC_CASE(16, 4, VF)
-    ABFT_OCC_CASE(64, 4, VF)
-    ABFT_OCC_CASE(64, 16, 1)
+    ABFT_BATCH_SHAPES(ABFT_OCC_CASE)
 #undef ABFT_OCC_CASE
     return 1;
 }
+#undef ABFT_BATCH_SHAPES
 
 // Launch and occupancy for one stencil form (radius 1 or 2 star, box), every mode, checksum
 // accumulation and dtype; instantiated once per form in its own translation unit.

@@ -12,7 +12,7 @@ namespace abft {
 bool batch_shape_supported(int dtype, const SweepShape& s)
 {
     const int vf = dtype == ABFT_F32 ? 4 : 2;
-    if (s.nw != kSweepBlock / 64) return false;
+    if (s.nw != kBatchWaves || s.pf != 1) return false;
     if (s.vec == vf) return (s.lpr == 16 || s.lpr == 64) && s.nch == 4;
     return s.vec == 1 && s.lpr == 64 && s.nch == 16;
 }

@@ -12,7 +12,7 @@ namespace abft {
 constexpr int kMaxFlags = 1024;   // flagged rows remembered per sweep for location
 constexpr int kMaxMemFlags = 64;  // mismatched input rows remembered per sweep for repair
 constexpr int kMaxRecompute = 65536;  // intersection points evaluated again per layer
-constexpr int kSweepBlock = 256;  // threads per block of the batched sweep (4 wavefronts)
+constexpr int kBatchWaves = 4;  // wavefronts per block of the batched sweep
 constexpr int kWideBlockLaneBytes = 64;  // most row bytes per lane for 8-wavefront sweep blocks
 constexpr int kFixBlock = 512;    // threads of the single locate/correct block
 constexpr int kCheckBlock = 1024; // threads per block of the offline window check

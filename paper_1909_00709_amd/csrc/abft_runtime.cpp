@@ -917,14 +917,18 @@ abft_status batch_autotune(abft_ctx* c)
     abft_status s = ABFT_OK;
     for (int tz : {2, 4, 8, 16, 32, 1 << 20})
         for (int p : {1, 0}) {
-            if ((s = batch_layout(c, tz, p))) break;
+            if ((s = batch_layout(c, tz, p))) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return s;
+            }
             // the timed sweeps read u^t and write the other buffers, as a real sweep would;
             // no fault plan, so nothing is flagged
             BatchArgs b = batch_args(c, c->t, nullptr, 0);
             b.faults = nullptr;
             b.fault_tmax = 0;
             float ms = 1e30f;
-            for (int g = 0; g < 3 && s == ABFT_OK; ++g) {
+            for (int g = 0; g < 3; ++g) {
                 (void)launch_sweep_batch(c->dtype, mode, c->csum, c->shape, b, c->nblocks,
                                          c->batch_lds, c->stream);
                 HIPCHK(c, hipEventRecord(e0, c->stream));
@@ -945,7 +949,6 @@ abft_status batch_autotune(abft_ctx* c)
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (s) return s;
     // the timing runs left the next sweep's flag slots and tile counter as a sweep would
     s = batch_layout(c, best_tz, best_p);
     if (s) return s;
