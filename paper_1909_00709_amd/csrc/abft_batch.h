@@ -128,14 +128,9 @@ hipError_t launch_batch_t(const SweepShape& s, const BatchArgs& b, int nblocks, 
 #define ABFT_BATCH_CASE(LPR_, NCH_, VEC_)                                                      \
     if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_) {                                     \
         auto kern = sweep_batch_kernel<T, MODE, CS, LPR_, NCH_, VEC_, RAD, BOX>;               \
-        static int lds_set = 0;                                                                \
-        if (lds > 65536 && (int)lds > lds_set) {                                               \
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),             \
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,      \
-                                               (int)lds);                                      \
-            if (e != hipSuccess) return e;                                                     \
-            lds_set = (int)lds;                                                                \
-        }                                                                                      \
+        static LdsAllowed lds_ok;                                                              \
+        if (hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds, lds_ok))        \
+            return e;                                                                          \
         hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kBatchWaves * 64), lds, st, b);           \
         return hipGetLastError();                                                              \
     }

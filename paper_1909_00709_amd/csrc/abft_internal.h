@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "abft_stencil.h"
 
 namespace abft {
@@ -39,6 +41,26 @@ __host__ __device__ constexpr int w_slot(int axis, int d, int sign)
 __host__ __device__ constexpr int box_slot(int dx, int dy, int dz)
 {
     return (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+}
+
+// Dynamic LDS above 64 KiB has to be allowed for each kernel on each device before it is
+// launched with it.  One LdsAllowed per kernel instantiation (a function-local static) records
+// the largest size allowed so far on each device, so the attribute is set once per size.
+constexpr int kMaxDevices = 64;
+struct LdsAllowed {
+    std::atomic<int> bytes[kMaxDevices];
+};
+inline hipError_t allow_lds(const void* kern, size_t lds, LdsAllowed& seen)
+{
+    if (lds <= 65536) return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const bool known = dev >= 0 && dev < kMaxDevices;
+    if (known && (int)lds <= seen.bytes[dev].load(std::memory_order_relaxed)) return hipSuccess;
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess && known) seen.bytes[dev].store((int)lds, std::memory_order_relaxed);
+    return e;
 }
 
 struct Stencil {

@@ -96,16 +96,11 @@ hipError_t launch_recover_t(const SweepShape& s, const RecoverArgs& r, size_t ld
 #define ABFT_RECOVER_CASE_NW(LPR_, NCH_, VEC_, NW_)                                            \
     if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_ && s.nw == NW_) {                      \
         auto kern = recover_kernel<T, CS, LPR_, NCH_, VEC_, NW_, RAD, BOX>;                    \
-        static int lds_set = 0;                                                                \
+        static LdsAllowed lds_ok;                                                              \
         static size_t occ_lds = 0;                                                             \
         static int occ = 0;                                                                    \
-        if (lds > 65536 && (int)lds > lds_set) {                                               \
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),             \
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,      \
-                                               (int)lds);                                      \
-            if (e != hipSuccess) return e;                                                     \
-            lds_set = (int)lds;                                                                \
-        }                                                                                      \
+        if (hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds, lds_ok))        \
+            return e;                                                                          \
         if (occ_lds != lds || occ < 1) {                                                       \
             hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, NW_ * 64,  \
                                                                         lds);                  \

@@ -671,14 +671,9 @@ hipError_t launch_sweep_t(const SweepShape& s, const SweepArgs& a, hipStream_t s
 #define ABFT_SWEEP_CASE_NW(LPR_, NCH_, VEC_, PF_, NW_)                                        \
     if (s.lpr == LPR_ && s.nch == NCH_ && s.vec == VEC_ && s.pf == PF_ && s.nw == NW_) {       \
         auto kern = sweep_kernel<T, MODE, CS, LPR_, NCH_, VEC_, PF_, NW_, RAD>;                \
-        static int lds_set = 0;                                                                \
-        if (lds > 65536 && (int)lds > lds_set) {                                               \
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),             \
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,      \
-                                               (int)lds);                                      \
-            if (e != hipSuccess) return e;                                                     \
-            lds_set = (int)lds;                                                                \
-        }                                                                                      \
+        static LdsAllowed lds_ok;                                                              \
+        if (hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds, lds_ok))        \
+            return e;                                                                          \
         hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(NW_ * 64), lds, st, a);                  \
         return hipGetLastError();                                                              \
     }
