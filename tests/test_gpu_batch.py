@@ -11,13 +11,13 @@ pytestmark = pytest.mark.gpu
 
 def _run_batch(shapes, inputs, nsweeps, plan, *, eps=1e-7, graph=False, persistent=None,
                autotune=False, chunks=None, csum="f64", correction="checksum",
-               taps=W.THERMAL_TAPS):
+               taps=W.THERMAL_TAPS, mode="online"):
     import torch
     from paper_1909_00709_amd import abft
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         grids = [(torch.from_numpy(u).cuda(), torch.from_numpy(c).cuda()) for u, c in inputs]
-        B = abft.Batch(grids, taps, threshold=eps, csum=csum, stream=stream,
+        B = abft.Batch(grids, taps, mode=mode, threshold=eps, csum=csum, stream=stream,
                        max_events=1 << 14, correction=correction)
         try:
             if autotune:
@@ -101,6 +101,23 @@ def test_batch_small_mixed():
     outs, ev, rep, _ = _run_batch(shapes, inputs, 30, plan)
     assert rep["corrected"] == sum(len(p) for p in per_grid.values())
     _check_grids(shapes, inputs, outs, ev, 30, per_grid, 1e-7, range(len(shapes)))
+
+
+def test_batch_plain_mode():
+    """The unprotected batch (its own kernel variant and register budget), eager and autotuned
+    in a graph, against each grid's plain oracle run; no checksum events."""
+    shapes = W.c4_shapes(12, seed=46)
+    inputs = W.c4_inputs(shapes)
+    say("batch plain", shapes)
+    a = _run_batch(shapes, inputs, 12, None, mode="none")
+    b = _run_batch(shapes, inputs, 12, None, mode="none", autotune=True, graph=True,
+                   chunks=[4, 8])
+    assert len(a[1]) == 0 and len(b[1]) == 0
+    for g in range(len(shapes)):
+        u0, C = inputs[g]
+        o, _, _ = run_oracle(u0, W.THERMAL_TAPS, 12, C=C, mode="none")
+        assert np.array_equal(a[0][g], b[0][g]), g
+        assert_grid_close(a[0][g], o, 1e-5, f"plain grid {g} {shapes[g]}")
 
 
 def test_batch_dispatch_forms_and_graph_agree():
