@@ -268,10 +268,10 @@ BOX27_TAPS = tuple((dx, dy, dz, (0.4, 0.05, 0.015, 0.005)[abs(dx) + abs(dy) + ab
 
 
 def bench_radius2(stream, timed, u0, C, tune=True, k=10, steps=10, taps=DIFF4_TAPS,
-                  name="13-point radius-2 star (fourth-order diffusion)"):
+                  name="13-point radius-2 star (fourth-order diffusion)", tuning_cache=None):
     """A stencil other than the 7-point star on the large grid (the 13-point radius-2 star
     by default): plain sweep, protected sweep kernel, online ABFT (graph) and offline windows
-    of k, each autotuned."""
+    of k, each autotuned (or, untuned, with the shapes of the tuning cache)."""
     import torch
 
     from paper_1909_00709_amd import abft
@@ -289,7 +289,8 @@ def bench_radius2(stream, timed, u0, C, tune=True, k=10, steps=10, taps=DIFF4_TA
                            ("offline", "offline", dict(threshold=2e-6, period=k,
                                                        input_check=False))):
         with torch.cuda.stream(stream):
-            S = abft.Stencil(u0.clone(), taps, C=C, mode=mode, stream=stream, **kw)
+            S = abft.Stencil(u0.clone(), taps, C=C, mode=mode, stream=stream,
+                             tuning_cache=tuning_cache, **kw)
             if tune:
                 S.autotune()
             if name.startswith("online"):
@@ -314,10 +315,10 @@ def bench_radius2(stream, timed, u0, C, tune=True, k=10, steps=10, taps=DIFF4_TA
     return res
 
 
-def bench_tiles(stream, timed, u0, C, tune=True, k=10, steps=10):
+def bench_tiles(stream, timed, u0, C, tune=True, k=10, steps=10, tuning_cache=None):
     """Tile-local checksums (64-point tiles) on the large grid against whole-row checksums:
     the protected sweep with its check (no locate launches) and online ABFT (graph), each
-    autotuned."""
+    autotuned (or, untuned, with the shapes of the tuning cache)."""
     import torch
 
     import workloads as W
@@ -332,7 +333,8 @@ def bench_tiles(stream, timed, u0, C, tune=True, k=10, steps=10):
                            ("tiles_online", "online", dict(tile_x=64))):
         with torch.cuda.stream(stream):
             S = abft.Stencil(u0.clone(), W.THERMAL_TAPS, C=C, mode=mode, stream=stream,
-                             threshold=4e-7, input_check=False, **kw)
+                             threshold=4e-7, input_check=False, tuning_cache=tuning_cache,
+                             **kw)
             if tune:
                 S.autotune()
             if name.endswith("online"):
@@ -515,19 +517,19 @@ def main():
         batch = bench_batch(stream, timed, tune=not args.no_tune)
 
     if args.only == "radius2":
-        print(json.dumps({"only": "radius2", "radius2": bench_radius2(stream, timed, u0, C,
-                                                                      tune=not args.no_tune)}))
+        print(json.dumps({"only": "radius2", "radius2": bench_radius2(
+            stream, timed, u0, C, tune=not args.no_tune, tuning_cache=args.tuning_cache)}))
         return
 
     if args.only == "tiles":
-        print(json.dumps({"only": "tiles", "tiles": bench_tiles(stream, timed, u0, C,
-                                                                tune=not args.no_tune)}))
+        print(json.dumps({"only": "tiles", "tiles": bench_tiles(
+            stream, timed, u0, C, tune=not args.no_tune, tuning_cache=args.tuning_cache)}))
         return
 
     if args.only == "box27":
         print(json.dumps({"only": "box27", "box27": bench_radius2(
             stream, timed, u0, C, tune=not args.no_tune, taps=BOX27_TAPS,
-            name="27-point box smoother")}))
+            name="27-point box smoother", tuning_cache=args.tuning_cache)}))
         return
 
     if args.only == "periods":

@@ -39,13 +39,17 @@ __device__ __forceinline__ T ghost_value(const FixArgs& a, const T* u, int x, in
 // term, then one fused multiply-add per tap, absent taps adding zero), so that the value is
 // the one the sweep stores for the same input.
 template <typename T, int RAD, int BOX>
-__device__ T point_value(const FixArgs& a, const T* u, int x, int y, int z)
+__device__ __forceinline__ T point_value(const FixArgs& a, const T* u, int x, int y, int z)
 {
     const size_t i = ((size_t)z * a.ny + y) * a.nx + x;
     T acc = a.C != nullptr ? static_cast<const T*>(a.C)[i] : (T)a.c_scalar;
     if constexpr (BOX) {
+        // unrolled: constant tap indices keep the weights out of private memory
+#pragma unroll
         for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) {
                     const int sl = box_slot(dx, dy, dz);
                     const bool on = (a.st.bmask >> sl) & 1u;
@@ -74,7 +78,7 @@ __device__ T point_value(const FixArgs& a, const T* u, int x, int y, int z)
 // outside the grid (a row of constant ghosts has none): dx < 0 reads G(dx .. -1) and drops
 // u(nx+dx .. nx-1); dx > 0 reads G(nx .. nx+dx-1) and drops u(0 .. dx-1).
 template <typename T>
-__device__ double row_boundary_term(const FixArgs& a, const T* u, int z, int y, int dx)
+__device__ __forceinline__ double row_boundary_term(const FixArgs& a, const T* u, int z, int y, int dx)
 {
     if (map_coord(z, a.nz, a.st.bc) < 0 || map_coord(y, a.ny, a.st.bc) < 0) return 0.0;
     double b = 0.0;
@@ -90,7 +94,7 @@ __device__ double row_boundary_term(const FixArgs& a, const T* u, int z, int y, 
 // Theorem 1's prediction of output row (z, y) from the input's checksums and boundary values,
 // as the sweep forms it.
 template <typename T, int RAD, int BOX>
-__device__ double predict_row(const FixArgs& a, const T* u, int z, int y)
+__device__ __forceinline__ double predict_row(const FixArgs& a, const T* u, int z, int y)
 {
     const int bc = a.st.bc, nx = a.nx;
     auto brow = [&](int z2, int y2) -> double {
@@ -102,17 +106,23 @@ __device__ double predict_row(const FixArgs& a, const T* u, int z, int y)
     double bp = a.cB[l];
     if constexpr (BOX) {
         double e = 0.0;
+        // unrolled, as in point_value
+#pragma unroll
         for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
             for (int dy = -1; dy <= 1; ++dy) {
                 const int sm = box_slot(-1, dy, dz), sp = box_slot(1, dy, dz);
                 if ((a.st.bmask >> sm) & 1u) e += a.st.wb[sm] * row_boundary_term(a, u, z + dz, y + dy, -1);
                 if ((a.st.bmask >> sp) & 1u) e += a.st.wb[sp] * row_boundary_term(a, u, z + dz, y + dy, 1);
             }
         bp += e;
+#pragma unroll
         for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
             for (int dy = -1; dy <= 1; ++dy) {
                 double wsum = 0.0;
                 bool any = false;
+#pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) {
                     const int sl = box_slot(dx, dy, dz);
                     if ((a.st.bmask >> sl) & 1u) {
@@ -186,7 +196,7 @@ __device__ void block_row_sums(const T* row, int nx, double* red, double* s, dou
 // again, and the checksums of the output rows in the window recomputed.  Returns the number of
 // points repaired (the same in every thread).
 template <typename T, int RAD, int BOX>
-__device__ int repair_inputs(const FixArgs& a, double* red, int64_t t)
+__device__ __forceinline__ int repair_inputs(const FixArgs& a, double* red, int64_t t)
 {
     FlagSlot* slot = a.slot;
     const unsigned m_all = slot->mcount;
@@ -289,7 +299,7 @@ __device__ int repair_inputs(const FixArgs& a, double* red, int64_t t)
 // flagged tiles' sums are recomputed.
 // ------------------------------------------------------------------------------------------
 template <typename T, int RAD>
-__device__ void fix_tiles_layer(const FixArgs& a, int i, int j, int z, const int* xs, int K,
+__device__ __forceinline__ void fix_tiles_layer(const FixArgs& a, int i, int j, int z, const int* xs, int K,
                                 const double* Ap, double* red, int& sh, int64_t t)
 {
     FlagSlot* slot = a.slot;
@@ -499,7 +509,7 @@ __global__ void __launch_bounds__(256) tile_check_kernel(const TileCheckArgs a, 
 // directly).  Exits at once when nothing was flagged.
 // ------------------------------------------------------------------------------------------
 template <typename T, int RAD, int BOX>
-__device__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* red, int& sh_K)
+__device__ __forceinline__ void fixup_body(const FixArgs& a, unsigned char* smem_raw, double* red, int& sh_K)
 {
     FlagSlot* slot = a.slot;
     if (slot->count == 0u && slot->mcount == 0u) return;  // nothing flagged: the usual case
