@@ -11,14 +11,14 @@ pytestmark = pytest.mark.gpu
 
 def _run_batch(shapes, inputs, nsweeps, plan, *, eps=1e-7, graph=False, persistent=None,
                autotune=False, chunks=None, csum="f64", correction="checksum",
-               taps=W.THERMAL_TAPS, mode="online"):
+               taps=W.THERMAL_TAPS, mode="online", input_check=True):
     import torch
     from paper_1909_00709_amd import abft
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         grids = [(torch.from_numpy(u).cuda(), torch.from_numpy(c).cuda()) for u, c in inputs]
         B = abft.Batch(grids, taps, mode=mode, threshold=eps, csum=csum, stream=stream,
-                       max_events=1 << 14, correction=correction)
+                       max_events=1 << 14, correction=correction, input_check=input_check)
         try:
             if autotune:
                 B.autotune()
@@ -133,6 +133,41 @@ def test_batch_dispatch_forms_and_graph_agree():
         assert np.array_equal(a[0][g], b[0][g]) and np.array_equal(a[0][g], c[0][g]), g
     assert event_keys(a[1]) == event_keys(b[1]) == event_keys(c[1])
     assert a[2]["corrected"] == 2
+
+
+@pytest.mark.parametrize("dtype,csum,input_check", [
+    ("f32", "f64", False), ("f32", "f32comp", False), ("f32", "f32comp", True),
+    ("f64", "f64", False), ("f64", "f64", True)])
+def test_batch_dtypes_and_checksums(dtype, csum, input_check):
+    """The batched variants the other batch tests leave out: the protected sweep without the
+    input check (the online form the batch benchmark times), compensated-fp32 row checksums,
+    and fp64 grids; autotuned and graph-captured, with mantissa and exponent flips in three
+    grids, every grid against its own oracle run (events exactly; values within 1e-5 for
+    fp32, 1e-12 for fp64)."""
+    shapes = W.c4_shapes(10, seed=49)
+    npdt = np.float32 if dtype == "f32" else np.float64
+    inputs = [W.thermal_grid(nx, ny, nz, npdt, 10 + g, 110 + g)
+              for g, (nz, ny, nx) in enumerate(shapes)]
+    bits = (20, 26, 30) if dtype == "f32" else (44, 51, 60)
+    eps, tol = (1e-7, 1e-5) if dtype == "f32" else (1e-12, 1e-12)
+    per_grid = {}
+    for k, g in enumerate((0, 3, 6)):
+        nz, ny, nx = shapes[g]
+        per_grid[g] = W.make_plan([(2 + 3 * k, (k + 1) % nz, (5 * k + 3) % ny,
+                                    (11 * k + 7) % nx, bits[k])])
+    plan = _batch_plan(per_grid)
+    say("batch variant", dtype, csum, "input_check" if input_check else "no input check")
+    outs, ev, rep, _ = _run_batch(shapes, inputs, 12, plan, eps=eps, csum=csum,
+                                  input_check=input_check, autotune=True, graph=True,
+                                  chunks=[6, 6])
+    assert rep["corrected"] == 3 and rep["uncorrectable"] == 0, rep
+    assert rep["rows_flagged"] == 3 and rep["max_noise"] < eps, rep
+    for g in range(len(shapes)):
+        u0, C = inputs[g]
+        o, oev, _ = run_oracle(u0, W.THERMAL_TAPS, 12, C=C, eps=eps, plan=per_grid.get(g),
+                               input_check=input_check)
+        assert event_keys(ev[ev["grid"] == g]) == event_keys(oev), g
+        assert_grid_close(outs[g], o, tol, f"{dtype} {csum} grid {g} {shapes[g]}")
 
 
 def test_c4_full():
