@@ -11,14 +11,16 @@ pytestmark = pytest.mark.gpu
 
 def _run_batch(shapes, inputs, nsweeps, plan, *, eps=1e-7, graph=False, persistent=None,
                autotune=False, chunks=None, csum="f64", correction="checksum",
-               taps=W.THERMAL_TAPS, mode="online", input_check=True):
+               taps=W.THERMAL_TAPS, mode="online", input_check=True, bc="clamp",
+               bc_value=0.0):
     import torch
     from paper_1909_00709_amd import abft
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         grids = [(torch.from_numpy(u).cuda(), torch.from_numpy(c).cuda()) for u, c in inputs]
         B = abft.Batch(grids, taps, mode=mode, threshold=eps, csum=csum, stream=stream,
-                       max_events=1 << 14, correction=correction, input_check=input_check)
+                       max_events=1 << 14, correction=correction, input_check=input_check,
+                       bc=bc, bc_value=bc_value)
         try:
             if autotune:
                 B.autotune()
@@ -168,6 +170,47 @@ def test_batch_dtypes_and_checksums(dtype, csum, input_check):
                                input_check=input_check)
         assert event_keys(ev[ev["grid"] == g]) == event_keys(oev), g
         assert_grid_close(outs[g], o, tol, f"{dtype} {csum} grid {g} {shapes[g]}")
+
+
+@pytest.mark.parametrize("bc,input_check", [("clamp", False), ("periodic", True),
+                                             ("constant", True), ("constant", False)])
+def test_batch_boundary_rules_asymmetric(bc, input_check):
+    """Batches under every boundary rule with asymmetric weights, so that the x-boundary terms
+    of Theorem 1 do not cancel: stored-value flips in three grids and, with the input check,
+    a value changed in memory in a fourth; every grid against its own oracle run."""
+    from tests.test_gpu_parity import ASYM_TAPS
+    shapes = W.c4_shapes(8, seed=50)
+    inputs = W.c4_inputs(shapes)
+    per_grid = {}
+    for k, (g, bit) in enumerate(((1, 22), (4, 26), (6, 30))):
+        nz, ny, nx = shapes[g]
+        # row ends and an inner point, where the boundary terms and the ghosts matter
+        x = (0, nx - 1, nx // 2)[k]
+        per_grid[g] = W.make_plan([(1 + 3 * k, (k + 2) % nz, (7 * k + 1) % ny, x, bit)])
+    if input_check:
+        nz, ny, nx = shapes[2]
+        per_grid[2] = W.make_plan([(4, 1, ny - 1, 3, 27, 0, W.FAULT_MEMORY)])
+    rows = []
+    for g, p in per_grid.items():
+        for f in p:
+            rows.append((int(f["sweep"]), int(f["z"]), int(f["y"]), int(f["x"]), int(f["bit"]),
+                         0, int(f["kind"]), g))
+    plan = W.empty_plan(len(rows))
+    for i, r in enumerate(rows):
+        for k, name in enumerate(("sweep", "z", "y", "x", "bit", "attempt", "kind", "grid")):
+            plan[i][name] = r[k]
+    plan.sort(order="sweep", kind="stable")
+    say("batch bc", bc, "input_check" if input_check else "no input check")
+    outs, ev, rep, _ = _run_batch(shapes, inputs, 10, plan, eps=3e-7, taps=ASYM_TAPS,
+                                  input_check=input_check, bc=bc, bc_value=2.5, autotune=True)
+    assert rep["corrected"] == 3 and rep["uncorrectable"] == 0, rep
+    assert rep["mem_corrected"] == (1 if input_check else 0), rep
+    for g in range(len(shapes)):
+        u0, C = inputs[g]
+        o, oev, _ = run_oracle(u0, ASYM_TAPS, 10, C=C, eps=3e-7, plan=per_grid.get(g), bc=bc,
+                               bc_value=2.5, input_check=input_check)
+        assert event_keys(ev[ev["grid"] == g]) == event_keys(oev), g
+        assert_grid_close(outs[g], o, 1e-5, f"{bc} grid {g} {shapes[g]}")
 
 
 def test_c4_full():
