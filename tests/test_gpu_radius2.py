@@ -145,3 +145,30 @@ def test_radius2_rejected_where_unsupported():
     u = torch.zeros((2, 8, 1), device="cuda")
     with pytest.raises(abft.AbftError):  # the same in a batch
         abft.Batch([(u, None)], DYADIC2)
+
+
+@pytest.mark.parametrize("form", ["star2", "box"])
+@pytest.mark.parametrize("mode,input_check", [("online", False), ("online", True),
+                                              ("offline", False)])
+def test_f32comp_radius2_and_box(form, mode, input_check):
+    """Compensated-fp32 row checksums with the radius-2 star and the 27-point box (kernel
+    variants of their own): an fp32 thermal grid with asymmetric weights, flips at a row's
+    first and last points and inside, online location and correction (with and without the
+    input check) or offline rollback, against the oracle (fp64 checksums; events equal, every
+    flip far above the threshold; values within 1e-5)."""
+    from tests.test_gpu_memory_faults import BOX, STAR2
+    taps = {"star2": STAR2, "box": BOX}[form]
+    u0, C = W.thermal_grid(260, 33, 6, np.float32, 3, 4)
+    plan = W.make_plan([(1, 2, 0, 0, 26), (4, 4, 17, 259, 22), (7, 1, 32, 130, 30)])
+    eps = 3e-7 if mode == "online" else 2e-6
+    kw = dict(C=C, eps=eps, plan=plan, mode=mode, period=3, input_check=input_check)
+    say("f32comp", form, mode, input_check)
+    g, gev, grep, _ = run_gpu(u0, taps, 9, csum="f32comp", autotune=True, **kw)
+    o, oev, ocnt = run_oracle(u0, taps, 9, **kw)
+    if mode == "online":
+        assert grep["corrected"] == 3 and ocnt["corrected"] == 3, (grep, ocnt)
+    else:
+        assert grep["rollbacks"] == 3 and ocnt["rollbacks"] == 3, (grep, ocnt)
+    assert grep["uncorrectable"] == 0 and grep["persistent"] == 0
+    assert event_keys(gev) == event_keys(oev)
+    assert_grid_close(g, o, 1e-5, f"f32comp {form} {mode}")
