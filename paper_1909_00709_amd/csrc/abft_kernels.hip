@@ -35,6 +35,11 @@ __device__ __forceinline__ T ghost_value(const FixArgs& a, const T* u, int x, in
     return u[((size_t)mz * a.ny + my) * a.nx + mx];
 }
 
+// The locate/correct helpers below take the kernel's by-value arguments by reference and are
+// force-inlined: as real calls, the radius-2 and box variants had the arguments (with the
+// stencil's weights) copied into private memory, 552-656 bytes per lane, and even their
+// fault-free launch, which exits at once, took about twice as long.
+
 // Eq.(1) at one point with the operations of the sweep kernels in their order (the constant
 // term, then one fused multiply-add per tap, absent taps adding zero), so that the value is
 // the one the sweep stores for the same input.
