@@ -1258,7 +1258,7 @@ bool sweep_shape_supported(int dtype, const SweepShape& s)
     const int vf = dtype == ABFT_F32 ? 4 : 2;
     if (s.tz < 1 || (s.nw != 4 && s.nw != 8) || (s.rad != 1 && s.rad != 2)) return false;
     if (s.box && (s.rad != 1 || s.pf != 1)) return false;
-    if (s.nw == 8 && s.nch * s.vec * (vf == 4 ? 4 : 8) * s.rad > kWideBlockLaneBytes)
+    if (s.nw == 8 && s.nch * s.vec * (vf == 4 ? 4 : 8) > kWideBlockLaneBytes)
         return false;
     if (s.pf == 2)
         return s.rad == 1 && s.vec == vf && s.lpr == 64 && (s.nch == 2 || s.nch == 4);

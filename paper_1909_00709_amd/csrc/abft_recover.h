@@ -115,7 +115,7 @@ hipError_t launch_recover_t(const SweepShape& s, const RecoverArgs& r, size_t ld
     }
 #define ABFT_RECOVER_CASE(LPR_, NCH_, VEC_)                                                    \
     ABFT_RECOVER_CASE_NW(LPR_, NCH_, VEC_, 4)                                                  \
-    if constexpr (NCH_ * VEC_ * sizeof(T) * RAD <= kWideBlockLaneBytes) {                      \
+    if constexpr (NCH_ * VEC_ * sizeof(T) <= kWideBlockLaneBytes) {                            \
         ABFT_RECOVER_CASE_NW(LPR_, NCH_, VEC_, 8)                                              \
     }
     constexpr int VF = 16 / (int)sizeof(T);

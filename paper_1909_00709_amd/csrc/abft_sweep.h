@@ -677,12 +677,12 @@ hipError_t launch_sweep_t(const SweepShape& s, const SweepArgs& a, hipStream_t s
         hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(NW_ * 64), lds, st, a);                  \
         return hipGetLastError();                                                              \
     }
-// Blocks of 8 wavefronts only where a lane's share of a row is at most 64 bytes (32 for
-// radius 2, which holds five planes): with more, the planes held in registers exceed the 256
-// registers a lane may have at that block size.
+// Blocks of 8 wavefronts only where a lane's share of a row is at most 64 bytes: with more,
+// the planes held in registers exceed the 256 registers a lane may have at that block size.
+// At radius 2 (five planes) the 64-byte shapes take 230-234 registers without spilling.
 #define ABFT_SWEEP_CASE_PF(LPR_, NCH_, VEC_, PF_)                                              \
     ABFT_SWEEP_CASE_NW(LPR_, NCH_, VEC_, PF_, 4)                                               \
-    if constexpr (NCH_ * VEC_ * sizeof(T) * RAD <= kWideBlockLaneBytes) {                      \
+    if constexpr (NCH_ * VEC_ * sizeof(T) <= kWideBlockLaneBytes) {                            \
         ABFT_SWEEP_CASE_NW(LPR_, NCH_, VEC_, PF_, 8)                                           \
     }
 #define ABFT_SWEEP_CASE(LPR_, NCH_, VEC_) ABFT_SWEEP_CASE_PF(LPR_, NCH_, VEC_, 1)
