@@ -23,7 +23,7 @@ def say(*args):
 def run_gpu(u0, taps, nsweeps, *, C=None, c_scalar=0.0, mode="online", eps=1e-12, period=10,
             csum="f64", auto_correct=True, plan=None, bc="clamp", bc_value=0.0, graph=False,
             chunks=None, max_events=1 << 16, autotune=False, input_check=True,
-            correction="checksum", tile_x=0):
+            correction="checksum", tile_x=0, tuning_cache=None):
     """Returns (final grid as numpy, events, report, stencil-shape)."""
     import torch
     from paper_1909_00709_amd import abft
@@ -34,7 +34,7 @@ def run_gpu(u0, taps, nsweeps, *, C=None, c_scalar=0.0, mode="online", eps=1e-12
         S = abft.Stencil(ut, taps, C=Ct, c_scalar=c_scalar, bc=bc, bc_value=bc_value, mode=mode,
                          period=period, threshold=eps, csum=csum, auto_correct=auto_correct,
                          max_events=max_events, stream=stream, input_check=input_check,
-                         correction=correction, tile_x=tile_x)
+                         correction=correction, tile_x=tile_x, tuning_cache=tuning_cache)
         try:
             if autotune:
                 S.autotune()

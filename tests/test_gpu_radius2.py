@@ -172,3 +172,33 @@ def test_f32comp_radius2_and_box(form, mode, input_check):
     assert grep["uncorrectable"] == 0 and grep["persistent"] == 0
     assert event_keys(gev) == event_keys(oev)
     assert_grid_close(g, o, 1e-5, f"f32comp {form} {mode}")
+
+
+@pytest.mark.parametrize("mode,input_check", [("online", False), ("online", True),
+                                              ("offline", False), ("none", False)])
+def test_radius2_wide_blocks_forced(mode, input_check, tmp_path):
+    """Radius-2 sweeps in blocks of 8 wavefronts (8 rows of 1024 points, 64 lanes of four
+    16-byte chunks per row), forced through the tuning cache for every variant (the autotuner
+    may prefer 4-wavefront blocks for some): online location and correction with and without
+    the input check, offline rollback (the one-launch recompute in the same block shape), and
+    plain sweeps, against the oracle; a ragged last row block and a ragged last slab."""
+    u0, C = W.thermal_grid(1024, 21, 7, np.float32, 5, 6)
+    mcode = {"none": 0, "online": 1, "offline": 2}[mode]
+    tags = "r2 ic" if input_check else "r2"
+    cache = tmp_path / "wide.tune"
+    cache.write_text(f"0 1024 21 7 {mcode} 0 {tags} 64 4 4 4 1 8\n")
+    plan = W.make_plan([(1, 2, 0, 0, 26), (4, 6, 20, 1023, 22), (7, 1, 9, 517, 30)])
+    eps = 3e-7 if mode != "offline" else 2e-6
+    kw = dict(C=C, eps=eps, mode=mode, period=3, input_check=input_check)
+    if mode != "none":
+        kw["plan"] = plan
+    say("radius 2 wide blocks", mode, input_check)
+    g, gev, grep, shape = run_gpu(u0, ASYM2, 9, tuning_cache=str(cache), **kw)
+    assert shape[0] == 8, shape  # 8 rows per block: the cached 8-wavefront shape is in use
+    o, oev, ocnt = run_oracle(u0, ASYM2, 9, **kw)
+    if mode == "online":
+        assert grep["corrected"] == 3 and ocnt["corrected"] == 3, (grep, ocnt)
+    elif mode == "offline":
+        assert grep["rollbacks"] == 3 and ocnt["rollbacks"] == 3, (grep, ocnt)
+    assert event_keys(gev) == event_keys(oev)
+    assert_grid_close(g, o, 1e-5, f"radius 2 wide blocks {mode}")
