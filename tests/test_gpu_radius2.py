@@ -174,21 +174,30 @@ def test_f32comp_radius2_and_box(form, mode, input_check):
     assert_grid_close(g, o, 1e-5, f"f32comp {form} {mode}")
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("mode,input_check", [("online", False), ("online", True),
                                               ("offline", False), ("none", False)])
-def test_radius2_wide_blocks_forced(mode, input_check, tmp_path):
-    """Radius-2 sweeps in blocks of 8 wavefronts (8 rows of 1024 points, 64 lanes of four
-    16-byte chunks per row), forced through the tuning cache for every variant (the autotuner
-    may prefer 4-wavefront blocks for some): online location and correction with and without
-    the input check, offline rollback (the one-launch recompute in the same block shape), and
-    plain sweeps, against the oracle; a ragged last row block and a ragged last slab."""
-    u0, C = W.thermal_grid(1024, 21, 7, np.float32, 5, 6)
+def test_radius2_wide_blocks_forced(mode, input_check, dtype, tmp_path):
+    """Radius-2 sweeps in blocks of 8 wavefronts (8 rows of 1024 fp32 or 512 fp64 points, 64
+    lanes of four 16-byte chunks per row), forced through the tuning cache for every variant
+    (the autotuner may prefer 4-wavefront blocks for some): online location and correction
+    with and without the input check, offline rollback (the one-launch recompute in the same
+    block shape), and plain sweeps, against the oracle; a ragged last row block and a ragged
+    last slab."""
+    f32 = dtype == "f32"
+    nx = 1024 if f32 else 512
+    u0, C = W.thermal_grid(nx, 21, 7, np.float32 if f32 else np.float64, 5, 6)
     mcode = {"none": 0, "online": 1, "offline": 2}[mode]
     tags = "r2 ic" if input_check else "r2"
     cache = tmp_path / "wide.tune"
-    cache.write_text(f"0 1024 21 7 {mcode} 0 {tags} 64 4 4 4 1 8\n")
-    plan = W.make_plan([(1, 2, 0, 0, 26), (4, 6, 20, 1023, 22), (7, 1, 9, 517, 30)])
-    eps = 3e-7 if mode != "offline" else 2e-6
+    cache.write_text(f"{0 if f32 else 1} {nx} 21 7 {mcode} 0 {tags} 64 4 {4 if f32 else 2} 4 1 8\n")
+    bits = (26, 22, 30) if f32 else (60, 51, 44)
+    plan = W.make_plan([(1, 2, 0, 0, bits[0]), (4, 6, 20, nx - 1, bits[1]),
+                        (7, 1, 9, 317, bits[2])])
+    if f32:
+        eps, tol = (3e-7 if mode != "offline" else 2e-6), 1e-5
+    else:
+        eps, tol = 1e-12, 1e-12
     kw = dict(C=C, eps=eps, mode=mode, period=3, input_check=input_check)
     if mode != "none":
         kw["plan"] = plan
@@ -201,4 +210,4 @@ def test_radius2_wide_blocks_forced(mode, input_check, tmp_path):
     elif mode == "offline":
         assert grep["rollbacks"] == 3 and ocnt["rollbacks"] == 3, (grep, ocnt)
     assert event_keys(gev) == event_keys(oev)
-    assert_grid_close(g, o, 1e-5, f"radius 2 wide blocks {mode}")
+    assert_grid_close(g, o, tol, f"radius 2 wide blocks {dtype} {mode}")
