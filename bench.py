@@ -12,7 +12,7 @@ checked, locate/correct launch after each sweep), and the protected sweep kernel
 And the batched workload: 64 uneven fp32 grids (64..256 x 64..256 x 4..32) swept by one
 launch per sweep, online and plain, captured in hipGraphs, beside one context per grid.
 
-Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -383,7 +383,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is described, not built)", file=sys.stderr)
         sys.exit(2)
 

@@ -177,7 +177,7 @@ abft_status map_taps(abft_ctx* c, const abft_problem* p)
             const abft_tap& t = p->taps[k];
             if (std::abs(t.dx) > 1 || std::abs(t.dy) > 1 || std::abs(t.dz) > 1)
                 return fail(c, ABFT_E_UNSUPPORTED,
-                            "GPU box stencils take offsets within -1..1 on every axis");
+                            "box stencils on the GPU take offsets within -1..1 on every axis");
             const int slot = box_slot(t.dx, t.dy, t.dz);
             if (c->st.bmask & (1u << slot)) return fail(c, ABFT_E_INVAL, "duplicate tap offset");
             if (!std::isfinite(t.w)) return fail(c, ABFT_E_INVAL, "non-finite tap weight");

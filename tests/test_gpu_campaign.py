@@ -12,6 +12,7 @@ b <= 5: bits 0..5 are never seen.  Bits 6..11 depend on the value at the time of
 import collections
 import json
 import os
+import tempfile
 
 import numpy as np
 import pytest
@@ -23,7 +24,8 @@ pytestmark = pytest.mark.gpu
 
 B_MIN_GUARANTEED = 12
 B_MAX_NEVER = 5
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+# where the run writes its result summary (JSON): $ABFT_TEST_OUT, else the system temp folder
+OUT = os.environ.get("ABFT_TEST_OUT") or os.path.join(tempfile.gettempdir(), "abft_test_out")
 
 
 def _summary(plan, ev):

@@ -2,6 +2,7 @@
 (autotuned): parity with the oracle, and the offline run with 50 seeded flips."""
 import json
 import os
+import tempfile
 
 import numpy as np
 import pytest
@@ -10,7 +11,8 @@ import workloads as W
 from tests.gpu_util import assert_grid_close, event_keys, rel_errors, run_gpu, run_oracle, say
 
 pytestmark = pytest.mark.gpu
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+# where the run writes its result summary (JSON): $ABFT_TEST_OUT, else the system temp folder
+OUT = os.environ.get("ABFT_TEST_OUT") or os.path.join(tempfile.gettempdir(), "abft_test_out")
 
 
 def test_c5_online_parity_20_sweeps():

@@ -13,6 +13,7 @@ not fall by more than one as the age grows.  The measured table is written to
 offline_bmin_vs_age.json in the results folder."""
 import json
 import os
+import tempfile
 
 import numpy as np
 import pytest
@@ -21,7 +22,8 @@ import workloads as W
 from tests.gpu_util import say
 
 pytestmark = pytest.mark.gpu
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+# where the run writes its result summary (JSON): $ABFT_TEST_OUT, else the system temp folder
+OUT = os.environ.get("ABFT_TEST_OUT") or os.path.join(tempfile.gettempdir(), "abft_test_out")
 
 K = 10
 BITS = range(8, 25)
