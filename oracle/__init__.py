@@ -26,6 +26,9 @@ FAULT_STORE, FAULT_MEMORY = 0, 1
 
 EVENT_DTYPE = np.dtype([("sweep", "<i8"), ("kind", "<i4"), ("z", "<i4"), ("y", "<i4"),
                         ("x", "<i4"), ("a", "<f8"), ("b", "<f8")])
+FAULT_INFO_DTYPE = np.dtype([("applied", "<i4"), ("skipped", "<i4"), ("before", "<f8"),
+                             ("after", "<f8"), ("row_sum", "<f8"), ("col_sum", "<f8"),
+                             ("signal", "<f8"), ("col_signal", "<f8")])
 COUNTER_FIELDS = ("sweeps_done", "rows_flagged", "cols_flagged", "corrected",
                   "checksum_faults", "uncorrectable", "windows_checked", "windows_flagged",
                   "rollbacks", "persistent", "events_total", "mem_flagged", "mem_corrected",
@@ -60,6 +63,10 @@ class _Counters(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in COUNTER_FIELDS]
 
 
+class _Guard(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double), ("hi", ctypes.c_double), ("info", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -86,7 +93,8 @@ def lib():
         L.orc_detect.restype = ctypes.c_int64
         L.orc_run.argtypes = [P, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                               ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int64, vp,
-                              ctypes.c_int64, vp, ctypes.c_int64, ctypes.POINTER(_Counters)]
+                              ctypes.c_int64, vp, ctypes.c_int64, ctypes.POINTER(_Counters),
+                              ctypes.POINTER(_Guard)]
         L.orc_tile_checksums.argtypes = [P, vp, ctypes.c_int, dp]
         L.orc_const_tile_checksums.argtypes = [P, vp, ctypes.c_int, dp]
         L.orc_predict_tiles.argtypes = [P, dp, dp, vp, ctypes.c_int, dp]
@@ -230,11 +238,14 @@ class Problem:
     # ---- whole runs -----------------------------------------------------------------------
     def run(self, u0, nsweeps, C=None, mode=MODE_ONLINE, period=10, eps=1e-12,
             auto_correct=True, faults=None, max_events=100000, input_check=True,
-            recompute=False, tile_x=0):
+            recompute=False, tile_x=0, guard=None, info=None):
         """Returns (final grid, events structured array, counters dict).  Online mode:
         input_check also checks each sweep's input rows against the stored checksums;
         recompute corrects located points by evaluating them again from the sweep's input;
-        tile_x > 0 keeps tile-local checksums of tile_x points (the input check is then off)."""
+        tile_x > 0 keeps tile-local checksums of tile_x points (the input check is then off).
+        guard = (lo, hi) leaves out the flips whose relative signal lies in [lo, hi] (see
+        orc_guard); info, an array of FAULT_INFO_DTYPE with one entry per fault, receives
+        what each flip did."""
         u_a = self._grid(u0).copy()
         u_b = np.empty_like(u_a)
         C = self._const(C)
@@ -242,11 +253,20 @@ class Problem:
         fptr = None if nf == 0 else _ptr(np.ascontiguousarray(faults))
         ev = np.zeros(max_events, dtype=EVENT_DTYPE)
         cnt = _Counters()
+        g = None
+        if guard is not None or info is not None:
+            if info is not None:
+                assert info.dtype == FAULT_INFO_DTYPE and len(info) == nf and \
+                    info.flags["C_CONTIGUOUS"]
+            lo, hi = guard if guard is not None else (1.0, 0.0)
+            g = _Guard(float(lo), float(hi), None if info is None or nf == 0
+                       else info.ctypes.data_as(ctypes.c_void_p).value)
         rc = lib().orc_run(self.ref, _ptr(C), mode, period, eps, int(bool(auto_correct)),
                            (1 if input_check and not tile_x else 0) | (2 if recompute else 0),
                            int(tile_x), _ptr(u_a),
                            _ptr(u_b), nsweeps, fptr, nf,
-                           _ptr(ev), max_events, ctypes.byref(cnt))
+                           _ptr(ev), max_events, ctypes.byref(cnt),
+                           None if g is None else ctypes.byref(g))
         if rc != 0:
             raise ValueError(f"orc_run failed with code {rc}")
         counters = {f: getattr(cnt, f) for f in COUNTER_FIELDS}

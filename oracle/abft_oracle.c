@@ -469,6 +469,9 @@ typedef struct {
     double c_scalar; /* rounded scalar constant term */
     int reach;       /* largest |offset| of any tap along any axis */
     int tile;        /* tile-local checksums of this many points, or 0 (whole rows) */
+    int mode;        /* ORC_MODE_* */
+    int64_t win_end; /* offline: last sweep of the current window */
+    const orc_guard* guard;
 } run_state;
 
 static void emit(run_state* S, int64_t sweep, int kind, int z, int y, int x, double a, double b)
@@ -486,6 +489,108 @@ static void emit(run_state* S, int64_t sweep, int kind, int z, int y, int x, dou
     S->cnt->events_total++;
 }
 
+/* The value with one bit flipped (Section 5.1). */
+static double flipped(int dtype, const void* u, int64_t i, int bit)
+{
+    if (dtype == ORC_F32) {
+        uint32_t v;
+        float f;
+        memcpy(&v, (const float*)u + i, 4);
+        v ^= (uint32_t)1u << bit;
+        memcpy(&f, &v, 4);
+        return (double)f;
+    }
+    uint64_t v;
+    double d;
+    memcpy(&v, (const double*)u + i, 8);
+    v ^= (uint64_t)1u << bit;
+    memcpy(&d, &v, 8);
+    return d;
+}
+
+/* |change| / |sum|, infinite when either is not finite or the sum is zero. */
+static double rel_signal(double change, double sum)
+{
+    const double r = fabs(change) / fabs(sum);
+    return r <= 1.7976931348623157e308 ? r : INFINITY;
+}
+
+/* Offline: the change d of row (z, y) at sweep `sweep` carried to the window's last sweep by
+ * the linear part of Theorem 1 (the stencil weights stepped on the checksum plane; a constant
+ * ghost contributes nothing to a change), largest absolute entry over the plane. */
+static double carried_change(const run_state* S, int z, int y, double d, int64_t steps)
+{
+    const orc_problem* p = S->p;
+    const int64_t nrows = (int64_t)p->nz * p->ny;
+    double* a = (double*)calloc((size_t)nrows, sizeof(double));
+    double* b = (double*)calloc((size_t)nrows, sizeof(double));
+    a[(int64_t)z * p->ny + y] = d;
+    for (int64_t s = 0; s < steps; s++) {
+        for (int64_t zz = 0; zz < p->nz; zz++)
+            for (int64_t yy = 0; yy < p->ny; yy++) {
+                double acc = 0.0;
+                for (int k = 0; k < p->ntaps; k++) {
+                    const int64_t my = map_coord(p->bc, yy + p->taps[k].dy, p->ny);
+                    const int64_t mz = map_coord(p->bc, zz + p->taps[k].dz, p->nz);
+                    if (my >= 0 && mz >= 0) acc += S->w[k] * a[mz * p->ny + my];
+                }
+                b[zz * p->ny + yy] = acc;
+            }
+        double* t = a;
+        a = b;
+        b = t;
+    }
+    double m = 0.0;
+    for (int64_t l = 0; l < nrows; l++)
+        if (!(fabs(a[l]) <= m)) m = fabs(a[l]);
+    free(a);
+    free(b);
+    return m;
+}
+
+/* Records what flip F is about to do to grid u (orc_fault_info) and decides, under the guard
+ * band, whether it is applied.  Returns 1 to apply it. */
+static int guard_flip(run_state* S, int64_t f, const void* u, int64_t sweep, int attempt)
+{
+    const orc_problem* p = S->p;
+    const orc_fault* F = &S->faults[f];
+    const orc_guard* G = S->guard;
+    const int64_t i = idx(p, F->x, F->y, F->z);
+    const double before = ld(p->dtype, u, i), after = flipped(p->dtype, u, i, F->bit);
+    csum rs = {0.0, 0.0}, cs = {0.0, 0.0};
+    for (int64_t q = 0; q < p->nx; q++) cs_add(&rs, ld(p->dtype, u, idx(p, q, F->y, F->z)));
+    for (int64_t q = 0; q < p->ny; q++) cs_add(&cs, ld(p->dtype, u, idx(p, F->x, q, F->z)));
+    const double row = cs_val(rs), col = cs_val(cs), d = after - before;
+    double sig = rel_signal(d, row);
+    if (S->mode == ORC_MODE_OFFLINE && F->kind == ORC_FAULT_STORE && isfinite(sig) &&
+        S->win_end > sweep)
+        sig = rel_signal(carried_change(S, F->z, F->y, d, S->win_end - sweep), row);
+    const double csig = rel_signal(d, col);
+    int skip = 0;
+    if (F->kind == ORC_FAULT_STORE && attempt == 0 && G->lo <= G->hi) {
+        const int in_row = sig >= G->lo && sig <= G->hi;
+        const int in_col = S->mode == ORC_MODE_ONLINE && sig > G->hi && csig >= G->lo &&
+                           csig <= G->hi;
+        skip = in_row || in_col;
+    }
+    if (G->info) {
+        orc_fault_info* I = &G->info[f];
+        if (I->applied == 0 && !I->skipped) {
+            I->before = before;
+            I->after = after;
+            I->row_sum = row;
+            I->col_sum = col;
+            I->signal = sig;
+            I->col_signal = csig;
+        }
+        if (skip)
+            I->skipped = 1;
+        else
+            I->applied++;
+    }
+    return !skip;
+}
+
 /* Section 5.1 fault model: flip one bit of the value the sweep stores, after the update
  * (kind STORE, applied to uout), or of the sweep's input before it is read (kind MEMORY,
  * applied to uin). */
@@ -495,6 +600,7 @@ static void inject(run_state* S, void* uout, int64_t sweep, int attempt, int kin
     for (int64_t f = 0; f < S->nfaults; f++) {
         const orc_fault* F = &S->faults[f];
         if (F->sweep != sweep || F->attempt != attempt || F->kind != kind) continue;
+        if (S->guard && !guard_flip(S, f, uout, sweep, attempt)) continue;
         const int64_t i = idx(p, F->x, F->y, F->z);
         if (p->dtype == ORC_F32) {
             uint32_t v;
@@ -928,7 +1034,8 @@ static void online_check_tiles(run_state* S, int64_t sweep, const void* uin, voi
 int orc_run(const orc_problem* p, const void* C, int mode, int period, double eps,
             int auto_correct, int flags, int tile_x, void* u_a, void* u_b, int64_t nsweeps,
             const orc_fault* faults, int64_t nfaults,
-            orc_event* events, int64_t max_events, orc_counters* counters)
+            orc_event* events, int64_t max_events, orc_counters* counters,
+            const orc_guard* guard)
 {
     int rc = orc_validate(p);
     if (rc) return rc;
@@ -966,6 +1073,9 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
     S.input_check = (flags & ORC_INPUT_CHECK) && mode != ORC_MODE_NONE;
     S.recompute = (flags & ORC_RECOMPUTE) != 0;
     S.tile = tile_x;
+    S.mode = mode;
+    S.guard = guard;
+    if (guard && guard->info) memset(guard->info, 0, sizeof(orc_fault_info) * (size_t)nfaults);
     S.faults = faults;
     S.nfaults = nfaults;
     S.ev = events;
@@ -1052,6 +1162,7 @@ int orc_run(const orc_problem* p, const void* C, int mode, int period, double ep
             const int64_t k = (nsweeps - t0 < period) ? nsweeps - t0 : period;
             int attempt = 0;
             int halt = 0;
+            S.win_end = t0 + k - 1;
             for (;;) {
                 uin = u_a;
                 uout = u_b;

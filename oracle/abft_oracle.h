@@ -163,10 +163,43 @@ enum {
                             sweep's input (stencil locality) instead of Eq.(10) */
 };
 
+/* What a flip of the plan did, recorded when it was applied (one record per plan entry, in
+ * plan order).  The sums are of the clean row and column through the point (Eq.(3), Eq.(2))
+ * just before the flip, in the grid it lands in (the stored output for STORE, the input for
+ * MEMORY).  The relative signal is the change the check that sees the flip measures against
+ * the row checksum (Section 3.4): online |after - before| / |row_sum|; offline the change of
+ * the row sums carried from the flip's sweep to the window's last sweep by the linear part of
+ * Theorem 1 (the checksum plane stepped with the stencil weights, no constant term, no
+ * boundary terms), largest over the rows, over |row_sum|.  The boundary terms of a change
+ * vanish under the periodic rule and cancel under the clamp rule when the two x weights of
+ * each (dy, dz) pair are equal, so the carried change is then exact; under the constant rule
+ * it leaves out what the change loses through the row ends, which only a change within
+ * (steps x radius) points of an x edge has.  A non-finite change gives an infinite signal. */
+typedef struct {
+    int32_t applied;   /* times the flip was applied */
+    int32_t skipped;   /* 1 when the guard band (orc_guard) left it out */
+    double before, after;
+    double row_sum, col_sum;
+    double signal;     /* row signal as above */
+    double col_signal; /* |after - before| / |col_sum| */
+} orc_fault_info;
+
+/* Test harness option of orc_run.  Where a flip's relative signal lies close to the
+ * threshold, two correct implementations may decide differently under rounding (the direct
+ * and predicted checksums each carry rounding noise).  A STORE flip on attempt 0 whose row
+ * signal lies in [lo, hi], or (online) whose row signal is above hi and column signal in
+ * [lo, hi], is then left out (not applied, skipped = 1), so that the run equals the run of
+ * the plan without it.  lo > hi leaves every flip in.  info may be NULL. */
+typedef struct {
+    double lo, hi;
+    orc_fault_info* info;
+} orc_guard;
+
 int orc_run(const orc_problem* p, const void* C, int mode, int period, double eps,
             int auto_correct, int flags, int tile_x, void* u_a, void* u_b, int64_t nsweeps,
             const orc_fault* faults, int64_t nfaults,
-            orc_event* events, int64_t max_events, orc_counters* counters);
+            orc_event* events, int64_t max_events, orc_counters* counters,
+            const orc_guard* guard /* may be NULL: every flip applied, nothing recorded */);
 
 /* Thread control for the OpenMP loops (results do not depend on it). */
 void orc_set_threads(int n);
