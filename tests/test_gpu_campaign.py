@@ -10,22 +10,34 @@ located at their exact site and corrected.  It is at most 2^(b-15)/40960, below 
 b <= 5: bits 0..5 are never seen.  Bits 6..11 depend on the value at the time of the flip.
 """
 import collections
-import json
-import os
-import tempfile
 
 import numpy as np
 import pytest
 
 import workloads as W
-from tests.gpu_util import assert_grid_close, event_keys, run_gpu, run_oracle, say
+from tests.gpu_util import (assert_grid_close, error_vs, event_keys, fp64_reference,
+                            guarded_oracle, run_gpu, say, write_summary)
 
 pytestmark = pytest.mark.gpu
 
 B_MIN_GUARANTEED = 12
 B_MAX_NEVER = 5
-# where the run writes its result summary (JSON): $ABFT_TEST_OUT, else the system temp folder
-OUT = os.environ.get("ABFT_TEST_OUT") or os.path.join(tempfile.gettempdir(), "abft_test_out")
+
+
+@pytest.fixture(scope="module")
+def c3_oracle():
+    """The oracle's runs of the whole campaign, made once for both accumulations: the 1000
+    seeded flips with those in the guard band [eps/4, 4 eps] left out, and the fault-free
+    run with fp64 storage (the reference the fp32 error is stated against)."""
+    nz, ny, nx = W.C3.shape
+    u0, C = W.thermal_grid(nx, ny, nz, np.float32)
+    plan = W.c3_campaign()
+    o, oev, ocnt, kept, info = guarded_oracle(u0, W.THERMAL_TAPS, W.C3.nsweeps, plan, W.C3.eps,
+                                              C=C, chunk=100, name="C3 campaign")
+    ref = fp64_reference(u0, W.THERMAL_TAPS, W.C3.nsweeps, C=C, chunk=250,
+                         name="C3 fp64 reference")
+    return {"u0": u0, "C": C, "plan": plan, "grid": o, "events": oev, "counters": ocnt,
+            "kept": kept, "info": info, "ref64": ref}
 
 
 def _summary(plan, ev):
@@ -48,21 +60,20 @@ def _summary(plan, ev):
 
 
 @pytest.mark.parametrize("csum", ["f64", "f32comp"])
-def test_c3_campaign(csum):
-    nz, ny, nx = W.C3.shape
-    u0, C = W.thermal_grid(nx, ny, nz, np.float32)
-    plan = W.c3_campaign()
+def test_c3_campaign(csum, c3_oracle):
+    """The whole 1000-sweep campaign twice: every seeded flip (the smallest detectable bit
+    and the per-bit rates), and the flips outside the guard band against the oracle's run
+    (events equal, grid within 1e-5), with the error against the fp64-storage oracle."""
+    R = c3_oracle
+    u0, C, plan = R["u0"], R["C"], R["plan"]
     say("C3 campaign", csum)
     g, ev, rep, shape = run_gpu(u0, W.THERMAL_TAPS, W.C3.nsweeps, C=C, eps=W.C3.eps, csum=csum,
                                 plan=plan, max_events=1 << 16)
     s = _summary(plan, ev)
     s.update({"csum": csum, "corrected": rep["corrected"], "rows_flagged": rep["rows_flagged"],
               "checksum_faults": rep["checksum_faults"], "uncorrectable": rep["uncorrectable"],
-              "max_noise": rep["max_noise"], "launch_shape": shape})
-    os.makedirs(OUT, exist_ok=True)
-    with open(os.path.join(OUT, f"campaign_c3_{csum}.json"), "w") as f:
-        json.dump(s, f, indent=1)
-    print(json.dumps(s))
+              "max_noise": rep["max_noise"], "launch_shape": shape,
+              "vs_fp64_oracle_all_flips": error_vs(g, R["ref64"])})
     assert rep["events_total"] < (1 << 16)
     assert s["false_positive_rows"] == 0 and s["wrong_sites_corrected"] == 0
     assert rep["uncorrectable"] == 0
@@ -72,31 +83,35 @@ def test_c3_campaign(csum):
         if b <= B_MAX_NEVER:
             assert flagged == 0, (b, flagged)
 
+    kept, info = R["kept"], R["info"]
+    say("C3 campaign oracle parity", csum, len(kept), "of", len(plan))
+    g2, ev2, rep2, _ = run_gpu(u0, W.THERMAL_TAPS, W.C3.nsweeps, C=C, eps=W.C3.eps, csum=csum,
+                               plan=kept, max_events=1 << 16)
+    assert event_keys(ev2) == event_keys(R["events"])
+    for k in ("rows_flagged", "corrected", "checksum_faults", "uncorrectable"):
+        assert rep2[k] == R["counters"][k], k
+    assert_grid_close(g2, R["grid"], 1e-5, f"C3 campaign {csum}")
+    left = plan[info["skipped"] == 1]
+    s.update({"oracle_parity_flips": int(len(kept)),
+              "guard_band_left_out": {int(b): int(np.sum(left["bit"] == b))
+                                      for b in np.unique(left["bit"])},
+              "vs_fp64_oracle_parity_run": error_vs(g2, R["ref64"]),
+              "oracle_vs_fp64_oracle": error_vs(R["grid"], R["ref64"])})
+    write_summary(f"campaign_c3_{csum}.json", s)
+
 
 @pytest.mark.parametrize("csum", ["f64", "f32comp"])
-def test_c3_false_positives(csum):
+def test_c3_false_positives(csum, c3_oracle):
+    """A fault-free 1000-sweep run: no row flagged in 32.8 million row tests, and the error of
+    the fp32 grid against the fp64-storage oracle run stated."""
     nz, ny, nx = W.C3.shape
-    u0, C = W.thermal_grid(nx, ny, nz, np.float32)
+    u0, C = c3_oracle["u0"], c3_oracle["C"]
     say("C3 fault-free", csum)
-    _, ev, rep, _ = run_gpu(u0, W.THERMAL_TAPS, W.C3.nsweeps, C=C, eps=W.C3.eps, csum=csum)
-    print(json.dumps({"csum": csum, "row_tests": nz * ny * W.C3.nsweeps,
-                      "false_positives": rep["rows_flagged"], "max_noise": rep["max_noise"]}))
+    g, ev, rep, _ = run_gpu(u0, W.THERMAL_TAPS, W.C3.nsweeps, C=C, eps=W.C3.eps, csum=csum)
+    write_summary(f"c3_fault_free_{csum}.json", {
+        "csum": csum, "row_tests": nz * ny * W.C3.nsweeps, "false_positives": rep["rows_flagged"],
+        "max_noise": rep["max_noise"], "vs_fp64_oracle": error_vs(g, c3_oracle["ref64"])})
     assert rep["rows_flagged"] == 0 and len(ev) == 0
     # the noise floor of an fp32 grid: a smooth row rounds alike, up to half an ulp of values
     # near 80 (2^-18 / 80 / 2 = 4.8e-8 relative) plus the earlier roundings of the chain
     assert rep["max_noise"] < 0.6 * W.C3.eps
-
-
-def test_c3_oracle_parity_first_60():
-    """The campaign's first 60 sweeps at full size against the oracle (flips whose bit lies in
-    the value-dependent band 6..13 left out)."""
-    nz, ny, nx = W.C3.shape
-    u0, C = W.thermal_grid(nx, ny, nz, np.float32)
-    plan = W.c3_campaign()
-    plan = plan[(plan["sweep"] < 60) & ((plan["bit"] < 6) | (plan["bit"] > 13))]
-    say("C3 oracle parity", len(plan))
-    g, gev, grep, _ = run_gpu(u0, W.THERMAL_TAPS, 60, C=C, eps=W.C3.eps, plan=plan)
-    o, oev, ocnt = run_oracle(u0, W.THERMAL_TAPS, 60, C=C, eps=W.C3.eps, plan=plan)
-    assert event_keys(gev) == event_keys(oev)
-    assert grep["corrected"] == ocnt["corrected"] > 0
-    assert_grid_close(g, o, 1e-5, "C3 first 60")

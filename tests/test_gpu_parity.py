@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.gpu_util import (assert_grid_close, corrected_values, event_keys, guard_band_plan,
+from tests.gpu_util import (assert_grid_close, corrected_values, event_keys, guarded_oracle,
                             run_gpu, run_oracle, say)
 
 pytestmark = pytest.mark.gpu
@@ -122,23 +122,25 @@ def test_fp32_thermal_online(csum):
 @pytest.mark.parametrize("mode", ["online", "offline"])
 @pytest.mark.parametrize("nflips", [0, 1, 5, 10])
 def test_c2(mode, nflips):
+    """Every seeded flip runs unless the oracle's own run puts its relative signal inside the
+    guard band [eps/4, 4 eps] (there both sides may decide either way under rounding)."""
     u0, C = W.C2.inputs()
-    plan = guard_band_plan(W.c2_plan(nflips), 19, 24)
     eps = W.C2.eps
-    say("C2", mode, nflips, plan.tolist())
+    full = W.c2_plan(nflips)
+    o, oev, ocnt, plan, info = guarded_oracle(u0, W.THERMAL_TAPS, W.C2.nsweeps, full, eps, C=C,
+                                              mode=mode, period=10)
+    say("C2", mode, nflips, plan.tolist(), "left out:", int(info["skipped"].sum()))
     g, gev, grep, _ = run_gpu(u0, W.THERMAL_TAPS, W.C2.nsweeps, C=C, eps=eps, mode=mode,
-                              period=10, plan=plan)
-    o, oev, ocnt = run_oracle(u0, W.THERMAL_TAPS, W.C2.nsweeps, C=C, eps=eps, mode=mode,
                               period=10, plan=plan)
     assert event_keys(gev) == event_keys(oev)
     for k in ("rows_flagged", "corrected", "windows_flagged", "rollbacks", "persistent"):
         assert grep[k] == ocnt[k], k
     assert_grid_close(g, o, 1e-12, f"C2 {mode} {nflips}")
-    if mode == "offline":
+    kept = info[info["skipped"] == 0]
+    if mode == "offline" and np.all(kept["signal"] > 4 * eps):
+        # every flip was seen, so the rollbacks erase all of them bitwise
         clean, _, _, _ = run_gpu(u0, W.THERMAL_TAPS, W.C2.nsweeps, C=C, mode="none")
-        undetectable = plan[plan["bit"] <= 18] if len(plan) else plan
-        if len(undetectable) == 0:
-            assert np.array_equal(g, clean)  # rollback erases every detected flip bitwise
+        assert np.array_equal(g, clean)
 
 
 # ---------------------------------------------------------------------------------------
