@@ -227,14 +227,24 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // ------------------------------------------------------------------------------------------
 // Boundary rule on one coordinate: index inside [0, n), or -1 for a constant ghost.
-// Radius-1 stencils only ever step a few points outside the grid, so c lies in [-n, 2n) and
-// the periodic wrap needs no division.
+// Stencils of radius at most 2 only step up to two points outside the grid, so c lies in
+// [-2n, 3n) for every n >= 1 (an axis of length 1 included) and the periodic wrap takes at
+// most two steps of n, with no division.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ int map_coord(int c, int n, int bc)
+__host__ __device__ __forceinline__ int map_coord(int c, int n, int bc)
 {
     if (c >= 0 && c < n) return c;
     if (bc == ABFT_BC_CLAMP) return c < 0 ? 0 : n - 1;
-    if (bc == ABFT_BC_PERIODIC) return c < 0 ? c + n : c - n;
+    if (bc == ABFT_BC_PERIODIC) {
+        if (c < 0) {
+            c += n;
+            if (c < 0) c += n;
+        } else {
+            c -= n;
+            if (c >= n) c -= n;
+        }
+        return c;
+    }
     return -1;
 }
 

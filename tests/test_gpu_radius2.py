@@ -211,3 +211,24 @@ def test_radius2_wide_blocks_forced(mode, input_check, dtype, tmp_path):
         assert grep["rollbacks"] == 3 and ocnt["rollbacks"] == 3, (grep, ocnt)
     assert event_keys(gev) == event_keys(oev)
     assert_grid_close(g, o, tol, f"radius 2 wide blocks {dtype} {mode}")
+
+
+@pytest.mark.parametrize("shape,drop_axis", [((1, 48, 96), 2), ((6, 1, 64), 1)])
+@pytest.mark.parametrize("bc", ["periodic", "clamp", "constant"])
+def test_radius2_axis_of_length_one(shape, drop_axis, bc):
+    """A radius-2 star on a grid with an axis of length 1 that carries no distance-2 tap (a 2D
+    grid, or a single row per layer): the plane and halo-row coordinates two steps outside
+    that axis map back onto it under every boundary rule.  Online, with flips, against the
+    oracle."""
+    taps = tuple(t for t in ASYM2 if abs((t[0], t[1], t[2])[drop_axis]) < 2)
+    nz, ny, nx = shape
+    rng = np.random.default_rng(nz * 100 + ny)
+    u0 = 50 + 10 * rng.random(shape)
+    C = rng.random(shape)
+    plan = W.make_plan([(2, nz - 1, ny - 1, nx - 1, 60), (5, 0, 0, 1, 57)])
+    say("radius 2 axis of length 1", shape, bc)
+    g, gev, grep, _ = run_gpu(u0, taps, 8, C=C, eps=1e-12, bc=bc, bc_value=2.5, plan=plan)
+    o, oev, ocnt = run_oracle(u0, taps, 8, C=C, eps=1e-12, bc=bc, bc_value=2.5, plan=plan)
+    assert event_keys(gev) == event_keys(oev)
+    assert grep["corrected"] == ocnt["corrected"] == 2
+    assert_grid_close(g, o, 1e-12, f"radius 2 {shape} {bc}")
