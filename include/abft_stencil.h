@@ -240,7 +240,12 @@ abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft
 
 /* Enqueues nsweeps sweeps on the context's stream and returns without waiting for them
  * (offline mode without auto-correct is the exception: it waits at each window end and stops
- * after the first flagged window).  nsweeps >= 0.  ABFT_E_STATE while a detection awaits
+ * after the first flagged window).  What a sweep does by mode: NONE, Eq.(1) alone; ONLINE,
+ * Section 3: Eq.(1) with the row checksums of Eq.(3) in the same pass, their prediction by
+ * Theorem 1 (Eq.(5)) and the test of Section 3.4, then with auto-correct the location and
+ * correction of Section 3.5 (Eq.(10)); OFFLINE, Section 4: sweeps without checks, and at each
+ * window end the interpolation applied `period` times, one comparison, and with auto-correct
+ * the rollback to the checkpoint and the recompute of the window.  nsweeps >= 0.  ABFT_E_STATE while a detection awaits
  * abft_stencil_correct.  Offline with auto-correct, every window end enqueues the check and a
  * rollback recompute that runs only when the check flagged a mismatch: one launch of at most
  * one block per free block slot of the device, whose blocks wait for each other between the
@@ -248,23 +253,30 @@ abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft
 abft_status abft_stencil_step(abft_ctx* ctx, int64_t nsweeps);
 
 /* Enqueues nsweeps sweeps as one captured HIP graph (built on first use for a given nsweeps,
- * then replayed).  Same semantics as abft_stencil_step; the fault plan is fixed when the
+ * then replayed).  Same semantics as abft_stencil_step (Section 3 per sweep: Eq.(1), Eq.(3),
+ * Theorem 1, the test of Section 3.4, and Section 3.5's correction with auto-correct); the fault plan is fixed when the
  * graph is built.  Not available in offline mode without auto-correct. */
 abft_status abft_stencil_step_graph(abft_ctx* ctx, int64_t nsweeps);
 
-/* Waits for the stream and reports.  In offline mode a partial window is checked first (the
- * "after completion" detection), which also closes it.  `out` may be NULL.  Returns
+/* Waits for the stream and reports the detections of Section 3.4 (online: flagged rows,
+ * located and corrected points; offline: flagged windows, rollbacks).  In offline mode a
+ * partial window is checked first (Section 4's detection "after completion" of the run),
+ * which also closes it.  `out` may be NULL.  Returns
  * ABFT_E_HIP if a rollback recompute gave up waiting for its blocks (about three seconds at
  * one barrier): the recomputed window is then not to be trusted; the barrier is reset. */
 abft_status abft_stencil_check(abft_ctx* ctx, abft_report* out);
 
 /* Acts on pending detections: online, locates and corrects the flagged rows of the last
- * sweep; offline, rolls back to the checkpoint, recomputes the window and checks it again.
+ * sweep (Section 3.5: column checksums of the flagged layer, Eq.(2), their prediction,
+ * Eq.(4), the intersection, and the value of Eq.(10)); offline, rolls back to the checkpoint,
+ * recomputes the window and checks it again (Section 4).
  * Returns ABFT_E_UNCORRECTABLE when a point cannot be located or repaired (the grid is left
  * as it is), ABFT_OK otherwise (also when nothing is pending).  `inout` may be NULL. */
 abft_status abft_stencil_correct(abft_ctx* ctx, abft_report* inout);
 
-/* The device buffer holding the current grid (buffers rotate) and the sweep count.  For a
+/* The device buffer holding the current grid u^t of Eq.(1) (buffers rotate: online and plain
+ * runs alternate u0 and u1, offline windows rotate three buffers so that the checkpoint of
+ * Section 4 is never copied) and the sweep count t.  For a
  * batch context `grid` selects the grid; it must be 0 otherwise. */
 abft_status abft_stencil_current(abft_ctx* ctx, int32_t grid, void** dev_ptr, int64_t* sweep);
 

@@ -962,30 +962,10 @@ abft_status batch_autotune(abft_ctx* c)
 
 }  // namespace
 
-// ==========================================================================================
-extern "C" {
+namespace {
 
-const char* abft_strerror(abft_status s)
-{
-    switch (s) {
-    case ABFT_OK: return "ok";
-    case ABFT_E_INVAL: return "invalid argument";
-    case ABFT_E_UNSUPPORTED: return "not supported by the GPU kernels";
-    case ABFT_E_NOMEM: return "out of memory";
-    case ABFT_E_HIP: return "HIP runtime error";
-    case ABFT_E_STATE: return "call not allowed in the current state";
-    case ABFT_E_UNCORRECTABLE: return "detected corruption could not be corrected";
-    }
-    return "unknown status";
-}
-
-const char* abft_last_error(const abft_ctx* ctx)
-{
-    return ctx ? ctx->err.c_str() : g_init_error.c_str();
-}
-
-abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void* hip_stream,
-                              abft_ctx** out)
+abft_status init_impl(const abft_problem* p, const abft_options* o, void* hip_stream,
+                      abft_ctx** out)
 {
     g_init_error.clear();
     if (!out) return fail(nullptr, ABFT_E_INVAL, "out is NULL");
@@ -996,145 +976,152 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
     if (s) return s;
 
     abft_ctx* c = new abft_ctx();
-    c->nx = p->nx;
-    c->ny = p->ny;
-    c->nz = p->nz;
-    c->dtype = p->dtype;
-    c->bc = p->bc;
-    c->C = p->cterm;
-    c->cs = round_to(p->dtype, p->cterm_scalar);
-    c->u[0] = p->u0;
-    c->u[1] = p->u1;
-    c->mode = o->mode;
-    c->period = o->mode == ABFT_MODE_OFFLINE ? o->period : 1;
-    c->eps = o->threshold;
-    c->csum = o->csum == ABFT_CSUM_F32_COMP ? CS_F32C : CS_F64;
-    c->auto_correct = o->auto_correct ? 1 : 0;
-    c->recompute = o->correction == ABFT_CORRECT_RECOMPUTE ? 1 : 0;
-    c->input_check = (o->input_check && o->mode != ABFT_MODE_NONE) ? 1 : 0;
-    c->tile_x = o->tile_x;
-    c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
-    if (o->tuning_cache) c->cache_path = o->tuning_cache;
-    c->stream = static_cast<hipStream_t>(hip_stream);
+    try {
+        c->nx = p->nx;
+        c->ny = p->ny;
+        c->nz = p->nz;
+        c->dtype = p->dtype;
+        c->bc = p->bc;
+        c->C = p->cterm;
+        c->cs = round_to(p->dtype, p->cterm_scalar);
+        c->u[0] = p->u0;
+        c->u[1] = p->u1;
+        c->mode = o->mode;
+        c->period = o->mode == ABFT_MODE_OFFLINE ? o->period : 1;
+        c->eps = o->threshold;
+        c->csum = o->csum == ABFT_CSUM_F32_COMP ? CS_F32C : CS_F64;
+        c->auto_correct = o->auto_correct ? 1 : 0;
+        c->recompute = o->correction == ABFT_CORRECT_RECOMPUTE ? 1 : 0;
+        c->input_check = (o->input_check && o->mode != ABFT_MODE_NONE) ? 1 : 0;
+        c->tile_x = o->tile_x;
+        c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
+        if (o->tuning_cache) c->cache_path = o->tuning_cache;
+        c->stream = static_cast<hipStream_t>(hip_stream);
 
-    auto bail = [&](abft_status st) {
-        g_init_error = c->err;
+        auto bail = [&](abft_status st) {
+            g_init_error = c->err;
+            free_all(c);
+            delete c;
+            return st;
+        };
+        {
+            int dev = 0;
+            hipDeviceProp_t prop;
+            if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+                return bail(fail(c, ABFT_E_HIP, "device query failed"));
+            c->num_cus = prop.multiProcessorCount;
+        }
+
+        s = map_taps(c, p);
+        if (s) return bail(s);
+        if (c->tile_x != 0) {
+            // tiles are the 16 lanes x 16 bytes one lane group of the sweep holds of a row
+            const int tt = 16 * (16 / (int)esize(c->dtype));
+            if (c->tile_x != tt || c->nx % tt || c->st.box || c->input_check ||
+                c->mode == ABFT_MODE_OFFLINE || c->csum != CS_F64)
+                return bail(fail(c, ABFT_E_UNSUPPORTED, "tile-local checksums: online star "
+                                                        "stencils, T = 64 (fp32) or 32 (fp64), "
+                                                        "T dividing nx, fp64 accumulation"));
+        }
+        SweepShape shape{};
+        if (c->st.rad == 2) {
+            // the shifted-line sums of Theorem 1 (and the periodic wrap) need every axis that
+            // carries a distance-2 tap to be at least 2 long
+            for (int ax = 0; ax < 3; ++ax) {
+                const int n = ax == 0 ? c->nx : ax == 1 ? c->ny : c->nz;
+                const uint32_t m2 = (1u << w_slot(ax, 2, -1)) | (1u << w_slot(ax, 2, 1));
+                if ((c->st.mask & m2) && n < 2)
+                    return bail(fail(c, ABFT_E_UNSUPPORTED, "distance-2 taps along an axis of "
+                                                            "length 1"));
+            }
+        }
+        const bool cached = cache_lookup(c, &shape);
+        shape.rad = c->st.rad;
+        shape.box = c->st.box;
+        if (!cached || !sweep_shape_supported(c->dtype, shape)) {
+            if (!default_shape(c->dtype, c->nx, c->ny, c->nz, c->st.rad, c->st.box, &shape))
+                return bail(fail(c, ABFT_E_UNSUPPORTED, "row length beyond the GPU kernels"));
+        }
+        s = apply_shape(c, shape);
+        if (s) return bail(s);
+        if (fixup_lds_bytes(c->nx, c->st.box) > (c->st.box ? kSweepLdsLimit : kLdsLimit) ||
+            c->nx > 4 * kFixBlock)
+            return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
+        if (c->mode == ABFT_MODE_OFFLINE) {
+            check_shape(c, std::min(c->period, kCheckChunk / c->st.rad) * c->st.rad);
+            if ((int64_t)c->ck.ry * c->ck.rz > (int64_t)kCheckCells * kCheckBlock)
+                return bail(fail(c, ABFT_E_UNSUPPORTED, "offline period too long for this grid"));
+        }
+
+        // checksum entries: one per row, or one per tile of each row
+        const size_t nrows = (size_t)c->nz * c->ny * (c->tile_x ? c->nx / c->tile_x : 1),
+                     ncols = (size_t)c->nz * c->nx;
+        const size_t gbytes = (size_t)c->nx * c->ny * c->nz * esize(c->dtype);
+        if ((s = dalloc(c, &c->B[0], nrows * 8)) || (s = dalloc(c, &c->B[1], nrows * 8)) ||
+            (s = dalloc(c, &c->cB, nrows * 8)) || (s = dalloc(c, &c->cA, ncols * 8)) ||
+            (s = dalloc(c, &c->slot[0], sizeof(FlagSlot))) ||
+            (s = dalloc(c, &c->slot[1], sizeof(FlagSlot))) ||
+            (s = dalloc(c, &c->cnt, sizeof(Counters))) ||
+            (s = dalloc(c, &c->ev, (size_t)c->ev_cap * sizeof(abft_event))) ||
+            (s = dalloc(c, &c->win, 4 * sizeof(uint32_t))) ||
+            (s = dalloc(c, &c->ticket, 4 * sizeof(uint32_t))) ||
+            (s = dalloc(c, &c->tbase, sizeof(int64_t))))
+            return bail(s);
+        if (c->input_check &&
+            ((s = dalloc(c, &c->W[0], nrows * 8)) || (s = dalloc(c, &c->W[1], nrows * 8))))
+            return bail(s);
+        if (c->tile_x && (s = dalloc(c, &c->Et, nrows * 8))) return bail(s);
+        if (c->mode == ABFT_MODE_OFFLINE) {
+            if (p->u2 != nullptr) {
+                if (p->u2 == p->u0 || p->u2 == p->u1)
+                    return bail(fail(c, ABFT_E_INVAL, "u2 must differ from u0 and u1"));
+                c->u[2] = p->u2;
+            } else {
+                if ((s = dalloc(c, &c->u[2], gbytes))) return bail(s);
+                c->own_u2 = true;
+            }
+            if (need_boundary_terms(c) && (s = dalloc(c, &c->E, (size_t)c->period * nrows * 8)))
+                return bail(s);
+            if (c->period > kCheckChunk / c->st.rad &&
+                ((s = dalloc(c, &c->Btmp[0], nrows * 8)) || (s = dalloc(c, &c->Btmp[1], nrows * 8))))
+                return bail(s);
+        }
+
+        hipError_t e;
+#define INIT_CHK(expr)                                      \
+        if ((e = (expr)) != hipSuccess) {                       \
+            hip_fail(c, e, #expr);                              \
+            return bail(ABFT_E_HIP);                            \
+        }
+        INIT_CHK(launch_fill_u32(reinterpret_cast<uint32_t*>(c->cnt), 0u,
+                                 sizeof(Counters) / 4, c->stream));
+        INIT_CHK(launch_fill_u32(&c->slot[0]->count, 0u, 2, c->stream));
+        INIT_CHK(launch_fill_u32(&c->slot[1]->count, 0u, 2, c->stream));
+        INIT_CHK(launch_fill_u32(c->win, 0u, 4, c->stream));
+        INIT_CHK(launch_fill_u32(c->ticket, 0u, 4, c->stream));
+        INIT_CHK(launch_set_i64(c->tbase, 0, c->stream));
+        // Theorem 1's constant-term checksums and the checksums of u^0
+        // a tile is a contiguous run of tile_x points, so tile sums are row sums of that length
+        const int line = c->tile_x ? c->tile_x : c->nx;
+        INIT_CHK(launch_row_sums(c->dtype, c->C, c->cs, line, (int64_t)nrows, c->cB, c->stream));
+        INIT_CHK(launch_col_sums(c->dtype, c->C, c->cs, c->nx, c->ny, c->nz, c->cA, c->stream));
+        INIT_CHK(launch_row_sums(c->dtype, c->u[0], 0.0, line, (int64_t)nrows, c->B[0], c->stream));
+        if (c->W[0] != nullptr)
+            INIT_CHK(launch_weighted_row_sums(c->dtype, c->u[0], c->nx, (int64_t)nrows, c->W[0],
+                                              c->stream));
+        INIT_CHK(hipStreamSynchronize(c->stream));
+#undef INIT_CHK
+        *out = c;
+        return ABFT_OK;
+    } catch (...) {
+        // a host exception (allocation) after the context was made: nothing leaks
         free_all(c);
         delete c;
-        return st;
-    };
-    {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-            return bail(fail(c, ABFT_E_HIP, "device query failed"));
-        c->num_cus = prop.multiProcessorCount;
+        throw;
     }
-
-    s = map_taps(c, p);
-    if (s) return bail(s);
-    if (c->tile_x != 0) {
-        // tiles are the 16 lanes x 16 bytes one lane group of the sweep holds of a row
-        const int tt = 16 * (16 / (int)esize(c->dtype));
-        if (c->tile_x != tt || c->nx % tt || c->st.box || c->input_check ||
-            c->mode == ABFT_MODE_OFFLINE || c->csum != CS_F64)
-            return bail(fail(c, ABFT_E_UNSUPPORTED, "tile-local checksums: online star "
-                                                    "stencils, T = 64 (fp32) or 32 (fp64), "
-                                                    "T dividing nx, fp64 accumulation"));
-    }
-    SweepShape shape{};
-    if (c->st.rad == 2) {
-        // the shifted-line sums of Theorem 1 (and the periodic wrap) need every axis that
-        // carries a distance-2 tap to be at least 2 long
-        for (int ax = 0; ax < 3; ++ax) {
-            const int n = ax == 0 ? c->nx : ax == 1 ? c->ny : c->nz;
-            const uint32_t m2 = (1u << w_slot(ax, 2, -1)) | (1u << w_slot(ax, 2, 1));
-            if ((c->st.mask & m2) && n < 2)
-                return bail(fail(c, ABFT_E_UNSUPPORTED, "distance-2 taps along an axis of "
-                                                        "length 1"));
-        }
-    }
-    const bool cached = cache_lookup(c, &shape);
-    shape.rad = c->st.rad;
-    shape.box = c->st.box;
-    if (!cached || !sweep_shape_supported(c->dtype, shape)) {
-        if (!default_shape(c->dtype, c->nx, c->ny, c->nz, c->st.rad, c->st.box, &shape))
-            return bail(fail(c, ABFT_E_UNSUPPORTED, "row length beyond the GPU kernels"));
-    }
-    s = apply_shape(c, shape);
-    if (s) return bail(s);
-    if (fixup_lds_bytes(c->nx, c->st.box) > (c->st.box ? kSweepLdsLimit : kLdsLimit) ||
-        c->nx > 4 * kFixBlock)
-        return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
-    if (c->mode == ABFT_MODE_OFFLINE) {
-        check_shape(c, std::min(c->period, kCheckChunk / c->st.rad) * c->st.rad);
-        if ((int64_t)c->ck.ry * c->ck.rz > (int64_t)kCheckCells * kCheckBlock)
-            return bail(fail(c, ABFT_E_UNSUPPORTED, "offline period too long for this grid"));
-    }
-
-    // checksum entries: one per row, or one per tile of each row
-    const size_t nrows = (size_t)c->nz * c->ny * (c->tile_x ? c->nx / c->tile_x : 1),
-                 ncols = (size_t)c->nz * c->nx;
-    const size_t gbytes = (size_t)c->nx * c->ny * c->nz * esize(c->dtype);
-    if ((s = dalloc(c, &c->B[0], nrows * 8)) || (s = dalloc(c, &c->B[1], nrows * 8)) ||
-        (s = dalloc(c, &c->cB, nrows * 8)) || (s = dalloc(c, &c->cA, ncols * 8)) ||
-        (s = dalloc(c, &c->slot[0], sizeof(FlagSlot))) ||
-        (s = dalloc(c, &c->slot[1], sizeof(FlagSlot))) ||
-        (s = dalloc(c, &c->cnt, sizeof(Counters))) ||
-        (s = dalloc(c, &c->ev, (size_t)c->ev_cap * sizeof(abft_event))) ||
-        (s = dalloc(c, &c->win, 4 * sizeof(uint32_t))) ||
-        (s = dalloc(c, &c->ticket, 4 * sizeof(uint32_t))) ||
-        (s = dalloc(c, &c->tbase, sizeof(int64_t))))
-        return bail(s);
-    if (c->input_check &&
-        ((s = dalloc(c, &c->W[0], nrows * 8)) || (s = dalloc(c, &c->W[1], nrows * 8))))
-        return bail(s);
-    if (c->tile_x && (s = dalloc(c, &c->Et, nrows * 8))) return bail(s);
-    if (c->mode == ABFT_MODE_OFFLINE) {
-        if (p->u2 != nullptr) {
-            if (p->u2 == p->u0 || p->u2 == p->u1)
-                return bail(fail(c, ABFT_E_INVAL, "u2 must differ from u0 and u1"));
-            c->u[2] = p->u2;
-        } else {
-            if ((s = dalloc(c, &c->u[2], gbytes))) return bail(s);
-            c->own_u2 = true;
-        }
-        if (need_boundary_terms(c) && (s = dalloc(c, &c->E, (size_t)c->period * nrows * 8)))
-            return bail(s);
-        if (c->period > kCheckChunk / c->st.rad &&
-            ((s = dalloc(c, &c->Btmp[0], nrows * 8)) || (s = dalloc(c, &c->Btmp[1], nrows * 8))))
-            return bail(s);
-    }
-
-    hipError_t e;
-#define INIT_CHK(expr)                                      \
-    if ((e = (expr)) != hipSuccess) {                       \
-        hip_fail(c, e, #expr);                              \
-        return bail(ABFT_E_HIP);                            \
-    }
-    INIT_CHK(launch_fill_u32(reinterpret_cast<uint32_t*>(c->cnt), 0u,
-                             sizeof(Counters) / 4, c->stream));
-    INIT_CHK(launch_fill_u32(&c->slot[0]->count, 0u, 2, c->stream));
-    INIT_CHK(launch_fill_u32(&c->slot[1]->count, 0u, 2, c->stream));
-    INIT_CHK(launch_fill_u32(c->win, 0u, 4, c->stream));
-    INIT_CHK(launch_fill_u32(c->ticket, 0u, 4, c->stream));
-    INIT_CHK(launch_set_i64(c->tbase, 0, c->stream));
-    // Theorem 1's constant-term checksums and the checksums of u^0
-    // a tile is a contiguous run of tile_x points, so tile sums are row sums of that length
-    const int line = c->tile_x ? c->tile_x : c->nx;
-    INIT_CHK(launch_row_sums(c->dtype, c->C, c->cs, line, (int64_t)nrows, c->cB, c->stream));
-    INIT_CHK(launch_col_sums(c->dtype, c->C, c->cs, c->nx, c->ny, c->nz, c->cA, c->stream));
-    INIT_CHK(launch_row_sums(c->dtype, c->u[0], 0.0, line, (int64_t)nrows, c->B[0], c->stream));
-    if (c->W[0] != nullptr)
-        INIT_CHK(launch_weighted_row_sums(c->dtype, c->u[0], c->nx, (int64_t)nrows, c->W[0],
-                                          c->stream));
-    INIT_CHK(hipStreamSynchronize(c->stream));
-#undef INIT_CHK
-    *out = c;
-    return ABFT_OK;
 }
 
-abft_status abft_stencil_step(abft_ctx* c, int64_t nsweeps)
+abft_status step_impl(abft_ctx* c, int64_t nsweeps)
 {
     if (!c) return ABFT_E_INVAL;
     if (nsweeps < 0) return fail(c, ABFT_E_INVAL, "nsweeps < 0");
@@ -1144,7 +1131,7 @@ abft_status abft_stencil_step(abft_ctx* c, int64_t nsweeps)
     return enqueue_online(c, nsweeps, nullptr, 0);
 }
 
-abft_status abft_stencil_step_graph(abft_ctx* c, int64_t nsweeps)
+abft_status step_graph_impl(abft_ctx* c, int64_t nsweeps)
 {
     if (!c) return ABFT_E_INVAL;
     if (nsweeps < 0) return fail(c, ABFT_E_INVAL, "nsweeps < 0");
@@ -1188,7 +1175,7 @@ abft_status abft_stencil_step_graph(abft_ctx* c, int64_t nsweeps)
     return ABFT_OK;
 }
 
-abft_status abft_stencil_check(abft_ctx* c, abft_report* out)
+abft_status check_impl(abft_ctx* c, abft_report* out)
 {
     if (!c) return ABFT_E_INVAL;
     if (c->mode == ABFT_MODE_OFFLINE) {
@@ -1259,7 +1246,7 @@ abft_status abft_stencil_check(abft_ctx* c, abft_report* out)
     return ABFT_OK;
 }
 
-abft_status abft_stencil_correct(abft_ctx* c, abft_report* inout)
+abft_status correct_impl(abft_ctx* c, abft_report* inout)
 {
     if (!c) return ABFT_E_INVAL;
     Counters before{};
@@ -1281,7 +1268,7 @@ abft_status abft_stencil_correct(abft_ctx* c, abft_report* inout)
         c->halted = false;
         offline_rotate(c, k);
     }
-    s = abft_stencil_check(c, inout);
+    s = check_impl(c, inout);
     if (s) return s;
     Counters after{};
     s = read_counters(c, &after);
@@ -1291,7 +1278,7 @@ abft_status abft_stencil_correct(abft_ctx* c, abft_report* inout)
     return ABFT_OK;
 }
 
-abft_status abft_stencil_current(abft_ctx* c, int32_t grid, void** dev_ptr, int64_t* sweep)
+abft_status current_impl(abft_ctx* c, int32_t grid, void** dev_ptr, int64_t* sweep)
 {
     if (!c) return ABFT_E_INVAL;
     if (c->batch) {
@@ -1306,7 +1293,7 @@ abft_status abft_stencil_current(abft_ctx* c, int32_t grid, void** dev_ptr, int6
     return ABFT_OK;
 }
 
-abft_status abft_stencil_checksums(abft_ctx* c, int32_t grid, double** dev_ptr)
+abft_status checksums_impl(abft_ctx* c, int32_t grid, double** dev_ptr)
 {
     if (!c || !dev_ptr) return ABFT_E_INVAL;
     if (c->batch) {
@@ -1319,7 +1306,7 @@ abft_status abft_stencil_checksums(abft_ctx* c, int32_t grid, double** dev_ptr)
     return ABFT_OK;
 }
 
-abft_status abft_stencil_inject(abft_ctx* c, const abft_fault* f, int32_t n)
+abft_status inject_impl(abft_ctx* c, const abft_fault* f, int32_t n)
 {
     if (!c || n < 0 || (n > 0 && !f)) return c ? fail(c, ABFT_E_INVAL, "fault plan") : ABFT_E_INVAL;
     const int bits = c->dtype == ABFT_F32 ? 32 : 64;
@@ -1383,7 +1370,7 @@ abft_status abft_stencil_inject(abft_ctx* c, const abft_fault* f, int32_t n)
     return ABFT_OK;
 }
 
-abft_status abft_stencil_autotune(abft_ctx* c)
+abft_status autotune_impl(abft_ctx* c)
 {
     if (!c) return ABFT_E_INVAL;
     if (c->batch) return batch_autotune(c);
@@ -1505,8 +1492,8 @@ abft_status abft_stencil_autotune(abft_ctx* c)
     return ABFT_OK;
 }
 
-abft_status abft_stencil_launch_shape(const abft_ctx* c, int32_t* rows_per_block,
-                                      int32_t* planes_per_block, int32_t* lanes_per_row)
+abft_status launch_shape_impl(const abft_ctx* c, int32_t* rows_per_block,
+                              int32_t* planes_per_block, int32_t* lanes_per_row)
 {
     if (!c) return ABFT_E_INVAL;
     if (rows_per_block) *rows_per_block = sweep_rows_per_block(c->shape);
@@ -1515,7 +1502,7 @@ abft_status abft_stencil_launch_shape(const abft_ctx* c, int32_t* rows_per_block
     return ABFT_OK;
 }
 
-void abft_stencil_destroy(abft_ctx* c)
+void destroy_impl(abft_ctx* c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
@@ -1523,8 +1510,8 @@ void abft_stencil_destroy(abft_ctx* c)
     delete c;
 }
 
-abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft_options* o,
-                                    void* hip_stream, abft_ctx** out)
+abft_status init_batch_impl(const abft_problem* p, int32_t n, const abft_options* o,
+                            void* hip_stream, abft_ctx** out)
 {
     g_init_error.clear();
     if (!out) return fail(nullptr, ABFT_E_INVAL, "out is NULL");
@@ -1540,121 +1527,238 @@ abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft
         return fail(nullptr, ABFT_E_UNSUPPORTED, "batches run the online and plain modes");
 
     abft_ctx* c = new abft_ctx();
-    c->batch = true;
-    c->dtype = p[0].dtype;
-    c->mode = o->mode;
-    c->eps = o->threshold;
-    c->csum = o->csum == ABFT_CSUM_F32_COMP ? CS_F32C : CS_F64;
-    c->auto_correct = o->auto_correct ? 1 : 0;
-    c->recompute = o->correction == ABFT_CORRECT_RECOMPUTE ? 1 : 0;
-    c->input_check = (o->input_check && o->mode == ABFT_MODE_ONLINE) ? 1 : 0;
-    c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
-    c->stream = static_cast<hipStream_t>(hip_stream);
-    if (o->tile_x != 0)
-        return fail(nullptr, ABFT_E_UNSUPPORTED, "batches keep whole-row checksums");
-    auto bail = [&](abft_status st) {
-        g_init_error = c->err;
+    try {
+        c->batch = true;
+        c->dtype = p[0].dtype;
+        c->mode = o->mode;
+        c->eps = o->threshold;
+        c->csum = o->csum == ABFT_CSUM_F32_COMP ? CS_F32C : CS_F64;
+        c->auto_correct = o->auto_correct ? 1 : 0;
+        c->recompute = o->correction == ABFT_CORRECT_RECOMPUTE ? 1 : 0;
+        c->input_check = (o->input_check && o->mode == ABFT_MODE_ONLINE) ? 1 : 0;
+        c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        if (o->tile_x != 0)
+            return fail(nullptr, ABFT_E_UNSUPPORTED, "batches keep whole-row checksums");
+        auto bail = [&](abft_status st) {
+            g_init_error = c->err;
+            free_all(c);
+            delete c;
+            return st;
+        };
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+            return bail(fail(c, ABFT_E_HIP, "device query failed"));
+        c->num_cus = prop.multiProcessorCount;
+
+        bool vec_ok = true;
+        const int vf = 16 / (int)esize(c->dtype);
+        for (int i = 0; i < n; ++i) {
+            c->maxnx = std::max(c->maxnx, p[i].nx);
+            c->maxnz = std::max(c->maxnz, p[i].nz);
+            vec_ok = vec_ok && p[i].nx % vf == 0;
+        }
+        // one kernel shape covers the widest row of the batch
+        SweepShape sh{};
+        sh.pf = 1;
+        if (vec_ok && c->maxnx <= 16 * 4 * vf) sh = SweepShape{16, 4, vf, 1, 1};
+        else if (vec_ok && c->maxnx <= 64 * 4 * vf) sh = SweepShape{64, 4, vf, 1, 1};
+        else if (c->maxnx <= 64 * 16) sh = SweepShape{64, 16, 1, 1, 1};
+        else return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the batched kernel"));
+        c->shape = sh;
+        c->grids.resize(n);
+        for (int i = 0; i < n; ++i) {
+            auto& G = c->grids[i];
+            // per-grid stencil: reuse the single-grid tap mapping on a scratch context
+            abft_ctx tmp;
+            if ((s = map_taps(&tmp, &p[i]))) return bail(fail(c, s, tmp.err));
+            // one kernel form per batch: every grid has the first grid's radius and form
+            if (i == 0) {
+                c->shape.rad = tmp.st.rad;
+                c->shape.box = tmp.st.box;
+            } else if (tmp.st.rad != c->shape.rad || tmp.st.box != c->shape.box) {
+                return bail(fail(c, ABFT_E_UNSUPPORTED, "batched grids share the stencil form"));
+            }
+            if (tmp.st.rad == 2)
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int len = ax == 0 ? p[i].nx : ax == 1 ? p[i].ny : p[i].nz;
+                    const uint32_t m2 = (1u << w_slot(ax, 2, -1)) | (1u << w_slot(ax, 2, 1));
+                    if ((tmp.st.mask & m2) && len < 2)
+                        return bail(fail(c, ABFT_E_UNSUPPORTED, "distance-2 taps along an axis of "
+                                                                "length 1"));
+                }
+            G.st = tmp.st;
+            G.nx = p[i].nx;
+            G.ny = p[i].ny;
+            G.nz = p[i].nz;
+            G.u[0] = p[i].u0;
+            G.u[1] = p[i].u1;
+            G.C = p[i].cterm;
+            G.cs = round_to(c->dtype, p[i].cterm_scalar);
+            const size_t nrows = (size_t)G.nz * G.ny, ncols = (size_t)G.nz * G.nx;
+            if ((s = dalloc(c, &G.B[0], nrows * 8)) || (s = dalloc(c, &G.B[1], nrows * 8)) ||
+                (s = dalloc(c, &G.cB, nrows * 8)) || (s = dalloc(c, &G.cA, ncols * 8)) ||
+                (s = dalloc(c, &G.slot[0], sizeof(FlagSlot))) ||
+                (s = dalloc(c, &G.slot[1], sizeof(FlagSlot))))
+                return bail(s);
+            G.W[0] = G.W[1] = nullptr;
+            if (i == n - 1 &&
+                (fixup_lds_bytes(c->maxnx, c->shape.box) > (c->shape.box ? kSweepLdsLimit : kLdsLimit) ||
+                 c->maxnx > 4 * kFixBlock))
+                return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
+            if (c->input_check &&
+                ((s = dalloc(c, &G.W[0], nrows * 8)) || (s = dalloc(c, &G.W[1], nrows * 8))))
+                return bail(s);
+        }
+        if ((s = dalloc(c, &c->cnt, sizeof(Counters))) ||
+            (s = dalloc(c, &c->ev, (size_t)c->ev_cap * sizeof(abft_event))) ||
+            (s = dalloc(c, &c->queue, 4 * sizeof(uint32_t))) ||
+            (s = dalloc(c, &c->tbase, sizeof(int64_t))) ||
+            (s = dalloc(c, &c->d_grids, (size_t)n * sizeof(GridDesc))))
+            return bail(s);
+
+        hipError_t e;
+#define INIT_CHK(expr)                                      \
+        if ((e = (expr)) != hipSuccess) {                       \
+            hip_fail(c, e, #expr);                              \
+            return bail(ABFT_E_HIP);                            \
+        }
+        INIT_CHK(launch_fill_u32(reinterpret_cast<uint32_t*>(c->cnt), 0u,
+                                 sizeof(Counters) / 4, c->stream));
+        INIT_CHK(launch_fill_u32(c->queue, 0u, 4, c->stream));
+        INIT_CHK(launch_set_i64(c->tbase, 0, c->stream));
+        for (auto& G : c->grids) {
+            const int64_t nrows = (int64_t)G.nz * G.ny;
+            INIT_CHK(launch_fill_u32(&G.slot[0]->count, 0u, 2, c->stream));
+            INIT_CHK(launch_fill_u32(&G.slot[1]->count, 0u, 2, c->stream));
+            INIT_CHK(launch_row_sums(c->dtype, G.C, G.cs, G.nx, nrows, G.cB, c->stream));
+            INIT_CHK(launch_col_sums(c->dtype, G.C, G.cs, G.nx, G.ny, G.nz, G.cA, c->stream));
+            INIT_CHK(launch_row_sums(c->dtype, G.u[0], 0.0, G.nx, nrows, G.B[0], c->stream));
+            if (G.W[0] != nullptr)
+                INIT_CHK(launch_weighted_row_sums(c->dtype, G.u[0], G.nx, nrows, G.W[0], c->stream));
+        }
+        INIT_CHK(hipStreamSynchronize(c->stream));
+#undef INIT_CHK
+        if ((s = batch_layout(c, 8, 1))) return bail(s);
+        *out = c;
+        return ABFT_OK;
+    } catch (...) {
+        // a host exception (allocation) after the context was made: nothing leaks
         free_all(c);
         delete c;
-        return st;
-    };
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-        return bail(fail(c, ABFT_E_HIP, "device query failed"));
-    c->num_cus = prop.multiProcessorCount;
-
-    bool vec_ok = true;
-    const int vf = 16 / (int)esize(c->dtype);
-    for (int i = 0; i < n; ++i) {
-        c->maxnx = std::max(c->maxnx, p[i].nx);
-        c->maxnz = std::max(c->maxnz, p[i].nz);
-        vec_ok = vec_ok && p[i].nx % vf == 0;
+        throw;
     }
-    // one kernel shape covers the widest row of the batch
-    SweepShape sh{};
-    sh.pf = 1;
-    if (vec_ok && c->maxnx <= 16 * 4 * vf) sh = SweepShape{16, 4, vf, 1, 1};
-    else if (vec_ok && c->maxnx <= 64 * 4 * vf) sh = SweepShape{64, 4, vf, 1, 1};
-    else if (c->maxnx <= 64 * 16) sh = SweepShape{64, 16, 1, 1, 1};
-    else return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the batched kernel"));
-    c->shape = sh;
-    c->grids.resize(n);
-    for (int i = 0; i < n; ++i) {
-        auto& G = c->grids[i];
-        // per-grid stencil: reuse the single-grid tap mapping on a scratch context
-        abft_ctx tmp;
-        if ((s = map_taps(&tmp, &p[i]))) return bail(fail(c, s, tmp.err));
-        // one kernel form per batch: every grid has the first grid's radius and form
-        if (i == 0) {
-            c->shape.rad = tmp.st.rad;
-            c->shape.box = tmp.st.box;
-        } else if (tmp.st.rad != c->shape.rad || tmp.st.box != c->shape.box) {
-            return bail(fail(c, ABFT_E_UNSUPPORTED, "batched grids share the stencil form"));
+}
+
+// Host exceptions (an allocation failing inside the standard library) never cross the C
+// boundary: every entry point turns them into ABFT_E_NOMEM.
+template <typename F>
+abft_status no_throw(abft_ctx* c, F&& f) noexcept
+{
+    try {
+        return f();
+    } catch (...) {
+        try {
+            fail(c, ABFT_E_NOMEM, "host allocation failed");
+        } catch (...) {
         }
-        if (tmp.st.rad == 2)
-            for (int ax = 0; ax < 3; ++ax) {
-                const int len = ax == 0 ? p[i].nx : ax == 1 ? p[i].ny : p[i].nz;
-                const uint32_t m2 = (1u << w_slot(ax, 2, -1)) | (1u << w_slot(ax, 2, 1));
-                if ((tmp.st.mask & m2) && len < 2)
-                    return bail(fail(c, ABFT_E_UNSUPPORTED, "distance-2 taps along an axis of "
-                                                            "length 1"));
-            }
-        G.st = tmp.st;
-        G.nx = p[i].nx;
-        G.ny = p[i].ny;
-        G.nz = p[i].nz;
-        G.u[0] = p[i].u0;
-        G.u[1] = p[i].u1;
-        G.C = p[i].cterm;
-        G.cs = round_to(c->dtype, p[i].cterm_scalar);
-        const size_t nrows = (size_t)G.nz * G.ny, ncols = (size_t)G.nz * G.nx;
-        if ((s = dalloc(c, &G.B[0], nrows * 8)) || (s = dalloc(c, &G.B[1], nrows * 8)) ||
-            (s = dalloc(c, &G.cB, nrows * 8)) || (s = dalloc(c, &G.cA, ncols * 8)) ||
-            (s = dalloc(c, &G.slot[0], sizeof(FlagSlot))) ||
-            (s = dalloc(c, &G.slot[1], sizeof(FlagSlot))))
-            return bail(s);
-        G.W[0] = G.W[1] = nullptr;
-        if (i == n - 1 &&
-            (fixup_lds_bytes(c->maxnx, c->shape.box) > (c->shape.box ? kSweepLdsLimit : kLdsLimit) ||
-             c->maxnx > 4 * kFixBlock))
-            return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
-        if (c->input_check &&
-            ((s = dalloc(c, &G.W[0], nrows * 8)) || (s = dalloc(c, &G.W[1], nrows * 8))))
-            return bail(s);
+        return ABFT_E_NOMEM;
     }
-    if ((s = dalloc(c, &c->cnt, sizeof(Counters))) ||
-        (s = dalloc(c, &c->ev, (size_t)c->ev_cap * sizeof(abft_event))) ||
-        (s = dalloc(c, &c->queue, 4 * sizeof(uint32_t))) ||
-        (s = dalloc(c, &c->tbase, sizeof(int64_t))) ||
-        (s = dalloc(c, &c->d_grids, (size_t)n * sizeof(GridDesc))))
-        return bail(s);
+}
 
-    hipError_t e;
-#define INIT_CHK(expr)                                      \
-    if ((e = (expr)) != hipSuccess) {                       \
-        hip_fail(c, e, #expr);                              \
-        return bail(ABFT_E_HIP);                            \
+}  // namespace
+
+// ==========================================================================================
+extern "C" {
+
+const char* abft_strerror(abft_status s)
+{
+    switch (s) {
+    case ABFT_OK: return "ok";
+    case ABFT_E_INVAL: return "invalid argument";
+    case ABFT_E_UNSUPPORTED: return "not supported by the GPU kernels";
+    case ABFT_E_NOMEM: return "out of memory";
+    case ABFT_E_HIP: return "HIP runtime error";
+    case ABFT_E_STATE: return "call not allowed in the current state";
+    case ABFT_E_UNCORRECTABLE: return "detected corruption could not be corrected";
     }
-    INIT_CHK(launch_fill_u32(reinterpret_cast<uint32_t*>(c->cnt), 0u,
-                             sizeof(Counters) / 4, c->stream));
-    INIT_CHK(launch_fill_u32(c->queue, 0u, 4, c->stream));
-    INIT_CHK(launch_set_i64(c->tbase, 0, c->stream));
-    for (auto& G : c->grids) {
-        const int64_t nrows = (int64_t)G.nz * G.ny;
-        INIT_CHK(launch_fill_u32(&G.slot[0]->count, 0u, 2, c->stream));
-        INIT_CHK(launch_fill_u32(&G.slot[1]->count, 0u, 2, c->stream));
-        INIT_CHK(launch_row_sums(c->dtype, G.C, G.cs, G.nx, nrows, G.cB, c->stream));
-        INIT_CHK(launch_col_sums(c->dtype, G.C, G.cs, G.nx, G.ny, G.nz, G.cA, c->stream));
-        INIT_CHK(launch_row_sums(c->dtype, G.u[0], 0.0, G.nx, nrows, G.B[0], c->stream));
-        if (G.W[0] != nullptr)
-            INIT_CHK(launch_weighted_row_sums(c->dtype, G.u[0], G.nx, nrows, G.W[0], c->stream));
+    return "unknown status";
+}
+
+const char* abft_last_error(const abft_ctx* ctx)
+{
+    return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void* hip_stream,
+                              abft_ctx** out)
+{
+    if (out) *out = nullptr;
+    return no_throw(nullptr, [&] { return init_impl(p, o, hip_stream, out); });
+}
+
+abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft_options* o,
+                                    void* hip_stream, abft_ctx** out)
+{
+    if (out) *out = nullptr;
+    return no_throw(nullptr, [&] { return init_batch_impl(p, n, o, hip_stream, out); });
+}
+
+abft_status abft_stencil_step(abft_ctx* c, int64_t nsweeps)
+{
+    return no_throw(c, [&] { return step_impl(c, nsweeps); });
+}
+
+abft_status abft_stencil_step_graph(abft_ctx* c, int64_t nsweeps)
+{
+    return no_throw(c, [&] { return step_graph_impl(c, nsweeps); });
+}
+
+abft_status abft_stencil_check(abft_ctx* c, abft_report* out)
+{
+    return no_throw(c, [&] { return check_impl(c, out); });
+}
+
+abft_status abft_stencil_correct(abft_ctx* c, abft_report* inout)
+{
+    return no_throw(c, [&] { return correct_impl(c, inout); });
+}
+
+abft_status abft_stencil_current(abft_ctx* c, int32_t grid, void** dev_ptr, int64_t* sweep)
+{
+    return no_throw(c, [&] { return current_impl(c, grid, dev_ptr, sweep); });
+}
+
+abft_status abft_stencil_checksums(abft_ctx* c, int32_t grid, double** dev_ptr)
+{
+    return no_throw(c, [&] { return checksums_impl(c, grid, dev_ptr); });
+}
+
+abft_status abft_stencil_inject(abft_ctx* c, const abft_fault* f, int32_t n)
+{
+    return no_throw(c, [&] { return inject_impl(c, f, n); });
+}
+
+abft_status abft_stencil_autotune(abft_ctx* c)
+{
+    return no_throw(c, [&] { return autotune_impl(c); });
+}
+
+abft_status abft_stencil_launch_shape(const abft_ctx* c, int32_t* rows_per_block,
+                                      int32_t* planes_per_block, int32_t* lanes_per_row)
+{
+    return no_throw(nullptr, [&] {
+        return launch_shape_impl(c, rows_per_block, planes_per_block, lanes_per_row);
+    });
+}
+
+void abft_stencil_destroy(abft_ctx* c)
+{
+    try {
+        destroy_impl(c);
+    } catch (...) {
     }
-    INIT_CHK(hipStreamSynchronize(c->stream));
-#undef INIT_CHK
-    if ((s = batch_layout(c, 8, 1))) return bail(s);
-    *out = c;
-    return ABFT_OK;
 }
 
 }  // extern "C"
