@@ -296,11 +296,39 @@ abft_status abft_stencil_autotune(abft_ctx* ctx);
 /* Frees the library's workspace.  NULL is allowed.  Waits for the context's stream. */
 void abft_stencil_destroy(abft_ctx* ctx);
 
+/* Bytes of the static device array abft_stencil_run_noalloc works in, on each GPU. */
+#define ABFT_NOALLOC_SCRATCH_BYTES (16u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): abft_stencil_init, abft_stencil_inject,
+ * abft_stencil_step(nsweeps) and abft_stencil_check in one call, for one grid in the ONLINE or
+ * NONE mode, that calls no hipMalloc, hipFree or other allocating routine.  Its workspace
+ * (checksum planes, constant-term checksums, flag slots, counters, event log and fault plan)
+ * lies in a static device array of ABFT_NOALLOC_SCRATCH_BYTES, one per GPU the library runs
+ * on, held until the process ends.
+ *   p, o: as for abft_stencil_init (o->tuning_cache is not read; the launch shape is the
+ *         default one, as init gives without a tuning cache); offline mode and tile_x != 0
+ *         give ABFT_E_UNSUPPORTED.
+ *   faults: host array of nfaults entries sorted by sweep (attempt 0), or NULL with
+ *         nfaults = 0; an unsorted plan gives ABFT_E_INVAL.
+ *   nsweeps >= 0.  The grid after nsweeps sweeps is in u0 when nsweeps is even, in u1 when
+ *         it is odd.
+ *   out: filled as by abft_stencil_check (may be NULL).  The call waits for the stream.
+ * Errors as for init, step and check; ABFT_E_UNSUPPORTED when the workspace (24 bytes per row
+ * of the grid, 40 with the input check, 8 per column of each layer, two flag slots of 33 KB,
+ * the event log and the plan, each rounded up to 256 bytes) exceeds the array.  The text is
+ * in abft_last_error(NULL).  Every call on a GPU works in that GPU's one array and leaves its
+ * contents there (each call clears what must start at zero): calls that overlap on one GPU,
+ * from other threads or on other streams, race. */
+abft_status abft_stencil_run_noalloc(const abft_problem* p, const abft_options* o,
+                                     const abft_fault* faults, int32_t nfaults, int64_t nsweeps,
+                                     void* hip_stream, abft_report* out);
+
 /* Static text for a status code. */
 const char* abft_strerror(abft_status s);
 
 /* Text of the context's last error ("" if none); valid until the next call on ctx.  With
- * ctx NULL, the last error of a failed init on this thread. */
+ * ctx NULL, the last error of a failed init or abft_stencil_run_noalloc on this thread. */
 const char* abft_last_error(const abft_ctx* ctx);
 
 /* Launch shape currently used by the context: rows per block, planes per block and lanes

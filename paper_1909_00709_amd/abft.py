@@ -35,8 +35,9 @@ EXPORTED = (
     "abft_stencil_step_graph", "abft_stencil_check", "abft_stencil_correct",
     "abft_stencil_current", "abft_stencil_checksums", "abft_stencil_inject",
     "abft_stencil_autotune", "abft_stencil_destroy", "abft_strerror", "abft_last_error",
-    "abft_stencil_launch_shape",
+    "abft_stencil_launch_shape", "abft_stencil_run_noalloc",
 )
+NOALLOC_SCRATCH_BYTES = 16 * 1024 * 1024  # ABFT_NOALLOC_SCRATCH_BYTES
 
 
 class AbftTap(ctypes.Structure):
@@ -133,6 +134,10 @@ def _load():
     L.abft_last_error.restype = ctypes.c_char_p
     L.abft_stencil_launch_shape.argtypes = [_ctx_p] + [ctypes.POINTER(ctypes.c_int32)] * 3
     L.abft_stencil_launch_shape.restype = st
+    L.abft_stencil_run_noalloc.argtypes = [ctypes.POINTER(AbftProblem), ctypes.POINTER(AbftOptions),
+                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                           ctypes.c_void_p, ctypes.POINTER(AbftReport)]
+    L.abft_stencil_run_noalloc.restype = st
     return L
 
 
@@ -213,6 +218,20 @@ def abft_stencil_launch_shape(ctx):
 
 def abft_stencil_destroy(ctx) -> None:
     LIB.abft_stencil_destroy(ctx)
+
+
+def abft_stencil_run_noalloc(problem: AbftProblem, options: AbftOptions, plan, nsweeps: int,
+                             stream: int, report: AbftReport | None = None) -> int:
+    """plan: numpy structured array with the abft_fault layout sorted by sweep, or None."""
+    if plan is None or len(plan) == 0:
+        fp, n = None, 0
+    else:
+        plan = np.ascontiguousarray(plan)
+        assert plan.dtype.itemsize == ctypes.sizeof(AbftFault)
+        fp, n = plan.ctypes.data_as(ctypes.c_void_p), len(plan)
+    return LIB.abft_stencil_run_noalloc(ctypes.byref(problem), ctypes.byref(options), fp, n,
+                                        nsweeps, ctypes.c_void_p(stream),
+                                        ctypes.byref(report) if report is not None else None)
 
 
 # ---- convenience wrapper over torch tensors ---------------------------------------------------

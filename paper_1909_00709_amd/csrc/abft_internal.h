@@ -384,4 +384,26 @@ ABFT_DECL_SWEEP(launch_sweep_f64_tile)
 #undef ABFT_DECL_SWEEP
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t st);
 
+// The allocation-free run (abft_noalloc.hip).  Byte offsets of the workspace of an online or
+// plain run inside one device buffer, each 256-byte aligned.
+struct NoAllocLayout {
+    size_t B[2], W[2], cB, cA, slot[2], cnt, ev, faults, first, total;
+    bool wsums;        // index-weighted row sums kept (online with the input check)
+    int ev_cap;        // event log capacity
+    int64_t tmax;      // one past the fault plan's last sweep
+};
+// Validates the arguments (no HIP call) and lays the workspace out; ABFT_E_UNSUPPORTED when
+// it needs more than `limit` bytes.
+abft_status noalloc_layout(const abft_problem* p, const abft_options* o, const abft_fault* f,
+                           int32_t nf, size_t limit, NoAllocLayout* L);
+// init + inject + step(nsweeps) + check on workspace ws laid out by L, with no allocation.
+abft_status run_in_workspace(const abft_problem* p, const abft_options* o, const abft_fault* f,
+                             int32_t nf, int64_t nsweeps, void* hip_stream, unsigned char* ws,
+                             const NoAllocLayout& L, abft_report* out);
+// Records the text of a failed allocation-free run for abft_last_error(NULL); returns s.
+abft_status run_error(abft_status s, const char* msg) noexcept;
+// first[t] = index of the first fault of a sweep-sorted plan with sweep >= t, t = 0 .. tmax.
+hipError_t launch_fault_index(const abft_fault* faults, int32_t n, int32_t* first, int64_t tmax,
+                              hipStream_t st);
+
 }  // namespace abft

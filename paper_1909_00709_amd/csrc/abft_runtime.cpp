@@ -964,6 +964,81 @@ abft_status batch_autotune(abft_ctx* c)
 
 namespace {
 
+// Everything init does before it allocates: the context's fields from the problem and options,
+// the device's compute units, the stencil's weight slots, the checks of what the kernels cover
+// and the launch shape (from the tuning cache when use_cache is set, else the default).
+abft_status configure(abft_ctx* c, const abft_problem* p, const abft_options* o, void* hip_stream,
+                      bool use_cache)
+{
+    c->nx = p->nx;
+    c->ny = p->ny;
+    c->nz = p->nz;
+    c->dtype = p->dtype;
+    c->bc = p->bc;
+    c->C = p->cterm;
+    c->cs = round_to(p->dtype, p->cterm_scalar);
+    c->u[0] = p->u0;
+    c->u[1] = p->u1;
+    c->mode = o->mode;
+    c->period = o->mode == ABFT_MODE_OFFLINE ? o->period : 1;
+    c->eps = o->threshold;
+    c->csum = o->csum == ABFT_CSUM_F32_COMP ? CS_F32C : CS_F64;
+    c->auto_correct = o->auto_correct ? 1 : 0;
+    c->recompute = o->correction == ABFT_CORRECT_RECOMPUTE ? 1 : 0;
+    c->input_check = (o->input_check && o->mode != ABFT_MODE_NONE) ? 1 : 0;
+    c->tile_x = o->tile_x;
+    c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
+    if (use_cache && o->tuning_cache) c->cache_path = o->tuning_cache;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+            return fail(c, ABFT_E_HIP, "device query failed");
+        c->num_cus = prop.multiProcessorCount;
+    }
+    abft_status s = map_taps(c, p);
+    if (s) return s;
+    if (c->tile_x != 0) {
+        // tiles are the 16 lanes x 16 bytes one lane group of the sweep holds of a row
+        const int tt = 16 * (16 / (int)esize(c->dtype));
+        if (c->tile_x != tt || c->nx % tt || c->st.box || c->input_check ||
+            c->mode == ABFT_MODE_OFFLINE || c->csum != CS_F64)
+            return fail(c, ABFT_E_UNSUPPORTED, "tile-local checksums: online star stencils, "
+                                               "T = 64 (fp32) or 32 (fp64), T dividing nx, "
+                                               "fp64 accumulation");
+    }
+    SweepShape shape{};
+    if (c->st.rad == 2) {
+        // the shifted-line sums of Theorem 1 (and the periodic wrap) need every axis that
+        // carries a distance-2 tap to be at least 2 long
+        for (int ax = 0; ax < 3; ++ax) {
+            const int n = ax == 0 ? c->nx : ax == 1 ? c->ny : c->nz;
+            const uint32_t m2 = (1u << w_slot(ax, 2, -1)) | (1u << w_slot(ax, 2, 1));
+            if ((c->st.mask & m2) && n < 2)
+                return fail(c, ABFT_E_UNSUPPORTED, "distance-2 taps along an axis of length 1");
+        }
+    }
+    const bool cached = use_cache && cache_lookup(c, &shape);
+    shape.rad = c->st.rad;
+    shape.box = c->st.box;
+    if (!cached || !sweep_shape_supported(c->dtype, shape)) {
+        if (!default_shape(c->dtype, c->nx, c->ny, c->nz, c->st.rad, c->st.box, &shape))
+            return fail(c, ABFT_E_UNSUPPORTED, "row length beyond the GPU kernels");
+    }
+    s = apply_shape(c, shape);
+    if (s) return s;
+    if (fixup_lds_bytes(c->nx, c->st.box) > (c->st.box ? kSweepLdsLimit : kLdsLimit) ||
+        c->nx > 4 * kFixBlock)
+        return fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel");
+    if (c->mode == ABFT_MODE_OFFLINE) {
+        check_shape(c, std::min(c->period, kCheckChunk / c->st.rad) * c->st.rad);
+        if ((int64_t)c->ck.ry * c->ck.rz > (int64_t)kCheckCells * kCheckBlock)
+            return fail(c, ABFT_E_UNSUPPORTED, "offline period too long for this grid");
+    }
+    return ABFT_OK;
+}
+
 abft_status init_impl(const abft_problem* p, const abft_options* o, void* hip_stream,
                       abft_ctx** out)
 {
@@ -977,81 +1052,14 @@ abft_status init_impl(const abft_problem* p, const abft_options* o, void* hip_st
 
     abft_ctx* c = new abft_ctx();
     try {
-        c->nx = p->nx;
-        c->ny = p->ny;
-        c->nz = p->nz;
-        c->dtype = p->dtype;
-        c->bc = p->bc;
-        c->C = p->cterm;
-        c->cs = round_to(p->dtype, p->cterm_scalar);
-        c->u[0] = p->u0;
-        c->u[1] = p->u1;
-        c->mode = o->mode;
-        c->period = o->mode == ABFT_MODE_OFFLINE ? o->period : 1;
-        c->eps = o->threshold;
-        c->csum = o->csum == ABFT_CSUM_F32_COMP ? CS_F32C : CS_F64;
-        c->auto_correct = o->auto_correct ? 1 : 0;
-        c->recompute = o->correction == ABFT_CORRECT_RECOMPUTE ? 1 : 0;
-        c->input_check = (o->input_check && o->mode != ABFT_MODE_NONE) ? 1 : 0;
-        c->tile_x = o->tile_x;
-        c->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
-        if (o->tuning_cache) c->cache_path = o->tuning_cache;
-        c->stream = static_cast<hipStream_t>(hip_stream);
-
         auto bail = [&](abft_status st) {
             g_init_error = c->err;
             free_all(c);
             delete c;
             return st;
         };
-        {
-            int dev = 0;
-            hipDeviceProp_t prop;
-            if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-                return bail(fail(c, ABFT_E_HIP, "device query failed"));
-            c->num_cus = prop.multiProcessorCount;
-        }
-
-        s = map_taps(c, p);
+        s = configure(c, p, o, hip_stream, true);
         if (s) return bail(s);
-        if (c->tile_x != 0) {
-            // tiles are the 16 lanes x 16 bytes one lane group of the sweep holds of a row
-            const int tt = 16 * (16 / (int)esize(c->dtype));
-            if (c->tile_x != tt || c->nx % tt || c->st.box || c->input_check ||
-                c->mode == ABFT_MODE_OFFLINE || c->csum != CS_F64)
-                return bail(fail(c, ABFT_E_UNSUPPORTED, "tile-local checksums: online star "
-                                                        "stencils, T = 64 (fp32) or 32 (fp64), "
-                                                        "T dividing nx, fp64 accumulation"));
-        }
-        SweepShape shape{};
-        if (c->st.rad == 2) {
-            // the shifted-line sums of Theorem 1 (and the periodic wrap) need every axis that
-            // carries a distance-2 tap to be at least 2 long
-            for (int ax = 0; ax < 3; ++ax) {
-                const int n = ax == 0 ? c->nx : ax == 1 ? c->ny : c->nz;
-                const uint32_t m2 = (1u << w_slot(ax, 2, -1)) | (1u << w_slot(ax, 2, 1));
-                if ((c->st.mask & m2) && n < 2)
-                    return bail(fail(c, ABFT_E_UNSUPPORTED, "distance-2 taps along an axis of "
-                                                            "length 1"));
-            }
-        }
-        const bool cached = cache_lookup(c, &shape);
-        shape.rad = c->st.rad;
-        shape.box = c->st.box;
-        if (!cached || !sweep_shape_supported(c->dtype, shape)) {
-            if (!default_shape(c->dtype, c->nx, c->ny, c->nz, c->st.rad, c->st.box, &shape))
-                return bail(fail(c, ABFT_E_UNSUPPORTED, "row length beyond the GPU kernels"));
-        }
-        s = apply_shape(c, shape);
-        if (s) return bail(s);
-        if (fixup_lds_bytes(c->nx, c->st.box) > (c->st.box ? kSweepLdsLimit : kLdsLimit) ||
-            c->nx > 4 * kFixBlock)
-            return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the locate kernel"));
-        if (c->mode == ABFT_MODE_OFFLINE) {
-            check_shape(c, std::min(c->period, kCheckChunk / c->st.rad) * c->st.rad);
-            if ((int64_t)c->ck.ry * c->ck.rz > (int64_t)kCheckCells * kCheckBlock)
-                return bail(fail(c, ABFT_E_UNSUPPORTED, "offline period too long for this grid"));
-        }
 
         // checksum entries: one per row, or one per tile of each row
         const size_t nrows = (size_t)c->nz * c->ny * (c->tile_x ? c->nx / c->tile_x : 1),
@@ -1668,6 +1676,138 @@ abft_status no_throw(abft_ctx* c, F&& f) noexcept
 }
 
 }  // namespace
+
+// ---- the allocation-free run (abft_stencil_run_noalloc, abft_noalloc.hip) ------------------
+namespace abft {
+
+abft_status run_error(abft_status s, const char* msg) noexcept
+{
+    try {
+        g_init_error = msg;
+    } catch (...) {
+    }
+    return s;
+}
+
+abft_status noalloc_layout(const abft_problem* p, const abft_options* o, const abft_fault* f,
+                           int32_t nf, size_t limit, NoAllocLayout* L)
+{
+    g_init_error.clear();
+    abft_status s = validate_problem(p);
+    if (s) return s;
+    if ((s = validate_options(p, o))) return s;
+    if (o->mode == ABFT_MODE_OFFLINE)
+        return fail(nullptr, ABFT_E_UNSUPPORTED,
+                    "the allocation-free run covers the online and plain modes");
+    if (o->tile_x != 0)
+        return fail(nullptr, ABFT_E_UNSUPPORTED, "the allocation-free run keeps row checksums");
+    if (nf < 0 || (nf > 0 && !f)) return fail(nullptr, ABFT_E_INVAL, "fault plan");
+    const int bits = p->dtype == ABFT_F32 ? 32 : 64;
+    for (int32_t i = 0; i < nf; ++i) {
+        const abft_fault& x = f[i];
+        if (x.grid != 0 || x.sweep < 0 || x.z < 0 || x.z >= p->nz || x.y < 0 || x.y >= p->ny ||
+            x.x < 0 || x.x >= p->nx || x.bit < 0 || x.bit >= bits || x.attempt != 0 ||
+            (x.kind != ABFT_FAULT_STORE && x.kind != ABFT_FAULT_MEMORY))
+            return fail(nullptr, ABFT_E_INVAL, "fault outside the grid or word");
+        if (i > 0 && x.sweep < f[i - 1].sweep)
+            return fail(nullptr, ABFT_E_INVAL, "the fault plan must be sorted by sweep");
+    }
+    L->tmax = nf > 0 ? f[nf - 1].sweep + 1 : 0;
+    if (L->tmax > (int64_t)1 << 26) return fail(nullptr, ABFT_E_INVAL, "fault sweep index too large");
+    L->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
+    const size_t nrows = (size_t)p->nz * p->ny, ncols = (size_t)p->nz * p->nx;
+    const bool wsums = o->input_check && o->mode == ABFT_MODE_ONLINE;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    L->B[0] = take(nrows * 8);
+    L->B[1] = take(nrows * 8);
+    L->W[0] = wsums ? take(nrows * 8) : 0;
+    L->W[1] = wsums ? take(nrows * 8) : 0;
+    L->wsums = wsums;
+    L->cB = take(nrows * 8);
+    L->cA = take(ncols * 8);
+    L->slot[0] = take(sizeof(FlagSlot));
+    L->slot[1] = take(sizeof(FlagSlot));
+    L->cnt = take(sizeof(Counters));
+    L->ev = take((size_t)L->ev_cap * sizeof(abft_event));
+    L->faults = take((size_t)nf * sizeof(abft_fault));
+    L->first = take((size_t)(L->tmax + 1) * sizeof(int32_t));
+    L->total = off;
+    if (L->total > limit) {
+        char m[160];
+        std::snprintf(m, sizeof(m), "the run needs %zu bytes of workspace; the static scratch "
+                                    "holds %zu", L->total, limit);
+        return fail(nullptr, ABFT_E_UNSUPPORTED, m);
+    }
+    return ABFT_OK;
+}
+
+abft_status run_in_workspace(const abft_problem* p, const abft_options* o, const abft_fault* f,
+                             int32_t nf, int64_t nsweeps, void* hip_stream, unsigned char* ws,
+                             const NoAllocLayout& L, abft_report* out)
+{
+    if (nsweeps < 0) return fail(nullptr, ABFT_E_INVAL, "nsweeps < 0");
+    abft_ctx c;  // on the stack: its containers stay empty, every buffer lies in ws
+    auto done = [&](abft_status st) {
+        if (st) g_init_error = c.err;
+        return st;
+    };
+    abft_status s = configure(&c, p, o, hip_stream, false);
+    if (s) return done(s);
+    auto at = [&](size_t off) { return static_cast<void*>(ws + off); };
+    c.B[0] = static_cast<double*>(at(L.B[0]));
+    c.B[1] = static_cast<double*>(at(L.B[1]));
+    if (L.wsums) {
+        c.W[0] = static_cast<double*>(at(L.W[0]));
+        c.W[1] = static_cast<double*>(at(L.W[1]));
+    }
+    c.cB = static_cast<double*>(at(L.cB));
+    c.cA = static_cast<double*>(at(L.cA));
+    c.slot[0] = static_cast<FlagSlot*>(at(L.slot[0]));
+    c.slot[1] = static_cast<FlagSlot*>(at(L.slot[1]));
+    c.cnt = static_cast<Counters*>(at(L.cnt));
+    c.ev = static_cast<abft_event*>(at(L.ev));
+    c.ev_cap = L.ev_cap;
+    if (nf > 0) {
+        c.faults = static_cast<abft_fault*>(at(L.faults));
+        c.fault_first = static_cast<int32_t*>(at(L.first));
+        c.fault_tmax = L.tmax;
+        c.nfaults = nf;
+        for (int32_t i = 0; i < nf; ++i) c.mem_faults = c.mem_faults || f[i].kind == ABFT_FAULT_MEMORY;
+    }
+    // the scratch keeps the last run's contents: everything that must start at zero is cleared
+    // by fill kernels, the rest is written before it is read
+    hipError_t e;
+#define RUN_CHK(expr)                        \
+    if ((e = (expr)) != hipSuccess) {        \
+        hip_fail(&c, e, #expr);              \
+        return done(ABFT_E_HIP);             \
+    }
+    RUN_CHK(launch_fill_u32(reinterpret_cast<uint32_t*>(c.cnt), 0u, sizeof(Counters) / 4,
+                            c.stream));
+    RUN_CHK(launch_fill_u32(&c.slot[0]->count, 0u, 2, c.stream));
+    RUN_CHK(launch_fill_u32(&c.slot[1]->count, 0u, 2, c.stream));
+    if (nf > 0) {
+        RUN_CHK(hipMemcpyAsync(c.faults, f, (size_t)nf * sizeof(abft_fault),
+                               hipMemcpyHostToDevice, c.stream));
+        RUN_CHK(launch_fault_index(c.faults, nf, c.fault_first, c.fault_tmax, c.stream));
+    }
+    RUN_CHK(launch_row_sums(c.dtype, c.C, c.cs, c.nx, (int64_t)c.nz * c.ny, c.cB, c.stream));
+    RUN_CHK(launch_col_sums(c.dtype, c.C, c.cs, c.nx, c.ny, c.nz, c.cA, c.stream));
+    RUN_CHK(launch_row_sums(c.dtype, c.u[0], 0.0, c.nx, (int64_t)c.nz * c.ny, c.B[0], c.stream));
+    if (c.W[0] != nullptr)
+        RUN_CHK(launch_weighted_row_sums(c.dtype, c.u[0], c.nx, (int64_t)c.nz * c.ny, c.W[0],
+                                         c.stream));
+#undef RUN_CHK
+    if ((s = enqueue_online(&c, nsweeps, nullptr, 0))) return done(s);
+    return done(check_impl(&c, out));
+}
+
+}  // namespace abft
 
 // ==========================================================================================
 extern "C" {
