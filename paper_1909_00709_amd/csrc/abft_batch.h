@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(kBatchWaves * 64)
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ int sh_next;
     const int p = b.parity;
-    if (blockIdx.x == 0) {
+    if (b.zero_slots && blockIdx.x == 0) {
         // the next sweep's flag slots start from zero
         for (int g = threadIdx.x; g < b.ngrids; g += blockDim.x) {
             b.grids[g].slot[p ^ 1]->count = 0u;
@@ -66,6 +66,7 @@ __global__ void __launch_bounds__(kBatchWaves * 64)
         a.st.mask = load_const(&d->st.mask);
         a.st.bc = load_const(&d->st.bc);
         a.st.g = load_const(&d->st.g);
+        a.st.xterms = load_const(&d->st.xterms);
         a.st.rad = RAD;
         a.st.box = BOX;
         if constexpr (BOX) {
@@ -113,12 +114,18 @@ __global__ void __launch_bounds__(kBatchWaves * 64)
     }
 }
 
-// Instantiated shapes: 16 or 64 lanes per row with 16-byte accesses, or 64 lanes of single
-// elements for rows that are not 16-byte multiples.
+// Instantiated shapes, one per size class of rows: 16 lanes per row with 1, 2 or 4 chunks of
+// 16-byte accesses (rows up to 64, 128, 256 fp32 points), 64 lanes with 1, 2 or 4 chunks (up to
+// 256, 512, 1024), and 64 lanes of single elements for rows that are not 16-byte multiples.
 #define ABFT_BATCH_SHAPES(X)                                                                   \
     constexpr int VF = 16 / (int)sizeof(T);                                                    \
+    X(16, 1, VF)                                                                               \
+    X(16, 2, VF)                                                                               \
     X(16, 4, VF)                                                                               \
+    X(64, 1, VF)                                                                               \
+    X(64, 2, VF)                                                                               \
     X(64, 4, VF)                                                                               \
+    X(64, 4, 1)                                                                                \
     X(64, 16, 1)
 
 template <typename T, int MODE, int CS, int RAD, int BOX>
@@ -157,46 +164,50 @@ int occupancy_t(const SweepShape& s, size_t lds)
 }
 #undef ABFT_BATCH_SHAPES
 
-// Launch and occupancy for one stencil form (radius 1 or 2 star, box), every mode, checksum
-// accumulation and dtype; instantiated once per form in its own translation unit.
-template <int RAD, int BOX>
-hipError_t launch_batch_form(int dtype, int mode, int csum, const SweepShape& s,
-                             const BatchArgs& b, int nblocks, size_t lds, hipStream_t st)
+// Launch and occupancy for one stencil form (radius 1 or 2 star, box) and one dtype, every
+// mode and checksum accumulation; each (form, dtype) pair is instantiated in a translation
+// unit of its own (ABFT_BATCH_TU), so that they compile in parallel.
+template <typename T, int RAD, int BOX>
+hipError_t launch_batch_dt(int mode, int csum, const SweepShape& s, const BatchArgs& b,
+                           int nblocks, size_t lds, hipStream_t st)
 {
-    if (dtype == ABFT_F32) {
-        if (mode == MODE_PLAIN)
-            return launch_batch_t<float, MODE_PLAIN, CS_F64, RAD, BOX>(s, b, nblocks, lds, st);
-        if (mode == MODE_PROTM) {
-            if (csum == CS_F32C)
-                return launch_batch_t<float, MODE_PROTM, CS_F32C, RAD, BOX>(s, b, nblocks, lds, st);
-            return launch_batch_t<float, MODE_PROTM, CS_F64, RAD, BOX>(s, b, nblocks, lds, st);
-        }
-        if (csum == CS_F32C)
-            return launch_batch_t<float, MODE_PROT, CS_F32C, RAD, BOX>(s, b, nblocks, lds, st);
-        return launch_batch_t<float, MODE_PROT, CS_F64, RAD, BOX>(s, b, nblocks, lds, st);
-    }
     if (mode == MODE_PLAIN)
-        return launch_batch_t<double, MODE_PLAIN, CS_F64, RAD, BOX>(s, b, nblocks, lds, st);
+        return launch_batch_t<T, MODE_PLAIN, CS_F64, RAD, BOX>(s, b, nblocks, lds, st);
+    if constexpr (sizeof(T) == 4) {
+        if (csum == CS_F32C) {
+            if (mode == MODE_PROTM)
+                return launch_batch_t<T, MODE_PROTM, CS_F32C, RAD, BOX>(s, b, nblocks, lds, st);
+            return launch_batch_t<T, MODE_PROT, CS_F32C, RAD, BOX>(s, b, nblocks, lds, st);
+        }
+    }
     if (mode == MODE_PROTM)
-        return launch_batch_t<double, MODE_PROTM, CS_F64, RAD, BOX>(s, b, nblocks, lds, st);
-    return launch_batch_t<double, MODE_PROT, CS_F64, RAD, BOX>(s, b, nblocks, lds, st);
+        return launch_batch_t<T, MODE_PROTM, CS_F64, RAD, BOX>(s, b, nblocks, lds, st);
+    return launch_batch_t<T, MODE_PROT, CS_F64, RAD, BOX>(s, b, nblocks, lds, st);
 }
 
-template <int RAD, int BOX>
-int occupancy_form(int dtype, int mode, int csum, const SweepShape& s, size_t lds)
+template <typename T, int RAD, int BOX>
+int occupancy_dt(int mode, int csum, const SweepShape& s, size_t lds)
 {
-    if (dtype == ABFT_F32) {
-        if (mode == MODE_PLAIN) return occupancy_t<float, MODE_PLAIN, CS_F64, RAD, BOX>(s, lds);
-        if (mode == MODE_PROTM) {
-            if (csum == CS_F32C) return occupancy_t<float, MODE_PROTM, CS_F32C, RAD, BOX>(s, lds);
-            return occupancy_t<float, MODE_PROTM, CS_F64, RAD, BOX>(s, lds);
+    if (mode == MODE_PLAIN) return occupancy_t<T, MODE_PLAIN, CS_F64, RAD, BOX>(s, lds);
+    if constexpr (sizeof(T) == 4) {
+        if (csum == CS_F32C) {
+            if (mode == MODE_PROTM) return occupancy_t<T, MODE_PROTM, CS_F32C, RAD, BOX>(s, lds);
+            return occupancy_t<T, MODE_PROT, CS_F32C, RAD, BOX>(s, lds);
         }
-        if (csum == CS_F32C) return occupancy_t<float, MODE_PROT, CS_F32C, RAD, BOX>(s, lds);
-        return occupancy_t<float, MODE_PROT, CS_F64, RAD, BOX>(s, lds);
     }
-    if (mode == MODE_PLAIN) return occupancy_t<double, MODE_PLAIN, CS_F64, RAD, BOX>(s, lds);
-    if (mode == MODE_PROTM) return occupancy_t<double, MODE_PROTM, CS_F64, RAD, BOX>(s, lds);
-    return occupancy_t<double, MODE_PROT, CS_F64, RAD, BOX>(s, lds);
+    if (mode == MODE_PROTM) return occupancy_t<T, MODE_PROTM, CS_F64, RAD, BOX>(s, lds);
+    return occupancy_t<T, MODE_PROT, CS_F64, RAD, BOX>(s, lds);
 }
+
+#define ABFT_BATCH_TU(NAME, T, RAD, BOX)                                                       \
+    hipError_t launch_batch_##NAME(int mode, int csum, const SweepShape& s, const BatchArgs& b, \
+                                   int nblocks, size_t lds, hipStream_t st)                    \
+    {                                                                                          \
+        return launch_batch_dt<T, RAD, BOX>(mode, csum, s, b, nblocks, lds, st);               \
+    }                                                                                          \
+    int batch_occupancy_##NAME(int mode, int csum, const SweepShape& s, size_t lds)            \
+    {                                                                                          \
+        return occupancy_dt<T, RAD, BOX>(mode, csum, s, lds);                                  \
+    }
 
 }  // namespace abft

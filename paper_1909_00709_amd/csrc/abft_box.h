@@ -214,7 +214,10 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
     double* tabE = tabS + TY * a.tz;
     double* tabI = tabE + TY * a.tz;
     double* tabW = tabI + TY * a.tz;
-    const bool keep_e = kProt || a.E != nullptr;
+    // the x-boundary terms: for the prediction unless they cancel exactly, and for the offline
+    // record when one is kept
+    const bool xt = a.st.xterms != 0;
+    const bool keep_e = (kProt && xt) || a.E != nullptr;
     using Acc = T;
 
     for (int z = z0; z < z1; ++z) {
@@ -374,7 +377,8 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
                     // Theorem 1 for the box: the weight sums over dx times the nine input
                     // row sums, plus the boundary terms formed in the march
                     const bool first = pz == sl;
-                    double bp = (first ? pcb : a.cB[l]) + tabE[r * a.tz + pz];
+                    double bp = (first ? pcb : a.cB[l]);
+                    if (xt) bp += tabE[r * a.tz + pz];
 #pragma unroll
                     for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll

@@ -72,7 +72,9 @@ struct Stencil {
     int32_t box;        // 1: a 27-point box stencil (taps off the axes); weights in wb
     double wb[27];      // box weights by box_slot (box stencils only)
     uint32_t bmask;     // bit box_slot set for each box tap
-    int32_t pad;
+    int32_t xterms;     // 1: the x-boundary terms of Theorem 1 do not cancel in the weighted
+                        // sum of a row's prediction, so the protected sweep forms them; 0:
+                        // they cancel exactly (periodic rule, or clamp with equal x weights)
 };
 
 struct RowFlag {
@@ -232,10 +234,12 @@ struct GridDesc {
 struct BatchArgs {
     const GridDesc* grids;
     int32_t ngrids;
-    int32_t ntiles;         // tiles of all grids
+    int32_t ntiles;         // tiles of this launch (one size class of grids, or all)
     const int2* order;      // (grid, tile) in processing order (largest first)
     uint32_t* queue;        // persistent launch: [0] next tile, [1] blocks finished
     int32_t persistent;     // 1: blocks pop tiles from the queue; 0: one tile per block
+    int32_t zero_slots;     // 1: block 0 clears every grid's next-sweep flag slot (the first
+                            // of a sweep's launches)
     int32_t parity;         // t & 1 of this sweep
     const int64_t* t_base;
     int64_t t_off;
@@ -278,12 +282,18 @@ hipError_t launch_sweep_batch(int dtype, int mode, int csum, const SweepShape& s
                               const BatchArgs& b, int nblocks, size_t lds, hipStream_t st);
 size_t batch_lds_bytes(int dtype, int maxnx, int maxtz, const SweepShape& s, bool input_check);
 // Batched sweeps of radius-2 stars and 27-point boxes (their own translation units).
-hipError_t launch_batch_r2(int dtype, int mode, int csum, const SweepShape& s, const BatchArgs& b,
-                           int nblocks, size_t lds, hipStream_t st);
-hipError_t launch_batch_box(int dtype, int mode, int csum, const SweepShape& s,
-                            const BatchArgs& b, int nblocks, size_t lds, hipStream_t st);
-int batch_occupancy_r2(int dtype, int mode, int csum, const SweepShape& s, size_t lds);
-int batch_occupancy_box(int dtype, int mode, int csum, const SweepShape& s, size_t lds);
+// Per stencil form and dtype (batch_{r1,r2,box}_{f32,f64}.hip).
+#define ABFT_BATCH_DECL(NAME)                                                                  \
+    hipError_t launch_batch_##NAME(int mode, int csum, const SweepShape& s, const BatchArgs& b, \
+                                   int nblocks, size_t lds, hipStream_t st);                   \
+    int batch_occupancy_##NAME(int mode, int csum, const SweepShape& s, size_t lds);
+ABFT_BATCH_DECL(r1_f32)
+ABFT_BATCH_DECL(r1_f64)
+ABFT_BATCH_DECL(r2_f32)
+ABFT_BATCH_DECL(r2_f64)
+ABFT_BATCH_DECL(box_f32)
+ABFT_BATCH_DECL(box_f64)
+#undef ABFT_BATCH_DECL
 // Offline, before a rollback recompute (guarded by the window's flag count): the checkpoint's
 // rows against their stored checksums, a changed point placed and restored in place.
 hipError_t launch_verify_ckpt(int dtype, void* u, const double* Bck, const double* Wck, int nx,

@@ -14,6 +14,8 @@
 #include <utility>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "abft_internal.h"
 
 using namespace abft;
@@ -27,6 +29,7 @@ constexpr size_t kLdsLimit = 64 * 1024;       // check and locate kernels
 constexpr size_t kSweepLdsLimit = 160 * 1024; // gfx950: 160 KB of LDS per compute unit
 constexpr int kTargetTiles = 1024;     // blocks of 4 wavefronts per sweep, untuned default
 constexpr int kTargetTilesWide = 256;  // blocks of 8 wavefronts: one per compute unit
+constexpr int kMaxBatchClasses = 16;   // size classes (launches per sweep) of a batch
 
 size_t esize(int dtype) { return dtype == ABFT_F32 ? 4 : 8; }
 
@@ -105,10 +108,22 @@ struct abft_ctx {
     };
     std::vector<Grid> grids;
     GridDesc* d_grids = nullptr;
-    int2* d_order = nullptr;
-    uint32_t* queue = nullptr;
-    int maxnx = 0, maxnz = 0, total_tiles = 0, persistent = 1, nblocks = 0, batch_tz = 0;
-    size_t batch_lds = 0;
+    // The grids of one size class share a launch of the batched sweep: its shape (lanes per
+    // row, chunks, 16-byte or single-element accesses), slab depth and dispatch form.  A
+    // sweep is one launch per class.
+    struct Class {
+        std::vector<int> grids;
+        SweepShape shape{};
+        int tz = 8, persistent = 1, nblocks = 0, ntiles = 0;
+        size_t lds = 0;
+        int2* order = nullptr;      // the class's tiles, largest first (inside d_order)
+        uint32_t* queue = nullptr;  // two words of `queue`
+    };
+    std::vector<Class> classes;
+    int2* d_order = nullptr;        // tile lists of all classes
+    size_t order_cap = 0;           // entries d_order holds (the most any layout needs)
+    uint32_t* queue = nullptr;      // persistent launches: two words per class
+    int maxnx = 0;
     int num_cus = 0;
 };
 
@@ -421,28 +436,30 @@ SweepArgs base_args(const abft_ctx* c)
 // The x-boundary terms of Theorem 1 cancel in the weighted sum (and need not be recorded for
 // the offline interpolation) under the periodic rule, and under clamp for radius-1 x taps of
 // equal weight; clamp with distance-2 x taps, and the constant rule, leave them.
-bool need_boundary_terms(const abft_ctx* c)
+bool boundary_terms_needed(int bc, const Stencil& st)
 {
-    if (c->bc == ABFT_BC_PERIODIC) return false;
-    if (c->st.box) {
+    if (bc == ABFT_BC_PERIODIC) return false;
+    if (st.box) {
         // per (dy, dz) the dx = -1 and dx = +1 terms of a row cancel under clamp only with
         // equal weights
         for (int dz = -1; dz <= 1; ++dz)
             for (int dy = -1; dy <= 1; ++dy) {
                 const int sm = box_slot(-1, dy, dz), sp = box_slot(1, dy, dz);
-                const bool hm = c->st.bmask & (1u << sm), hp = c->st.bmask & (1u << sp);
-                if (c->bc != ABFT_BC_CLAMP && (hm || hp)) return true;
-                if (hm != hp || (hm && c->st.wb[sm] != c->st.wb[sp])) return true;
+                const bool hm = st.bmask & (1u << sm), hp = st.bmask & (1u << sp);
+                if (bc != ABFT_BC_CLAMP && (hm || hp)) return true;
+                if (hm != hp || (hm && st.wb[sm] != st.wb[sp])) return true;
             }
         return false;
     }
-    const uint32_t m = c->st.mask;
+    const uint32_t m = st.mask;
     const bool xm = m & (1u << W_XM), xp = m & (1u << W_XP);
     const bool x2 = m & ((1u << W_XM2) | (1u << W_XP2));
-    if (c->bc == ABFT_BC_CLAMP)
-        return x2 || (xm != xp) || (xm && c->st.w[W_XM] != c->st.w[W_XP]);
+    if (bc == ABFT_BC_CLAMP)
+        return x2 || (xm != xp) || (xm && st.w[W_XM] != st.w[W_XP]);
     return xm || xp || x2;
 }
+
+bool need_boundary_terms(const abft_ctx* c) { return boundary_terms_needed(c->bc, c->st); }
 
 int buf_of(const abft_ctx* c, int j) { return j == 0 ? c->ckpt : ((j & 1) ? c->wq : c->wr); }
 
@@ -783,26 +800,106 @@ int batch_mode(const abft_ctx* c)
 }
 
 // ---- batches of grids ------------------------------------------------------------------------
-// Tile layout of every grid for a slab depth (planes per tile), the processing order (largest
-// tiles first, so that the tail of a sweep is made of small tiles), and the launch size.
-abft_status batch_layout(abft_ctx* c, int tz_choice, int persistent)
+// Batched-sweep shapes by the longest row they hold (lpr * nch * vec points), shortest first:
+// 16 lanes per row with 1, 2 or 4 chunks of 16-byte accesses, 64 lanes with 1, 2 or 4, and for
+// rows that are not 16-byte multiples 64 lanes of single elements with 4 or 16 chunks.
+std::vector<SweepShape> batch_shape_list(int dtype, bool vec_ok)
 {
-    const int ty = sweep_rows_per_block(c->shape);
+    const int vf = 16 / (int)esize(dtype);
+    std::vector<SweepShape> v;
+    auto add = [&](int lpr, int nch, int vec) {
+        SweepShape s{};
+        s.lpr = lpr;
+        s.nch = nch;
+        s.vec = vec;
+        s.tz = 1;
+        s.pf = 1;
+        s.nw = kBatchWaves;
+        v.push_back(s);
+    };
+    if (vec_ok) {
+        add(16, 1, vf);
+        add(16, 2, vf);
+        add(16, 4, vf);
+        add(64, 1, vf);
+        add(64, 2, vf);
+        add(64, 4, vf);
+    } else {
+        add(64, 4, 1);
+        add(64, 16, 1);
+    }
+    std::stable_sort(v.begin(), v.end(), [](const SweepShape& a, const SweepShape& b) {
+        return a.lpr * a.nch * a.vec < b.lpr * b.nch * b.vec;
+    });
+    return v;
+}
+
+int shape_width(const SweepShape& s) { return s.lpr * s.nch * s.vec; }
+
+// The shapes that hold rows of nx points with the least width (16 lanes first), or none.
+std::vector<SweepShape> batch_shapes_for(int dtype, bool vec_ok, int nx)
+{
+    std::vector<SweepShape> out;
+    int w = 0;
+    for (const SweepShape& s : batch_shape_list(dtype, vec_ok)) {
+        if (shape_width(s) < nx) continue;
+        if (out.empty()) w = shape_width(s);
+        if (shape_width(s) != w) break;
+        out.push_back(s);
+    }
+    return out;
+}
+
+bool grid_vec_ok(const abft_ctx* c, int g)
+{
+    return c->grids[g].nx % (16 / (int)esize(c->dtype)) == 0;
+}
+
+// Lays every class out: its grids' tiles for the class's slab depth (largest first, so that
+// the tail of a launch is made of small tiles), its LDS size and launch size; uploads the tile
+// lists and the grid descriptors.
+abft_status batch_layout(abft_ctx* c)
+{
     std::vector<GridDesc> desc(c->grids.size());
+    std::vector<int2> order;
     std::vector<std::pair<int64_t, int2>> tiles;
-    int maxtz = 1;
-    for (size_t g = 0; g < c->grids.size(); ++g) {
-        auto& G = c->grids[g];
-        G.tz = std::max(1, std::min(tz_choice, G.nz));
-        G.nyb = (G.ny + ty - 1) / ty;
-        G.ntiles = G.nyb * ((G.nz + G.tz - 1) / G.tz);
-        maxtz = std::max(maxtz, G.tz);
-        for (int t = 0; t < G.ntiles; ++t) {
-            const int yb = t % G.nyb, zb = t / G.nyb;
-            const int64_t rows = std::min(ty, G.ny - yb * ty);
-            const int64_t planes = std::min(G.tz, G.nz - zb * G.tz);
-            tiles.push_back({rows * planes * G.nx, int2((int)g, t)});
+    for (size_t k = 0; k < c->classes.size(); ++k) {
+        auto& K = c->classes[k];
+        const int ty = sweep_rows_per_block(K.shape);
+        int maxtz = 1, maxnx = 1;
+        tiles.clear();
+        for (int g : K.grids) {
+            auto& G = c->grids[g];
+            G.tz = std::max(1, std::min(K.tz, G.nz));
+            G.nyb = (G.ny + ty - 1) / ty;
+            G.ntiles = G.nyb * ((G.nz + G.tz - 1) / G.tz);
+            maxtz = std::max(maxtz, G.tz);
+            maxnx = std::max(maxnx, G.nx);
+            if (shape_width(K.shape) < G.nx || (K.shape.vec > 1 && G.nx % K.shape.vec))
+                return fail(c, ABFT_E_UNSUPPORTED, "batch class shape does not hold its rows");
+            for (int t = 0; t < G.ntiles; ++t) {
+                const int yb = t % G.nyb, zb = t / G.nyb;
+                const int64_t rows = std::min(ty, G.ny - yb * ty);
+                const int64_t planes = std::min(G.tz, G.nz - zb * G.tz);
+                tiles.push_back({rows * planes * G.nx, int2(g, t)});
+            }
         }
+        std::stable_sort(tiles.begin(), tiles.end(),
+                         [](const auto& a, const auto& b) { return a.first > b.first; });
+        K.lds = batch_lds_bytes(c->dtype, maxnx, maxtz, K.shape, c->input_check);
+        if (K.lds > kSweepLdsLimit)
+            return fail(c, ABFT_E_UNSUPPORTED, "batch tiles exceed the LDS");
+        K.order = c->d_order + order.size();
+        K.queue = c->queue + 2 * k;
+        K.ntiles = (int)tiles.size();
+        for (auto& t : tiles) order.push_back(t.second);
+        const int per_cu = batch_blocks_per_cu(c->dtype, batch_mode(c), c->csum, K.shape, K.lds);
+        K.nblocks = K.persistent ? std::min(K.ntiles, per_cu * c->num_cus) : K.ntiles;
+    }
+    if (order.size() > c->order_cap || c->classes.size() > (size_t)kMaxBatchClasses)
+        return fail(c, ABFT_E_UNSUPPORTED, "batch tile list");
+    for (size_t g = 0; g < c->grids.size(); ++g) {
+        const auto& G = c->grids[g];
         GridDesc& d = desc[g];
         d.u[0] = G.u[0];
         d.u[1] = G.u[1];
@@ -824,36 +921,32 @@ abft_status batch_layout(abft_ctx* c, int tz_choice, int persistent)
         d.slot[0] = G.slot[0];
         d.slot[1] = G.slot[1];
     }
-    std::stable_sort(tiles.begin(), tiles.end(),
-                     [](const auto& a, const auto& b) { return a.first > b.first; });
-    std::vector<int2> order;
-    order.reserve(tiles.size());
-    for (auto& t : tiles) order.push_back(t.second);
-    const size_t lds = batch_lds_bytes(c->dtype, c->maxnx, maxtz, c->shape, c->input_check);
-    if (lds > kSweepLdsLimit) return fail(c, ABFT_E_UNSUPPORTED, "batch tiles exceed the LDS");
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (c->d_order) {
-        auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)c->d_order);
-        if (it != c->allocs.end()) c->allocs.erase(it);
-        (void)hipFree(c->d_order);
-        c->d_order = nullptr;
-    }
-    abft_status s = dalloc(c, &c->d_order, order.size() * sizeof(int2));
-    if (s) return s;
     HIPCHK(c, hipMemcpy(c->d_order, order.data(), order.size() * sizeof(int2),
                         hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_grids, desc.data(), desc.size() * sizeof(GridDesc),
                         hipMemcpyHostToDevice));
-    c->total_tiles = (int)order.size();
-    c->batch_lds = lds;
-    c->batch_tz = tz_choice;
-    c->persistent = persistent;
-    const int mode = batch_mode(c);
-    const int per_cu = batch_blocks_per_cu(c->dtype, mode, c->csum, c->shape, lds);
-    c->nblocks = persistent ? std::min(c->total_tiles, per_cu * c->num_cus) : c->total_tiles;
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
     return ABFT_OK;
+}
+
+// One class of all grids in the shape that holds the longest row (the layout before tuning).
+abft_status batch_single_class(abft_ctx* c, int tz, int persistent)
+{
+    bool vec_ok = true;
+    for (size_t g = 0; g < c->grids.size(); ++g) vec_ok = vec_ok && grid_vec_ok(c, (int)g);
+    const std::vector<SweepShape> sh = batch_shapes_for(c->dtype, vec_ok, c->maxnx);
+    if (sh.empty()) return fail(c, ABFT_E_UNSUPPORTED, "rows too long for the batched kernel");
+    abft_ctx::Class K;
+    for (size_t g = 0; g < c->grids.size(); ++g) K.grids.push_back((int)g);
+    K.shape = sh[0];
+    K.shape.rad = c->shape.rad;
+    K.shape.box = c->shape.box;
+    K.tz = tz;
+    K.persistent = persistent;
+    c->classes.assign(1, K);
+    return batch_layout(c);
 }
 
 BatchArgs batch_args(const abft_ctx* c, int64_t t, const int64_t* tbase, int64_t t0)
@@ -861,10 +954,6 @@ BatchArgs batch_args(const abft_ctx* c, int64_t t, const int64_t* tbase, int64_t
     BatchArgs b{};
     b.grids = c->d_grids;
     b.ngrids = (int)c->grids.size();
-    b.ntiles = c->total_tiles;
-    b.order = c->d_order;
-    b.queue = c->queue;
-    b.persistent = c->persistent;
     b.parity = (int)(t & 1);
     b.t_base = tbase;
     b.t_off = tbase ? t - t0 : t;
@@ -879,9 +968,21 @@ BatchArgs batch_args(const abft_ctx* c, int64_t t, const int64_t* tbase, int64_t
     return b;
 }
 
+// The launch of one class in a sweep; the first class's launch clears the flag slots of the
+// next sweep.
+hipError_t launch_class(const abft_ctx* c, const abft_ctx::Class& K, BatchArgs b, bool first)
+{
+    b.ntiles = K.ntiles;
+    b.order = K.order;
+    b.queue = K.queue;
+    b.persistent = K.persistent;
+    b.zero_slots = first ? 1 : 0;
+    return launch_sweep_batch(c->dtype, batch_mode(c), c->csum, K.shape, b, K.nblocks, K.lds,
+                              c->stream);
+}
+
 abft_status enqueue_batch(abft_ctx* c, int64_t n, const int64_t* tbase, int64_t t0)
 {
-    const int mode = batch_mode(c);
     for (int64_t i = 0; i < n; ++i) {
         const int64_t t = c->t + i;
         const BatchArgs b = batch_args(c, t, tbase, t0);
@@ -891,9 +992,10 @@ abft_status enqueue_batch(abft_ctx* c, int64_t n, const int64_t* tbase, int64_t 
                                       c->fault_tmax, tbase, b.t_off, c->stream);
             if (e != hipSuccess) return hip_fail(c, e, "memory fault launch");
         }
-        e = launch_sweep_batch(c->dtype, mode, c->csum, c->shape, b, c->nblocks, c->batch_lds,
-                               c->stream);
-        if (e != hipSuccess) return hip_fail(c, e, "batched sweep launch");
+        for (size_t k = 0; k < c->classes.size(); ++k) {
+            e = launch_class(c, c->classes[k], b, k == 0);
+            if (e != hipSuccess) return hip_fail(c, e, "batched sweep launch");
+        }
         if (c->mode == ABFT_MODE_ONLINE && c->auto_correct) {
             e = launch_fixup_batch(c->dtype, b, c->maxnx, c->shape.rad, c->shape.box, c->stream);
             if (e != hipSuccess) return hip_fail(c, e, "batched locate/correct launch");
@@ -905,53 +1007,124 @@ abft_status enqueue_batch(abft_ctx* c, int64_t n, const int64_t* tbase, int64_t 
     return ABFT_OK;
 }
 
+// Per-size-class autotuning.  The grids are grouped by the narrowest shape that holds their
+// rows (classes in order of row length); every run of consecutive classes is timed as one
+// launch for each shape that holds its longest row, slab depth and dispatch form; the split
+// of the classes into runs whose summed launch times are least is kept.  The all-in-one
+// layout (one launch in the widest shape) is one of the splits tried.
 abft_status batch_autotune(abft_ctx* c)
 {
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
-    const int mode = batch_mode(c);
-    int best_tz = c->batch_tz, best_p = c->persistent;
-    float best_ms = 1e30f;
-    abft_status s = ABFT_OK;
-    for (int tz : {2, 4, 8, 16, 32, 1 << 20})
-        for (int p : {1, 0}) {
-            if ((s = batch_layout(c, tz, p))) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return s;
-            }
-            // the timed sweeps read u^t and write the other buffers, as a real sweep would;
-            // no fault plan, so nothing is flagged
-            BatchArgs b = batch_args(c, c->t, nullptr, 0);
-            b.faults = nullptr;
-            b.fault_tmax = 0;
-            float ms = 1e30f;
-            for (int g = 0; g < 3; ++g) {
-                (void)launch_sweep_batch(c->dtype, mode, c->csum, c->shape, b, c->nblocks,
-                                         c->batch_lds, c->stream);
-                HIPCHK(c, hipEventRecord(e0, c->stream));
-                for (int r = 0; r < 5; ++r)
-                    (void)launch_sweep_batch(c->dtype, mode, c->csum, c->shape, b, c->nblocks,
-                                             c->batch_lds, c->stream);
-                HIPCHK(c, hipEventRecord(e1, c->stream));
-                HIPCHK(c, hipEventSynchronize(e1));
-                float gms = 0.f;
-                HIPCHK(c, hipEventElapsedTime(&gms, e0, e1));
-                ms = std::min(ms, gms / 5);
-            }
-            if (ms < best_ms) {
-                best_ms = ms;
-                best_tz = tz;
-                best_p = p;
-            }
-        }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    // the timing runs left the next sweep's flag slots and tile counter as a sweep would
-    s = batch_layout(c, best_tz, best_p);
+    Counters* scnt = nullptr;  // the timing launches count into scratch, log no events
+    abft_status s = dalloc(c, &scnt, sizeof(Counters));
     if (s) return s;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)scnt);
+        if (it != c->allocs.end()) c->allocs.erase(it);
+        (void)hipFree(scnt);
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(c, ABFT_E_HIP, "hipEventCreate");
+    }
+    // base classes: (16-byte accesses, narrowest shape) per grid, in order of row length
+    std::map<std::pair<int, int>, std::vector<int>> by;
+    for (size_t g = 0; g < c->grids.size(); ++g) {
+        const bool vo = grid_vec_ok(c, (int)g);
+        const auto sh = batch_shapes_for(c->dtype, vo, c->grids[g].nx);
+        if (sh.empty()) {
+            cleanup();
+            return fail(c, ABFT_E_UNSUPPORTED, "rows too long for the batched kernel");
+        }
+        by[{vo ? 0 : 1, shape_width(sh[0])}].push_back((int)g);
+    }
+    std::vector<std::vector<int>> base;
+    std::vector<bool> base_vec;
+    for (auto& kv : by) {
+        base.push_back(kv.second);
+        base_vec.push_back(kv.first.first == 0);
+    }
+    const int nb = (int)base.size();
+    struct Best {
+        float ms = 1e30f;
+        abft_ctx::Class k;
+    };
+    std::vector<std::vector<Best>> best(nb, std::vector<Best>(nb));
+    BatchArgs b = batch_args(c, c->t, nullptr, 0);
+    b.faults = nullptr;
+    b.fault_tmax = 0;
+    b.cnt = scnt;
+    b.ev = nullptr;
+    b.ev_cap = 0;
+    for (int i = 0; i < nb; ++i)
+        for (int j = i; j < nb; ++j) {
+            abft_ctx::Class K;
+            bool vo = true;
+            int wmax = 1;
+            for (int q = i; q <= j; ++q) {
+                K.grids.insert(K.grids.end(), base[q].begin(), base[q].end());
+                vo = vo && base_vec[q];
+                for (int g : base[q]) wmax = std::max(wmax, c->grids[g].nx);
+            }
+            for (SweepShape sh : batch_shapes_for(c->dtype, vo, wmax))
+                for (int tz : {2, 4, 8, 16, 32, 1 << 20})
+                    for (int p : {1, 0}) {
+                        sh.rad = c->shape.rad;
+                        sh.box = c->shape.box;
+                        K.shape = sh;
+                        K.tz = tz;
+                        K.persistent = p;
+                        c->classes.assign(1, K);
+                        if (batch_layout(c)) continue;  // e.g. tiles beyond the LDS
+                        const abft_ctx::Class& L = c->classes[0];
+                        float ms = 1e30f;
+                        bool ok = launch_class(c, L, b, true) == hipSuccess &&
+                                  launch_class(c, L, b, true) == hipSuccess;
+                        for (int grp = 0; ok && grp < 3; ++grp) {
+                            ok = hipEventRecord(e0, c->stream) == hipSuccess;
+                            for (int r = 0; ok && r < 5; ++r)
+                                ok = launch_class(c, L, b, true) == hipSuccess;
+                            float gms = 0.f;
+                            ok = ok && hipEventRecord(e1, c->stream) == hipSuccess &&
+                                 hipEventSynchronize(e1) == hipSuccess &&
+                                 hipEventElapsedTime(&gms, e0, e1) == hipSuccess;
+                            if (ok) ms = std::min(ms, gms / 5);
+                        }
+                        if (!ok) {
+                            (void)hipGetLastError();
+                            (void)hipStreamSynchronize(c->stream);
+                            continue;
+                        }
+                        if (ms < best[i][j].ms) {
+                            best[i][j].ms = ms;
+                            best[i][j].k = L;
+                        }
+                    }
+        }
+    // least summed time over the splits into runs of consecutive classes
+    std::vector<float> f(nb + 1, 1e30f);
+    std::vector<int> from(nb + 1, -1);
+    f[0] = 0.f;
+    for (int j = 0; j < nb; ++j)
+        for (int i = 0; i <= j; ++i)
+            if (f[i] + best[i][j].ms < f[j + 1]) {
+                f[j + 1] = f[i] + best[i][j].ms;
+                from[j + 1] = i;
+            }
+    std::vector<abft_ctx::Class> chosen;
+    for (int j = nb; j > 0 && from[j] >= 0; j = from[j]) chosen.push_back(best[from[j]][j - 1].k);
+    cleanup();
+    if (chosen.empty() || f[nb] >= 1e29f)
+        return fail(c, ABFT_E_UNSUPPORTED, "no batched launch shape ran");
+    std::reverse(chosen.begin(), chosen.end());
+    c->classes = chosen;
+    s = batch_layout(c);
+    if (s) return s;
+    // the timing launches cleared the next sweep's flag slots as a sweep would; clear this
+    // sweep's as well
     for (auto& G : c->grids) {
         hipError_t e = launch_fill_u32(&G.slot[c->t & 1]->count, 0u, 2, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "reset");
@@ -999,6 +1172,7 @@ abft_status configure(abft_ctx* c, const abft_problem* p, const abft_options* o,
     }
     abft_status s = map_taps(c, p);
     if (s) return s;
+    c->st.xterms = need_boundary_terms(c) ? 1 : 0;
     if (c->tile_x != 0) {
         // tiles are the 16 lanes x 16 bytes one lane group of the sweep holds of a row
         const int tt = 16 * (16 / (int)esize(c->dtype));
@@ -1262,7 +1436,8 @@ abft_status correct_impl(abft_ctx* c, abft_report* inout)
     if (s) return s;
     if (c->batch && c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
         const BatchArgs b = batch_args(c, c->t - 1, nullptr, 0);
-        hipError_t e = launch_fixup_batch(c->dtype, b, c->maxnx, c->shape.rad, c->shape.box, c->stream);
+        hipError_t e = launch_fixup_batch(c->dtype, b, c->maxnx, c->shape.rad, c->shape.box,
+                                          c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "batched locate/correct launch");
     } else if (c->mode == ABFT_MODE_ONLINE && !c->auto_correct && c->t > 0) {
         const int64_t t = c->t - 1;
@@ -1504,9 +1679,23 @@ abft_status launch_shape_impl(const abft_ctx* c, int32_t* rows_per_block,
                               int32_t* planes_per_block, int32_t* lanes_per_row)
 {
     if (!c) return ABFT_E_INVAL;
-    if (rows_per_block) *rows_per_block = sweep_rows_per_block(c->shape);
-    if (planes_per_block) *planes_per_block = c->batch ? c->batch_tz : c->shape.tz;
-    if (lanes_per_row) *lanes_per_row = c->shape.lpr;
+    SweepShape sh = c->shape;
+    if (c->batch && !c->classes.empty()) {
+        // the launch of the size class holding the most points
+        int64_t most = -1;
+        for (const auto& K : c->classes) {
+            int64_t pts = 0;
+            for (int g : K.grids) pts += (int64_t)c->grids[g].nx * c->grids[g].ny * c->grids[g].nz;
+            if (pts > most) {
+                most = pts;
+                sh = K.shape;
+                sh.tz = K.tz;
+            }
+        }
+    }
+    if (rows_per_block) *rows_per_block = sweep_rows_per_block(sh);
+    if (planes_per_block) *planes_per_block = sh.tz;
+    if (lanes_per_row) *lanes_per_row = sh.lpr;
     return ABFT_OK;
 }
 
@@ -1560,27 +1749,23 @@ abft_status init_batch_impl(const abft_problem* p, int32_t n, const abft_options
             return bail(fail(c, ABFT_E_HIP, "device query failed"));
         c->num_cus = prop.multiProcessorCount;
 
-        bool vec_ok = true;
-        const int vf = 16 / (int)esize(c->dtype);
+        // the worst-case tile list: one plane per tile, 4 rows per block (64 lanes per row)
+        size_t order_cap = 0;
         for (int i = 0; i < n; ++i) {
             c->maxnx = std::max(c->maxnx, p[i].nx);
-            c->maxnz = std::max(c->maxnz, p[i].nz);
-            vec_ok = vec_ok && p[i].nx % vf == 0;
+            order_cap += (size_t)((p[i].ny + 3) / 4) * p[i].nz;
         }
-        // one kernel shape covers the widest row of the batch
-        SweepShape sh{};
-        sh.pf = 1;
-        if (vec_ok && c->maxnx <= 16 * 4 * vf) sh = SweepShape{16, 4, vf, 1, 1};
-        else if (vec_ok && c->maxnx <= 64 * 4 * vf) sh = SweepShape{64, 4, vf, 1, 1};
-        else if (c->maxnx <= 64 * 16) sh = SweepShape{64, 16, 1, 1, 1};
-        else return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the batched kernel"));
-        c->shape = sh;
+        if (c->maxnx > 64 * 16)
+            return bail(fail(c, ABFT_E_UNSUPPORTED, "rows too long for the batched kernel"));
+        c->shape = SweepShape{};
+        c->shape.nw = kBatchWaves;
         c->grids.resize(n);
         for (int i = 0; i < n; ++i) {
             auto& G = c->grids[i];
             // per-grid stencil: reuse the single-grid tap mapping on a scratch context
             abft_ctx tmp;
             if ((s = map_taps(&tmp, &p[i]))) return bail(fail(c, s, tmp.err));
+            tmp.st.xterms = boundary_terms_needed(p[i].bc, tmp.st) ? 1 : 0;
             // one kernel form per batch: every grid has the first grid's radius and form
             if (i == 0) {
                 c->shape.rad = tmp.st.rad;
@@ -1621,7 +1806,8 @@ abft_status init_batch_impl(const abft_problem* p, int32_t n, const abft_options
         }
         if ((s = dalloc(c, &c->cnt, sizeof(Counters))) ||
             (s = dalloc(c, &c->ev, (size_t)c->ev_cap * sizeof(abft_event))) ||
-            (s = dalloc(c, &c->queue, 4 * sizeof(uint32_t))) ||
+            (s = dalloc(c, &c->queue, 2 * kMaxBatchClasses * sizeof(uint32_t))) ||
+            (s = dalloc(c, &c->d_order, order_cap * sizeof(int2))) ||
             (s = dalloc(c, &c->tbase, sizeof(int64_t))) ||
             (s = dalloc(c, &c->d_grids, (size_t)n * sizeof(GridDesc))))
             return bail(s);
@@ -1634,7 +1820,7 @@ abft_status init_batch_impl(const abft_problem* p, int32_t n, const abft_options
         }
         INIT_CHK(launch_fill_u32(reinterpret_cast<uint32_t*>(c->cnt), 0u,
                                  sizeof(Counters) / 4, c->stream));
-        INIT_CHK(launch_fill_u32(c->queue, 0u, 4, c->stream));
+        INIT_CHK(launch_fill_u32(c->queue, 0u, 2 * kMaxBatchClasses, c->stream));
         INIT_CHK(launch_set_i64(c->tbase, 0, c->stream));
         for (auto& G : c->grids) {
             const int64_t nrows = (int64_t)G.nz * G.ny;
@@ -1648,7 +1834,8 @@ abft_status init_batch_impl(const abft_problem* p, int32_t n, const abft_options
         }
         INIT_CHK(hipStreamSynchronize(c->stream));
 #undef INIT_CHK
-        if ((s = batch_layout(c, 8, 1))) return bail(s);
+        c->order_cap = order_cap;
+        if ((s = batch_single_class(c, 8, 1))) return bail(s);
         *out = c;
         return ABFT_OK;
     } catch (...) {
@@ -1659,11 +1846,19 @@ abft_status init_batch_impl(const abft_problem* p, int32_t n, const abft_options
     }
 }
 
+// Every entry point is a named roctx range, so that a profiler's trace shows the library's
+// calls around the kernels they enqueue (free when no profiler listens).
+struct TraceRange {
+    explicit TraceRange(const char* name) noexcept { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+};
+
 // Host exceptions (an allocation failing inside the standard library) never cross the C
 // boundary: every entry point turns them into ABFT_E_NOMEM.
 template <typename F>
-abft_status no_throw(abft_ctx* c, F&& f) noexcept
+abft_status no_throw(abft_ctx* c, const char* name, F&& f) noexcept
 {
+    const TraceRange range(name);
     try {
         return f();
     } catch (...) {
@@ -1713,7 +1908,8 @@ abft_status noalloc_layout(const abft_problem* p, const abft_options* o, const a
             return fail(nullptr, ABFT_E_INVAL, "the fault plan must be sorted by sweep");
     }
     L->tmax = nf > 0 ? f[nf - 1].sweep + 1 : 0;
-    if (L->tmax > (int64_t)1 << 26) return fail(nullptr, ABFT_E_INVAL, "fault sweep index too large");
+    if (L->tmax > (int64_t)1 << 26)
+        return fail(nullptr, ABFT_E_INVAL, "fault sweep index too large");
     L->ev_cap = o->max_events ? o->max_events : kDefaultEvents;
     const size_t nrows = (size_t)p->nz * p->ny, ncols = (size_t)p->nz * p->nx;
     const bool wsums = o->input_check && o->mode == ABFT_MODE_ONLINE;
@@ -1777,7 +1973,8 @@ abft_status run_in_workspace(const abft_problem* p, const abft_options* o, const
         c.fault_first = static_cast<int32_t*>(at(L.first));
         c.fault_tmax = L.tmax;
         c.nfaults = nf;
-        for (int32_t i = 0; i < nf; ++i) c.mem_faults = c.mem_faults || f[i].kind == ABFT_FAULT_MEMORY;
+        for (int32_t i = 0; i < nf; ++i)
+            c.mem_faults = c.mem_faults || f[i].kind == ABFT_FAULT_MEMORY;
     }
     // the scratch keeps the last run's contents: everything that must start at zero is cleared
     // by fill kernels, the rest is written before it is read
@@ -1835,66 +2032,72 @@ abft_status abft_stencil_init(const abft_problem* p, const abft_options* o, void
                               abft_ctx** out)
 {
     if (out) *out = nullptr;
-    return no_throw(nullptr, [&] { return init_impl(p, o, hip_stream, out); });
+    return no_throw(nullptr, "abft_stencil_init",
+                    [&] { return init_impl(p, o, hip_stream, out); });
 }
 
 abft_status abft_stencil_init_batch(const abft_problem* p, int32_t n, const abft_options* o,
                                     void* hip_stream, abft_ctx** out)
 {
     if (out) *out = nullptr;
-    return no_throw(nullptr, [&] { return init_batch_impl(p, n, o, hip_stream, out); });
+    return no_throw(nullptr, "abft_stencil_init_batch", [&] {
+        return init_batch_impl(p, n, o, hip_stream, out);
+    });
 }
 
 abft_status abft_stencil_step(abft_ctx* c, int64_t nsweeps)
 {
-    return no_throw(c, [&] { return step_impl(c, nsweeps); });
+    return no_throw(c, "abft_stencil_step", [&] { return step_impl(c, nsweeps); });
 }
 
 abft_status abft_stencil_step_graph(abft_ctx* c, int64_t nsweeps)
 {
-    return no_throw(c, [&] { return step_graph_impl(c, nsweeps); });
+    return no_throw(c, "abft_stencil_step_graph", [&] { return step_graph_impl(c, nsweeps); });
 }
 
 abft_status abft_stencil_check(abft_ctx* c, abft_report* out)
 {
-    return no_throw(c, [&] { return check_impl(c, out); });
+    return no_throw(c, "abft_stencil_check", [&] { return check_impl(c, out); });
 }
 
 abft_status abft_stencil_correct(abft_ctx* c, abft_report* inout)
 {
-    return no_throw(c, [&] { return correct_impl(c, inout); });
+    return no_throw(c, "abft_stencil_correct", [&] { return correct_impl(c, inout); });
 }
 
 abft_status abft_stencil_current(abft_ctx* c, int32_t grid, void** dev_ptr, int64_t* sweep)
 {
-    return no_throw(c, [&] { return current_impl(c, grid, dev_ptr, sweep); });
+    return no_throw(c, "abft_stencil_current", [&] {
+        return current_impl(c, grid, dev_ptr, sweep);
+    });
 }
 
 abft_status abft_stencil_checksums(abft_ctx* c, int32_t grid, double** dev_ptr)
 {
-    return no_throw(c, [&] { return checksums_impl(c, grid, dev_ptr); });
+    return no_throw(c, "abft_stencil_checksums", [&] { return checksums_impl(c, grid, dev_ptr); });
 }
 
 abft_status abft_stencil_inject(abft_ctx* c, const abft_fault* f, int32_t n)
 {
-    return no_throw(c, [&] { return inject_impl(c, f, n); });
+    return no_throw(c, "abft_stencil_inject", [&] { return inject_impl(c, f, n); });
 }
 
 abft_status abft_stencil_autotune(abft_ctx* c)
 {
-    return no_throw(c, [&] { return autotune_impl(c); });
+    return no_throw(c, "abft_stencil_autotune", [&] { return autotune_impl(c); });
 }
 
 abft_status abft_stencil_launch_shape(const abft_ctx* c, int32_t* rows_per_block,
                                       int32_t* planes_per_block, int32_t* lanes_per_row)
 {
-    return no_throw(nullptr, [&] {
+    return no_throw(nullptr, "abft_stencil_launch_shape", [&] {
         return launch_shape_impl(c, rows_per_block, planes_per_block, lanes_per_row);
     });
 }
 
 void abft_stencil_destroy(abft_ctx* c)
 {
+    const TraceRange range("abft_stencil_destroy");
     try {
         destroy_impl(c);
     } catch (...) {

@@ -327,7 +327,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
     double* tabE = tabS + TY * a.tz;
     double* tabI = tabE + TY * a.tz;
     double* tabW = tabI + TY * a.tz;
-    const bool keep_e = kProt || a.E != nullptr;
+    // the x-boundary terms: for the prediction unless they cancel exactly, and for the offline
+    // record when one is kept
+    const bool xt = a.st.xterms != 0;
+    const bool keep_e = (kProt && xt) || a.E != nullptr;
 
     for (int z = z0; z < z1; ++z) {
         if constexpr (kMemChk) {
@@ -604,7 +607,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                         if (has(w_slot(0, d, -1))) bp += a.st.w[w_slot(0, d, -1)] * b0;
                         if (has(w_slot(0, d, 1))) bp += a.st.w[w_slot(0, d, 1)] * b0;
                     }
-                    bp += tabE[r * a.tz + pz];
+                    if (xt) bp += tabE[r * a.tz + pz];
 #pragma unroll
                     for (int d = 1; d <= RAD; ++d) {
                         if (has(w_slot(1, d, -1)))

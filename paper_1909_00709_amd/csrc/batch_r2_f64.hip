@@ -1,0 +1,8 @@
+// Instantiations of the batched sweep for radius-2 stars, f64 grids.
+#include "abft_batch.h"
+
+namespace abft {
+
+ABFT_BATCH_TU(r2_f64, double, 2, 0)
+
+}  // namespace abft
