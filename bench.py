@@ -140,18 +140,20 @@ def bench_configs(stream, timed, tune=True):
             C = torch.from_numpy(Cn).cuda() if Cn is not None else None
         stream.synchronize()
         chunk = 10
-        for mode in modes + ("prot",):
-            for cs in (csums if mode != "none" else ("f64",)):
+        for mode in modes + ("prot", "none_windows"):
+            for cs in (csums if not mode.startswith("none") else ("f64",)):
                 with torch.cuda.stream(stream):
                     u = u0.clone()
                 eps = w.eps if not (mode == "offline" and w.dtype == W.F32) else W.C5.eps
                 # "prot": the protected sweep kernel alone (online, no locate launches)
-                S = abft.Stencil(u, w.taps, C=C, mode="online" if mode == "prot" else mode,
+                # "none_windows": the plain sweep as step(k) calls, the offline windows' harness
+                cmode = {"prot": "online", "none_windows": "none"}.get(mode, mode)
+                S = abft.Stencil(u, w.taps, C=C, mode=cmode,
                                  threshold=eps, csum=cs, period=chunk, stream=stream,
                                  auto_correct=mode != "prot", input_check=False)
                 if tune:
                     S.autotune()
-                if mode == "offline":
+                if mode in ("offline", "none_windows"):
                     S.step(chunk)
                     ms = timed(lambda: S.step(chunk), 20) / chunk
                 else:
@@ -159,10 +161,18 @@ def bench_configs(stream, timed, tune=True):
                     ms = timed(lambda: S.step_graph(chunk), 20) / chunk
                 rep, _ = S.check()
                 assert rep["rows_flagged"] == 0 and rep["windows_flagged"] == 0, rep
-                key = mode if mode == "none" else f"{mode}_{cs}"
+                key = mode if mode.startswith("none") else f"{mode}_{cs}"
                 r[f"gpu_{key}_gpts"] = round(w.npoints / (ms * 1e-3) / 1e9, 3)
                 r[f"gpu_{key}_us_per_sweep"] = round(ms * 1e3, 3)
                 S.close()
+        # overheads, each against the plain sweep in the same harness: graphs for online, the
+        # single-sweep launches of a graph for the protected kernel, step(k) for offline
+        for key in list(r):
+            if key.startswith("gpu_") and key.endswith("_us_per_sweep") and "none" not in key:
+                base = r["gpu_none_windows_us_per_sweep" if "offline" in key
+                         else "gpu_none_us_per_sweep"]
+                r[key.replace("_us_per_sweep", "_overhead_pct")] = round(
+                    (r[key] / base - 1) * 100, 2)
         # the oracle on the same grid, all host threads
         p = O.Problem(u0n.shape, O.F64 if w.dtype == W.F64 else O.F32, w.taps)
         nsw = max(2, min(w.nsweeps, int(2e9 // w.npoints)))
@@ -278,7 +288,7 @@ def bench_radius2(stream, timed, u0, C, tune=True, k=10, steps=10, taps=DIFF4_TA
 
     npts = u0.numel()
     res = {"workload": f"{name}, {tuple(u0.shape)} fp32"}
-    for name, mode, kw in (("plain", "none", {}),
+    for name, mode, kw in (("plain", "none", {}), ("plain_graph", "none", {}),
                            ("prot_kernel", "online", dict(threshold=2e-7, auto_correct=False,
                                                           input_check=False)),
                            ("online", "online", dict(threshold=2e-7, input_check=False)),
@@ -293,7 +303,7 @@ def bench_radius2(stream, timed, u0, C, tune=True, k=10, steps=10, taps=DIFF4_TA
                              tuning_cache=tuning_cache, **kw)
             if tune:
                 S.autotune()
-            if name.startswith("online"):
+            if name.startswith("online") or name == "plain_graph":
                 S.step_graph(k)
                 ms = timed(lambda: S.step_graph(k), steps) / k
             else:
@@ -304,14 +314,16 @@ def bench_radius2(stream, timed, u0, C, tune=True, k=10, steps=10, taps=DIFF4_TA
             res[f"{name}_gpts"] = round(npts / (ms * 1e-3) / 1e9, 3)
             res[f"{name}_ms_per_sweep"] = round(ms, 5)
             res[f"{name}_shape"] = S.launch_shape()
-            if name != "plain":
+            if not name.startswith("plain"):
                 res[f"{name}_noise"] = rep["max_noise"]
             S.close()
     res["plain_GBs"] = round(12.0 * npts / (res["plain_ms_per_sweep"] * 1e-3) / 1e9, 1)
+    # each against the plain sweep in the same harness: graphs for online, step(k) otherwise
     for name in ("prot_kernel", "online", "prot_kernel_input_check", "online_input_check",
                  "offline"):
-        res[f"overhead_{name}_pct"] = round(
-            (res[f"{name}_ms_per_sweep"] / res["plain_ms_per_sweep"] - 1) * 100, 2)
+        base = res["plain_graph_ms_per_sweep" if name.startswith("online")
+                   else "plain_ms_per_sweep"]
+        res[f"overhead_{name}_pct"] = round((res[f"{name}_ms_per_sweep"] / base - 1) * 100, 2)
     return res
 
 
@@ -326,7 +338,7 @@ def bench_tiles(stream, timed, u0, C, tune=True, k=10, steps=10, tuning_cache=No
 
     npts = u0.numel()
     res = {"workload": f"7-point thermal, {tuple(u0.shape)} fp32, 64-point tiles vs rows"}
-    for name, mode, kw in (("plain", "none", {}),
+    for name, mode, kw in (("plain", "none", {}), ("plain_graph", "none", {}),
                            ("rows_prot_kernel", "online", dict(auto_correct=False)),
                            ("tiles_prot_kernel", "online", dict(auto_correct=False, tile_x=64)),
                            ("rows_online", "online", {}),
@@ -337,7 +349,7 @@ def bench_tiles(stream, timed, u0, C, tune=True, k=10, steps=10, tuning_cache=No
                              **kw)
             if tune:
                 S.autotune()
-            if name.endswith("online"):
+            if name.endswith("online") or name == "plain_graph":
                 S.step_graph(k)
                 ms = timed(lambda: S.step_graph(k), steps) / k
             else:
@@ -348,12 +360,12 @@ def bench_tiles(stream, timed, u0, C, tune=True, k=10, steps=10, tuning_cache=No
             res[f"{name}_gpts"] = round(npts / (ms * 1e-3) / 1e9, 3)
             res[f"{name}_ms_per_sweep"] = round(ms, 5)
             res[f"{name}_shape"] = S.launch_shape()
-            if name != "plain":
+            if not name.startswith("plain"):
                 res[f"{name}_noise"] = rep["max_noise"]
             S.close()
     for name in ("rows_prot_kernel", "tiles_prot_kernel", "rows_online", "tiles_online"):
-        res[f"overhead_{name}_pct"] = round(
-            (res[f"{name}_ms_per_sweep"] / res["plain_ms_per_sweep"] - 1) * 100, 2)
+        base = res["plain_graph_ms_per_sweep" if name.endswith("online") else "plain_ms_per_sweep"]
+        res[f"overhead_{name}_pct"] = round((res[f"{name}_ms_per_sweep"] / base - 1) * 100, 2)
     return res
 
 
@@ -439,11 +451,18 @@ def main():
         del a, b
 
     # ---- plain sweep: the overhead baseline and the dominant kernel of an offline window ----
+    # Each protected form is compared with the plain sweep timed the same way: single-sweep
+    # calls for the protected kernel alone, graphs of k sweeps for online ABFT, step(k) calls
+    # for offline windows.
     plain_ms = None
     if args.only in (None, "plain"):
         S = make("none")
         S.step(5)
         plain_ms = timed(lambda: S.step(1), 10 * max(1, args.steps // 2))
+        S.step_graph(k)
+        out["plain_graph_ms"] = timed(lambda: S.step_graph(k), max(1, args.steps // 2)) / k
+        S.step(k)
+        out["plain_window_ms"] = timed(lambda: S.step(k), args.steps)
         out["plain_shape"] = S.launch_shape()
         S.close()
 
@@ -544,6 +563,8 @@ def main():
 
     if args.only is not None:
         print(json.dumps({"only": args.only, "plain_ms": plain_ms, "prot_ms": prot_ms,
+                          "plain_graph_ms": out.get("plain_graph_ms"),
+                          "plain_window_ms": out.get("plain_window_ms"),
                           "prot_ms_input_check": out.get("prot_ms_input_check"),
                           "online_ms_per_sweep": online_ms,
                           "online_ms_input_check": out.get("online_ms_input_check"),
@@ -619,13 +640,16 @@ def main():
                                      for cs in ("f64", "f32comp")},
         "launch_shapes": {"plain": out.get("plain_shape"),
                           "prot": out.get(f"prot_shape_{args.csum}")},
-        "overhead_offline_pct": round((offline_ms / (k * plain_ms) - 1) * 100, 2),
+        # each against the plain sweep in the same harness (single calls, graphs, windows)
+        "plain_gpts_graph": round(gpts(out["plain_graph_ms"]), 3),
+        "plain_gpts_windows": round(gpts(out["plain_window_ms"], k), 3),
+        "overhead_offline_pct": round((offline_ms / out["plain_window_ms"] - 1) * 100, 2),
         "overhead_offline_input_check_pct": round(
-            (out["offline_ms_input_check"] / (k * plain_ms) - 1) * 100, 2),
-        "overhead_online_pct": round((online_ms / plain_ms - 1) * 100, 2),
+            (out["offline_ms_input_check"] / out["plain_window_ms"] - 1) * 100, 2),
+        "overhead_online_pct": round((online_ms / out["plain_graph_ms"] - 1) * 100, 2),
         "overhead_prot_kernel_pct": round((prot_ms / plain_ms - 1) * 100, 2),
         "overhead_online_input_check_pct": round(
-            (out["online_ms_input_check"] / plain_ms - 1) * 100, 2),
+            (out["online_ms_input_check"] / out["plain_graph_ms"] - 1) * 100, 2),
         "overhead_prot_kernel_input_check_pct": round(
             (out["prot_ms_input_check"] / plain_ms - 1) * 100, 2),
         "paper_context": "paper: <8% ABFT overhead, Xeon E5-2640 v4, 8 OpenMP threads, "
