@@ -416,16 +416,46 @@ def main():
     del u0_np, C_np
     stream.synchronize()
 
+    import tempfile
+    tune_dir = tempfile.mkdtemp(prefix="abft_bench_")
+    ncache = [0]
+
     def make(mode, tune=True, **kw):
-        """A context on a fresh copy of u0; every variant gets the same autotuning budget."""
+        """A context on a fresh copy of u0; every variant gets the same autotuning budget.  The
+        shape the autotuner keeps is written to a cache file of the context's own (the given
+        --tuning-cache when not tuning), read back by plain_twin."""
         with torch.cuda.stream(stream):
             u = u0.clone()
         stream.synchronize()
-        S = abft.Stencil(u, W.THERMAL_TAPS, C=C, mode=mode, stream=stream,
-                         tuning_cache=args.tuning_cache, **kw)
+        cache = args.tuning_cache
+        if tune and not args.no_tune:
+            ncache[0] += 1
+            cache = os.path.join(tune_dir, f"ctx{ncache[0]}.txt")
+        S = abft.Stencil(u, W.THERMAL_TAPS, C=C, mode=mode, stream=stream, tuning_cache=cache,
+                         **kw)
+        S.cache_file = cache
         if tune and not args.no_tune:
             S.autotune()
         return S
+
+    def plain_twin(S):
+        """The plain sweep in the launch shape of context S (a tuning-cache line for the plain
+        variant carrying S's tuned shape), so that an overhead compares the two in one shape and
+        measures the ABFT work alone; None when S's shape is not known."""
+        try:
+            with open(S.cache_file) as f:
+                shape = [ln.split()[-6:] for ln in f if ln.strip()][-1]
+        except (OSError, IndexError, TypeError):
+            return None
+        ncache[0] += 1
+        path = os.path.join(tune_dir, f"twin{ncache[0]}.txt")
+        with open(path, "w") as f:
+            f.write(f"0 {nx} {ny} {nz} 0 0 " + " ".join(shape) + "\n")
+        with torch.cuda.stream(stream):
+            u = u0.clone()
+        stream.synchronize()
+        return abft.Stencil(u, W.THERMAL_TAPS, C=C, mode="none", stream=stream,
+                            tuning_cache=path)
 
     def timed(fn, n):
         """HIP events on the context's stream around n calls; returns ms per call."""
@@ -451,20 +481,26 @@ def main():
         del a, b
 
     # ---- plain sweep: the overhead baseline and the dominant kernel of an offline window ----
-    # Each protected form is compared with the plain sweep timed the same way: single-sweep
-    # calls for the protected kernel alone, graphs of k sweeps for online ABFT, step(k) calls
-    # for offline windows.
+    # Each protected form is compared with the plain sweep in the same launch shape (the shape
+    # the autotuner kept for the protected form) and timed the same way (single-sweep calls for
+    # the protected kernel alone, graphs of k sweeps for online ABFT, step(k) calls for offline
+    # windows), the two timed in alternation (best of `rounds` groups each), so that neither
+    # drift nor a different tuning outcome between them enters the overhead.
+    def paired(fa, fb, n, rounds=4):
+        ta = tb = float("inf")
+        for _ in range(rounds):
+            ta = min(ta, timed(fa, n))
+            tb = min(tb, timed(fb, n))
+        return ta, tb
+
     plain_ms = None
-    if args.only in (None, "plain"):
-        S = make("none")
-        S.step(5)
-        plain_ms = timed(lambda: S.step(1), 10 * max(1, args.steps // 2))
-        S.step_graph(k)
-        out["plain_graph_ms"] = timed(lambda: S.step_graph(k), max(1, args.steps // 2)) / k
-        S.step(k)
-        out["plain_window_ms"] = timed(lambda: S.step(k), args.steps)
-        out["plain_shape"] = S.launch_shape()
-        S.close()
+    P = None
+    if args.only in (None, "plain", "prot", "online"):
+        P = make("none")
+        P.step(5)
+        P.step_graph(k)
+        plain_ms = timed(lambda: P.step(1), 10 * max(1, args.steps // 2))
+        out["plain_shape"] = P.launch_shape()
 
     # ---- protected sweep kernel alone (online, no locate launches) ----------------------------
     prot_ms = None
@@ -472,13 +508,19 @@ def main():
         for cs, ic in (("f64", False), ("f32comp", False), (args.csum, True)):
             S = make("online", threshold=1e-7, csum=cs, auto_correct=False, input_check=ic)
             S.step(5)
-            ms = timed(lambda: S.step(1), 10 * max(1, args.steps // 2))
+            T = plain_twin(S) or P
+            T.step(5)
+            pm, ms = paired(lambda: T.step(1), lambda: S.step(1), 5 * max(1, args.steps // 2))
+            if T is not P:
+                T.close()
             rep, _ = S.check()
             assert rep["rows_flagged"] == 0 and rep["mem_flagged"] == 0, rep
             key = "input_check" if ic else cs
             out[f"prot_ms_{key}"] = ms
+            out[f"plain_ms_vs_prot_{key}"] = pm
             out[f"prot_shape_{key}"] = S.launch_shape()
             out[f"prot_noise_{key}"] = rep["max_noise"]
+            plain_ms = min(plain_ms, pm)
             S.close()
         prot_ms = out[f"prot_ms_{args.csum}"]
 
@@ -489,12 +531,22 @@ def main():
             S = make("online", threshold=1e-7, csum=args.csum, auto_correct=True,
                      input_check=ic)
             S.step_graph(k)
-            ms = timed(lambda: S.step_graph(k), max(1, args.steps // 2)) / k
+            T = plain_twin(S) or P
+            T.step_graph(k)
+            pm, ms = paired(lambda: T.step_graph(k), lambda: S.step_graph(k),
+                            max(1, args.steps // 4))
+            if T is not P:
+                T.close()
             rep, _ = S.check()
             assert rep["rows_flagged"] == 0 and rep["mem_flagged"] == 0, rep
-            out["online_ms_input_check" if ic else "online_ms"] = ms
+            key = "online_ms_input_check" if ic else "online_ms"
+            out[key] = ms / k
+            out["plain_graph_ms_vs_" + key] = pm / k
             S.close()
         online_ms = out["online_ms"]
+        out["plain_graph_ms"] = out["plain_graph_ms_vs_online_ms"]
+    if P is not None:
+        P.close()
 
     # ---- headline: offline ABFT windows ---------------------------------------------------
     offline_ms = None
@@ -504,12 +556,25 @@ def main():
         S = make("offline", period=k, threshold=W.C5.eps, csum=args.csum, auto_correct=True,
                  input_check=True)
         S.step(k)
-        out["offline_ms_input_check"] = timed(lambda: S.step(k), args.steps)
+        T = plain_twin(S) or make("none")
+        T.step(k)
+        pm, out["offline_ms_input_check"] = paired(lambda: T.step(k), lambda: S.step(k),
+                                                   max(1, args.steps // 2))
+        out["plain_window_ms_vs_offline_input_check"] = pm
         rep, _ = S.check()
         assert rep["windows_flagged"] == 0 and rep["mem_flagged"] == 0, rep
         S.close()
+        T.close()
         S = make("offline", period=k, threshold=W.C5.eps, csum=args.csum, auto_correct=True,
                  input_check=False)
+        S.step(k)
+        T = plain_twin(S) or make("none")
+        T.step(k)
+        pm, out["offline_ms_paired"] = paired(lambda: T.step(k), lambda: S.step(k),
+                                              max(1, args.steps // 2))
+        out["plain_window_ms"] = pm
+        T.close()
+        # the headline: the same context, W windows of warm-up, then exactly K timed windows
         for _ in range(args.warmup):
             S.step(k)
         torch.cuda.synchronize()
@@ -643,15 +708,21 @@ def main():
         # each against the plain sweep in the same harness (single calls, graphs, windows)
         "plain_gpts_graph": round(gpts(out["plain_graph_ms"]), 3),
         "plain_gpts_windows": round(gpts(out["plain_window_ms"], k), 3),
-        "overhead_offline_pct": round((offline_ms / out["plain_window_ms"] - 1) * 100, 2),
+        # each protected form over the plain sweep timed in its own harness, in alternation
+        "overhead_offline_pct": round(
+            (out["offline_ms_paired"] / out["plain_window_ms"] - 1) * 100, 2),
         "overhead_offline_input_check_pct": round(
-            (out["offline_ms_input_check"] / out["plain_window_ms"] - 1) * 100, 2),
-        "overhead_online_pct": round((online_ms / out["plain_graph_ms"] - 1) * 100, 2),
-        "overhead_prot_kernel_pct": round((prot_ms / plain_ms - 1) * 100, 2),
+            (out["offline_ms_input_check"] / out["plain_window_ms_vs_offline_input_check"] - 1)
+            * 100, 2),
+        "overhead_online_pct": round(
+            (online_ms / out["plain_graph_ms_vs_online_ms"] - 1) * 100, 2),
+        "overhead_prot_kernel_pct": round(
+            (prot_ms / out[f"plain_ms_vs_prot_{args.csum}"] - 1) * 100, 2),
         "overhead_online_input_check_pct": round(
-            (out["online_ms_input_check"] / out["plain_graph_ms"] - 1) * 100, 2),
+            (out["online_ms_input_check"] / out["plain_graph_ms_vs_online_ms_input_check"] - 1)
+            * 100, 2),
         "overhead_prot_kernel_input_check_pct": round(
-            (out["prot_ms_input_check"] / plain_ms - 1) * 100, 2),
+            (out["prot_ms_input_check"] / out["plain_ms_vs_prot_input_check"] - 1) * 100, 2),
         "paper_context": "paper: <8% ABFT overhead, Xeon E5-2640 v4, 8 OpenMP threads, "
                          "512x512x8 fp32 HotSpot3D tiles (CPU, other hardware)",
         "cpu_baseline": cpu,

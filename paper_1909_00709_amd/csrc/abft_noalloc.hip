@@ -5,6 +5,8 @@
 // call's contents (the run clears what must start at zero); calls that overlap on one GPU race.
 #include <mutex>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "abft_internal.h"
 
 // The workspace.  In host code its name is only a stand-in for the symbol: its device address
@@ -74,6 +76,10 @@ extern "C" abft_status abft_stencil_run_noalloc(const abft_problem* p, const abf
                                                 int64_t nsweeps, void* hip_stream,
                                                 abft_report* out)
 {
+    roctxRangePushA("abft_stencil_run_noalloc");
+    struct Pop {
+        ~Pop() { roctxRangePop(); }
+    } pop;
     try {
         abft::NoAllocLayout L{};
         abft_status s = abft::noalloc_layout(p, o, faults, nfaults,
