@@ -74,12 +74,15 @@ def bench_batch(stream, timed, tune=True, chunk=50):
     res = {"workload": f"{len(shapes)} fp32 thermal grids, 64..256 x 64..256 x 4..32 "
                        f"({npts / 1e6:.1f} M points), online threshold {W.C4_EPS}",
            "grids": len(shapes), "points": npts}
-    for name, mode, ic in (("online", "online", False), ("online_input_check", "online", True),
-                           ("none", "none", False)):
+    # prot_kernel: the protected batched sweep without the locate launch (auto_correct off)
+    for name, mode, ic, ac in (("online", "online", False, True),
+                               ("online_input_check", "online", True, True),
+                               ("prot_kernel", "online", False, False),
+                               ("none", "none", False, True)):
         with torch.cuda.stream(stream):
             grids = [(u.clone(), c) for u, c in dev]
         B = abft.Batch(grids, W.THERMAL_TAPS, mode=mode, threshold=W.C4_EPS, stream=stream,
-                       input_check=ic)
+                       input_check=ic, auto_correct=ac)
         if tune:
             B.autotune()
         B.step_graph(chunk)
@@ -95,6 +98,8 @@ def bench_batch(stream, timed, tune=True, chunk=50):
                                        * 100, 2)
     res["overhead_online_input_check_pct"] = round(
         (res["online_input_check_ms_per_sweep"] / res["none_ms_per_sweep"] - 1) * 100, 2)
+    res["overhead_prot_kernel_pct"] = round(
+        (res["prot_kernel_ms_per_sweep"] / res["none_ms_per_sweep"] - 1) * 100, 2)
     # the same grids, one context each, stepped one after another (eager launches)
     ctxs = []
     for u, c in dev:

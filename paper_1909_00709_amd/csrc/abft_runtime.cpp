@@ -1049,8 +1049,8 @@ abft_status batch_autotune(abft_ctx* c)
     }
     const int nb = (int)base.size();
     struct Best {
-        float ms = 1e30f;
-        abft_ctx::Class k;
+        float ms = 1e30f, ms2 = 1e30f;  // the fastest and the runner-up
+        abft_ctx::Class k, k2;
     };
     std::vector<std::vector<Best>> best(nb, std::vector<Best>(nb));
     BatchArgs b = batch_args(c, c->t, nullptr, 0);
@@ -1098,9 +1098,15 @@ abft_status batch_autotune(abft_ctx* c)
                             (void)hipStreamSynchronize(c->stream);
                             continue;
                         }
-                        if (ms < best[i][j].ms) {
-                            best[i][j].ms = ms;
-                            best[i][j].k = L;
+                        Best& bb = best[i][j];
+                        if (ms < bb.ms) {
+                            bb.ms2 = bb.ms;
+                            bb.k2 = bb.k;
+                            bb.ms = ms;
+                            bb.k = L;
+                        } else if (ms < bb.ms2) {
+                            bb.ms2 = ms;
+                            bb.k2 = L;
                         }
                     }
         }
@@ -1114,13 +1120,67 @@ abft_status batch_autotune(abft_ctx* c)
                 f[j + 1] = f[i] + best[i][j].ms;
                 from[j + 1] = i;
             }
-    std::vector<abft_ctx::Class> chosen;
-    for (int j = nb; j > 0 && from[j] >= 0; j = from[j]) chosen.push_back(best[from[j]][j - 1].k);
-    cleanup();
-    if (chosen.empty() || f[nb] >= 1e29f)
+    std::vector<std::pair<int, int>> runs;
+    for (int j = nb; j > 0 && from[j] >= 0; j = from[j]) runs.push_back({from[j], j - 1});
+    if (runs.empty() || f[nb] >= 1e29f) {
+        cleanup();
+        (void)batch_single_class(c, 8, 1);
         return fail(c, ABFT_E_UNSUPPORTED, "no batched launch shape ran");
-    std::reverse(chosen.begin(), chosen.end());
-    c->classes = chosen;
+    }
+    std::reverse(runs.begin(), runs.end());
+    // Launch times of one run alone only approximate a whole sweep (the runs' launches follow
+    // one another, and configurations within a few percent trade places between timings): the
+    // split found above, the same split with one run in its runner-up configuration, and the
+    // two best one-launch layouts are timed again as whole sweeps, in alternation, and the
+    // fastest is kept.
+    std::vector<std::vector<abft_ctx::Class>> finalists;
+    {
+        std::vector<abft_ctx::Class> opt;
+        for (auto& r : runs) opt.push_back(best[r.first][r.second].k);
+        finalists.push_back(opt);
+        for (size_t q = 0; q < runs.size(); ++q) {
+            const Best& bb = best[runs[q].first][runs[q].second];
+            if (bb.ms2 >= 1e29f) continue;
+            std::vector<abft_ctx::Class> alt = opt;
+            alt[q] = bb.k2;
+            finalists.push_back(alt);
+        }
+        const Best& all = best[0][nb - 1];
+        if (runs.size() > 1 && all.ms < 1e29f) finalists.push_back({all.k});
+        if (all.ms2 < 1e29f) finalists.push_back({all.k2});
+    }
+    auto time_sweeps = [&](const std::vector<abft_ctx::Class>& layout, int reps) -> float {
+        c->classes = layout;
+        if (batch_layout(c)) return -1.f;
+        bool ok = true;
+        for (size_t k = 0; ok && k < c->classes.size(); ++k)
+            ok = launch_class(c, c->classes[k], b, k == 0) == hipSuccess;
+        ok = ok && hipEventRecord(e0, c->stream) == hipSuccess;
+        for (int r = 0; ok && r < reps; ++r)
+            for (size_t k = 0; ok && k < c->classes.size(); ++k)
+                ok = launch_class(c, c->classes[k], b, k == 0) == hipSuccess;
+        float ms = 0.f;
+        ok = ok && hipEventRecord(e1, c->stream) == hipSuccess &&
+             hipEventSynchronize(e1) == hipSuccess &&
+             hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(c->stream);
+            return -1.f;
+        }
+        return ms / reps;
+    };
+    std::vector<float> fin(finalists.size(), 1e30f);
+    for (int round = 0; round < 5; ++round)
+        for (size_t q = 0; q < finalists.size(); ++q) {
+            const float ms = time_sweeps(finalists[q], 10);
+            if (ms > 0.f) fin[q] = std::min(fin[q], ms);
+        }
+    size_t pick = 0;
+    for (size_t q = 1; q < finalists.size(); ++q)
+        if (fin[q] < fin[pick]) pick = q;
+    cleanup();
+    c->classes = finalists[pick];
     s = batch_layout(c);
     if (s) return s;
     // the timing launches cleared the next sweep's flag slots as a sweep would; clear this

@@ -278,34 +278,47 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
         }
     };
 
-    // The checksums the epilogue's prediction reads for this lane's first plane (its own
-    // row's, the neighbouring rows' and the constant term's) are loaded now, so that their
-    // latency hides behind the march instead of adding to the end of every tile.  Radius 2
-    // skips this: its five register planes leave no room for the ten values across the march
-    // (they would halve the wavefronts a SIMD can hold).
-    constexpr bool kPrefetch = RAD == 1;
+    // The prediction of every row and plane of the tile (Theorem 1, Eq.(5)) depends only on the
+    // previous checksums and the constant term's, except for the x-boundary term of the input
+    // row, which the march forms: the lanes of each row take the tile's planes in parallel and
+    // leave that partial prediction in an LDS table before the march.  Their loads are issued
+    // ahead of the first planes' and overlap them, so no checksum load sits in the epilogue.
     auto brow = [&](int z2, int y2) -> double {
         const int mz = map_coord(z2, nz, bc), my = map_coord(y2, ny, bc);
         if (mz < 0 || my < 0) return (double)nx * (double)g;
         return a.Bt[(size_t)mz * ny + my];
     };
-    double pb0 = 0.0, pcb = 0.0, pfy[RAD][2], pfz[RAD][2];
-#pragma unroll
-    for (int d = 0; d < RAD; ++d) pfy[d][0] = pfy[d][1] = pfz[d][0] = pfz[d][1] = 0.0;
+    // checksum, boundary-term, input-sum, weighted-sum and partial-prediction tables: [TY][tz]
+    // doubles each, after the two plane buffers (the input-sum and weighted-sum tables only
+    // with the input-side check; the partial predictions then follow them)
+    double* tabS = reinterpret_cast<double*>(smem_raw + (size_t)2 * plane_elems * sizeof(T));
+    double* tabE = tabS + TY * a.tz;
+    double* tabI = tabE + TY * a.tz;
+    double* tabW = tabI + TY * a.tz;
+    double* tabP = kMemChk ? tabW + TY * a.tz : tabI;
     unsigned long long nknown = 0ull;
     if constexpr (kProt) {
         nknown = noise_known(a.cnt);
-        if (kPrefetch && row_ok && sl < z1 - z0) {
-            const int z = z0 + sl;
-            const size_t l = (size_t)z * ny + y;
-            pb0 = a.Bt[l];
-            pcb = a.cB[l];
+        if (row_ok) {
+            for (int pz = sl; pz < z1 - z0; pz += LPR) {
+                const int z = z0 + pz;
+                const size_t l = (size_t)z * ny + y;
+                const double b0 = a.Bt[l];
+                double bp = a.cB[l];
+                if (has(W_C)) bp += a.st.w[W_C] * b0;
 #pragma unroll
-            for (int d = 0; d < RAD; ++d) {
-                if (has(w_slot(1, d + 1, -1))) pfy[d][0] = brow(z, y - d - 1);
-                if (has(w_slot(1, d + 1, 1))) pfy[d][1] = brow(z, y + d + 1);
-                if (has(w_slot(2, d + 1, -1))) pfz[d][0] = brow(z - d - 1, y);
-                if (has(w_slot(2, d + 1, 1))) pfz[d][1] = brow(z + d + 1, y);
+                for (int d = 1; d <= RAD; ++d) {
+                    if (has(w_slot(0, d, -1))) bp += a.st.w[w_slot(0, d, -1)] * b0;
+                    if (has(w_slot(0, d, 1))) bp += a.st.w[w_slot(0, d, 1)] * b0;
+                }
+#pragma unroll
+                for (int d = 1; d <= RAD; ++d) {
+                    if (has(w_slot(1, d, -1))) bp += a.st.w[w_slot(1, d, -1)] * brow(z, y - d);
+                    if (has(w_slot(1, d, 1))) bp += a.st.w[w_slot(1, d, 1)] * brow(z, y + d);
+                    if (has(w_slot(2, d, -1))) bp += a.st.w[w_slot(2, d, -1)] * brow(z - d, y);
+                    if (has(w_slot(2, d, 1))) bp += a.st.w[w_slot(2, d, 1)] * brow(z + d, y);
+                }
+                tabP[r * a.tz + pz] = bp;
             }
         }
     }
@@ -321,12 +334,6 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
             load_halo(hn, z0 + 1);
         }
     }
-    // checksum, boundary-term, input-sum and weighted-sum tables: [TY][tz] doubles each,
-    // after the two plane buffers
-    double* tabS = reinterpret_cast<double*>(smem_raw + (size_t)2 * plane_elems * sizeof(T));
-    double* tabE = tabS + TY * a.tz;
-    double* tabI = tabE + TY * a.tz;
-    double* tabW = tabI + TY * a.tz;
     // the x-boundary terms: for the prediction unless they cancel exactly, and for the offline
     // record when one is kept
     const bool xt = a.st.xterms != 0;
@@ -594,34 +601,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
                     if (a.Wn != nullptr) a.Wn[l] = tabW[r * a.tz + pz];
                 }
                 if constexpr (kProt) {
-                    // Theorem 1 (Eq.(5)) on the checksum plane: the x shifts become the
-                    // boundary term e of the input row, the y and z shifts read the
-                    // neighbouring rows' checksums (loaded before the march for the first
-                    // plane of the lane).
-                    const bool first = kPrefetch && pz == sl;
-                    const double b0 = first ? pb0 : a.Bt[l];
-                    double bp = first ? pcb : a.cB[l];
-                    if (has(W_C)) bp += a.st.w[W_C] * b0;
-#pragma unroll
-                    for (int d = 1; d <= RAD; ++d) {
-                        if (has(w_slot(0, d, -1))) bp += a.st.w[w_slot(0, d, -1)] * b0;
-                        if (has(w_slot(0, d, 1))) bp += a.st.w[w_slot(0, d, 1)] * b0;
-                    }
+                    // Theorem 1 (Eq.(5)) on the checksum plane: the partial prediction formed
+                    // before the march, plus the x-boundary term of the input row
+                    double bp = tabP[r * a.tz + pz];
                     if (xt) bp += tabE[r * a.tz + pz];
-#pragma unroll
-                    for (int d = 1; d <= RAD; ++d) {
-                        if (has(w_slot(1, d, -1)))
-                            bp += a.st.w[w_slot(1, d, -1)] * (first ? pfy[d - 1][0] : brow(z, y - d));
-                        if (has(w_slot(1, d, 1)))
-                            bp += a.st.w[w_slot(1, d, 1)] * (first ? pfy[d - 1][1] : brow(z, y + d));
-                        if (has(w_slot(2, d, -1)))
-                            bp += a.st.w[w_slot(2, d, -1)] * (first ? pfz[d - 1][0] : brow(z - d, y));
-                        if (has(w_slot(2, d, 1)))
-                            bp += a.st.w[w_slot(2, d, 1)] * (first ? pfz[d - 1][1] : brow(z + d, y));
-                    }
                     if constexpr (kMemChk) {
                         a.Wn[l] = tabW[r * a.tz + pz];
-                        check_input_row(a, t, z, y, tabI[r * a.tz + pz], b0);
+                        check_input_row(a, t, z, y, tabI[r * a.tz + pz], a.Bt[l]);
                     }
                     // Section 3.4, written so that NaN and Inf mismatches are flagged
                     const double dlt = fabs(S - bp);
