@@ -280,9 +280,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
 
     // The prediction of every row and plane of the tile (Theorem 1, Eq.(5)) depends only on the
     // previous checksums and the constant term's, except for the x-boundary term of the input
-    // row, which the march forms: the lanes of each row take the tile's planes in parallel and
-    // leave that partial prediction in an LDS table before the march.  Their loads are issued
-    // ahead of the first planes' and overlap them, so no checksum load sits in the epilogue.
+    // row, which the march forms: the block's threads take the tile's (row, plane) pairs, rows
+    // fastest, so that neighbouring threads read neighbouring checksums, and leave that partial
+    // prediction in an LDS table before the march.  Their loads are issued ahead of the first
+    // planes' and overlap them, so no checksum load sits in the epilogue.
     auto brow = [&](int z2, int y2) -> double {
         const int mz = map_coord(z2, nz, bc), my = map_coord(y2, ny, bc);
         if (mz < 0 || my < 0) return (double)nx * (double)g;
@@ -297,29 +298,29 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
     double* tabW = tabI + TY * a.tz;
     double* tabP = kMemChk ? tabW + TY * a.tz : tabI;
     unsigned long long nknown = 0ull;
+    const int npairs = nrows * (z1 - z0);  // the tile's (row, plane) pairs
     if constexpr (kProt) {
         nknown = noise_known(a.cnt);
-        if (row_ok) {
-            for (int pz = sl; pz < z1 - z0; pz += LPR) {
-                const int z = z0 + pz;
-                const size_t l = (size_t)z * ny + y;
-                const double b0 = a.Bt[l];
-                double bp = a.cB[l];
-                if (has(W_C)) bp += a.st.w[W_C] * b0;
+        for (int q = tid; q < npairs; q += NT) {
+            const int rr = q % nrows, pz = q / nrows;
+            const int z = z0 + pz, yy = y0 + rr;
+            const size_t l = (size_t)z * ny + yy;
+            const double b0 = a.Bt[l];
+            double bp = a.cB[l];
+            if (has(W_C)) bp += a.st.w[W_C] * b0;
 #pragma unroll
-                for (int d = 1; d <= RAD; ++d) {
-                    if (has(w_slot(0, d, -1))) bp += a.st.w[w_slot(0, d, -1)] * b0;
-                    if (has(w_slot(0, d, 1))) bp += a.st.w[w_slot(0, d, 1)] * b0;
-                }
-#pragma unroll
-                for (int d = 1; d <= RAD; ++d) {
-                    if (has(w_slot(1, d, -1))) bp += a.st.w[w_slot(1, d, -1)] * brow(z, y - d);
-                    if (has(w_slot(1, d, 1))) bp += a.st.w[w_slot(1, d, 1)] * brow(z, y + d);
-                    if (has(w_slot(2, d, -1))) bp += a.st.w[w_slot(2, d, -1)] * brow(z - d, y);
-                    if (has(w_slot(2, d, 1))) bp += a.st.w[w_slot(2, d, 1)] * brow(z + d, y);
-                }
-                tabP[r * a.tz + pz] = bp;
+            for (int d = 1; d <= RAD; ++d) {
+                if (has(w_slot(0, d, -1))) bp += a.st.w[w_slot(0, d, -1)] * b0;
+                if (has(w_slot(0, d, 1))) bp += a.st.w[w_slot(0, d, 1)] * b0;
             }
+#pragma unroll
+            for (int d = 1; d <= RAD; ++d) {
+                if (has(w_slot(1, d, -1))) bp += a.st.w[w_slot(1, d, -1)] * brow(z, yy - d);
+                if (has(w_slot(1, d, 1))) bp += a.st.w[w_slot(1, d, 1)] * brow(z, yy + d);
+                if (has(w_slot(2, d, -1))) bp += a.st.w[w_slot(2, d, -1)] * brow(z - d, yy);
+                if (has(w_slot(2, d, 1))) bp += a.st.w[w_slot(2, d, 1)] * brow(z + d, yy);
+            }
+            tabP[rr * a.tz + pz] = bp;
         }
     }
 
@@ -586,12 +587,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int tile,
         if (a.E == nullptr) return;
     }
     __syncthreads();
-    // Epilogue: the segment's lanes take the tile's planes of their row in parallel.
-    const int nzt = z1 - z0;
+    // Epilogue: the block's threads take the tile's (row, plane) pairs, rows fastest, as before
+    // the march.
     double noise = 0.0;
-    if (row_ok) {
-        for (int pz = sl; pz < nzt; pz += LPR) {
-            const int z = z0 + pz;
+    {
+        for (int q = tid; q < npairs; q += NT) {
+            const int r = q % nrows, pz = q / nrows;
+            const int z = z0 + pz, y = y0 + r;
             const size_t l = (size_t)z * ny + y;
             if (a.E != nullptr) a.E[l] = tabE[r * a.tz + pz];
             if constexpr (kRowSum) {
