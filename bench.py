@@ -441,6 +441,11 @@ def main():
         S.cache_file = cache
         if tune and not args.no_tune:
             S.autotune()
+            if args.tuning_cache:
+                # the kept shape also goes to --tuning-cache (the last line of a key wins), so
+                # that a later untuned run, under a profiler say, launches the same shape
+                with open(cache) as f, open(args.tuning_cache, "a") as g:
+                    g.write(f.read())
         return S
 
     def plain_twin(S):

@@ -158,31 +158,12 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
         }
     };
 
-    // The input row sums the epilogue's prediction reads for this lane's first plane (the
-    // nine rows around it) and its constant-term sum, loaded now so that their latency hides
-    // behind the march.
     auto brow = [&](int z2, int y2) -> double {
         const int mz = map_coord(z2, nz, bc), my = map_coord(y2, ny, bc);
         if (mz < 0 || my < 0) return (double)nx * (double)g;
         return a.Bt[(size_t)mz * ny + my];
     };
-    double pre[3][3], pcb = 0.0;
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy) pre[dz][dy] = 0.0;
     unsigned long long nknown = 0ull;
-    if constexpr (kProt) {
-        nknown = noise_known(a.cnt);
-        if (row_ok && sl < z1 - z0) {
-            const int z = z0 + sl;
-            pcb = a.cB[(size_t)z * ny + y];
-#pragma unroll
-            for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-                for (int dy = -1; dy <= 1; ++dy) pre[dz + 1][dy + 1] = brow(z + dz, y + dy);
-        }
-    }
 
     // prologue: planes z0-1 and z0 into the ring, z0+1 in flight
     {
@@ -214,6 +195,37 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
     double* tabE = tabS + TY * a.tz;
     double* tabI = tabE + TY * a.tz;
     double* tabW = tabI + TY * a.tz;
+    double* tabP = kMemChk ? tabW + TY * a.tz : tabI;  // partial predictions
+    // The prediction of every row and plane of the tile (Theorem 1 for the box: the weight sums
+    // over dx times the nine input row sums, plus the constant term's) except the boundary
+    // terms the march forms, by the block's threads over the tile's (row, plane) pairs, rows
+    // fastest, into an LDS table; the loads overlap those of the planes in flight.
+    const int npairs = nrows * (z1 - z0);
+    if constexpr (kProt) {
+        nknown = noise_known(a.cnt);
+        for (int q = tid; q < npairs; q += NT) {
+            const int rr = q % nrows, pz = q / nrows;
+            const int z = z0 + pz, yy = y0 + rr;
+            double bp = a.cB[(size_t)z * ny + yy];
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy) {
+                    double wsum = 0.0;
+                    bool any = false;
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int sl_ = box_slot(dx, dy, dz);
+                        if (has(sl_)) {
+                            wsum += a.st.wb[sl_];
+                            any = true;
+                        }
+                    }
+                    if (any) bp += wsum * brow(z + dz, yy + dy);
+                }
+            tabP[rr * a.tz + pz] = bp;
+        }
+    }
     // the x-boundary terms: for the prediction unless they cancel exactly, and for the offline
     // record when one is kept
     const bool xt = a.st.xterms != 0;
@@ -360,11 +372,12 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
         if (a.E == nullptr) return;
     }
     __syncthreads();
-    const int nzt = z1 - z0;
+    // the block's threads take the tile's (row, plane) pairs, rows fastest
     double noise = 0.0;
-    if (row_ok) {
-        for (int pz = sl; pz < nzt; pz += LPR) {
-            const int z = z0 + pz;
+    {
+        for (int q = tid; q < npairs; q += NT) {
+            const int r = q % nrows, pz = q / nrows;
+            const int z = z0 + pz, y = y0 + r;
             const size_t l = (size_t)z * ny + y;
             if (a.E != nullptr) a.E[l] = tabE[r * a.tz + pz];
             if constexpr (MODE != MODE_PLAIN) {
@@ -374,32 +387,13 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
                     if (a.Wn != nullptr) a.Wn[l] = tabW[r * a.tz + pz];
                 }
                 if constexpr (kProt) {
-                    // Theorem 1 for the box: the weight sums over dx times the nine input
-                    // row sums, plus the boundary terms formed in the march
-                    const bool first = pz == sl;
-                    double bp = (first ? pcb : a.cB[l]);
+                    // Theorem 1 for the box: the partial prediction formed before the march,
+                    // plus the boundary terms formed in it
+                    double bp = tabP[r * a.tz + pz];
                     if (xt) bp += tabE[r * a.tz + pz];
-#pragma unroll
-                    for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-                        for (int dy = -1; dy <= 1; ++dy) {
-                            double wsum = 0.0;
-                            bool any = false;
-#pragma unroll
-                            for (int dx = -1; dx <= 1; ++dx) {
-                                const int sl_ = box_slot(dx, dy, dz);
-                                if (has(sl_)) {
-                                    wsum += a.st.wb[sl_];
-                                    any = true;
-                                }
-                            }
-                            if (any)
-                                bp += wsum * (first ? pre[dz + 1][dy + 1] : brow(z + dz, y + dy));
-                        }
                     if constexpr (kMemChk) {
                         a.Wn[l] = tabW[r * a.tz + pz];
-                        check_input_row(a, t, z, y, tabI[r * a.tz + pz],
-                                        first ? pre[1][1] : a.Bt[l]);
+                        check_input_row(a, t, z, y, tabI[r * a.tz + pz], a.Bt[l]);
                     }
                     const double dlt = fabs(S - bp);
                     if (!(dlt <= a.eps * fabs(bp))) {
