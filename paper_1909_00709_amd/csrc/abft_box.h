@@ -61,6 +61,11 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
     const size_t pstride = (size_t)nx * (size_t)ny;
     const uint32_t bmask = a.st.bmask;
     auto has = [&](int slot) { return (bmask >> slot) & 1u; };
+    // every tap present: the march needs no per-point selection of the absent ones
+    const bool full = bmask == 0x7FFFFFFu;
+    T wt[27];  // the weights in the grid dtype, converted once
+#pragma unroll
+    for (int k = 0; k < 27; ++k) wt[k] = (T)a.st.wb[k];
 
     int flo = 0, fhi = 0;
     if (a.faults != nullptr && t >= 0 && t < a.fault_tmax) {
@@ -258,28 +263,33 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) acc[v] = (Acc)cc[c][v];
                 // taps in the order dz, dy, dx (absent taps contribute nothing, also next to
-                // non-finite values)
+                // non-finite values); with every tap present, no per-point selection
+                auto taps = [&](auto every) {
+                    constexpr bool kEvery = decltype(every)::value;
 #pragma unroll
-                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-                    for (int dy = -1; dy <= 1; ++dy) {
-                        const T* rw = rows[dz + 1][dy + 1];
-                        T m[VEC];
-                        V::load(rw + x, m);
-                        const T xl = rw[x - 1], xr = rw[x + VEC];
+                        for (int dy = -1; dy <= 1; ++dy) {
+                            const T* rw = rows[dz + 1][dy + 1];
+                            T m[VEC];
+                            V::load(rw + x, m);
+                            const T xl = rw[x - 1], xr = rw[x + VEC];
 #pragma unroll
-                        for (int dx = -1; dx <= 1; ++dx) {
-                            const int sl_ = box_slot(dx, dy, dz);
-                            const Acc wv = (Acc)a.st.wb[sl_];
-                            const bool on = has(sl_);
+                            for (int dx = -1; dx <= 1; ++dx) {
+                                const int sl_ = box_slot(dx, dy, dz);
+                                const Acc wv = (Acc)wt[sl_];
+                                const bool on = kEvery || has(sl_);
 #pragma unroll
-                            for (int v = 0; v < VEC; ++v) {
-                                const int idx = v + dx;
-                                const T val = idx < 0 ? xl : (idx >= VEC ? xr : m[idx]);
-                                acc[v] = fma(wv, on ? (Acc)val : Acc(0), acc[v]);
+                                for (int v = 0; v < VEC; ++v) {
+                                    const int idx = v + dx;
+                                    const T val = idx < 0 ? xl : (idx >= VEC ? xr : m[idx]);
+                                    acc[v] = fma(wv, on ? (Acc)val : Acc(0), acc[v]);
+                                }
                             }
                         }
-                    }
+                };
+                if (full) taps(std::true_type{});
+                else taps(std::false_type{});
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) o[c][v] = (T)acc[v];
             } else {
