@@ -4,11 +4,13 @@
 //
 // The decomposition is that of the star sweep (abft_sweep.h): a block of NW wavefronts owns
 // TY whole rows of a slab of planes and marches along z, each row held by LPR lanes.  A box
-// tap reads the in-plane neighbours of planes z-1 and z+1 as well, so the block keeps a ring
-// of three LDS plane buffers, each with the block's rows, one halo row above and below and
-// the x-ghosts: at step z they hold the planes z-1, z, z+1; plane z+1 is written into the
-// buffer of plane z-2 at the start of the step, after a barrier that ends the previous step's
-// reads (a fourth buffer would save that barrier but halves the blocks a CU can hold).
+// tap reads the in-plane neighbours of planes z-1 and z+1 as well.  The march visits each input
+// plane p once: it goes through LDS (the block's rows, one halo row above and below, the
+// x-ghosts), each lane gathers its 3 x 3 in-plane neighbourhood from there once, and the nine
+// values feed three accumulators held in registers, those of output planes p+1 (taps dz = -1),
+// p (dz = 0) and p-1 (dz = +1), which is then complete.  Every output so receives its taps in
+// the order dz, dy, dx.  Two LDS plane buffers alternate: plane p+1 is written into the one
+// plane p-1 used, after the step's single barrier.
 //
 // Theorem 1 for a box stencil: the row sum of the output row (z, y) is the constant term's
 // row sum plus, for every (dy, dz), the weight sum over dx times the input row sum of row
@@ -34,7 +36,7 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
     constexpr int TY = NW * RPW;
     constexpr int SEGW = LPR * VEC;
     constexpr int HMAX = (NCH * SEGW + NT * VEC - 1) / (NT * VEC);
-    constexpr int NB = 3;  // LDS plane buffers in the ring
+    constexpr int NB = 2;  // LDS plane buffers, alternating
 
     T* lds = reinterpret_cast<T*>(smem_raw);
     const int64_t t = a.t_off + (a.t_base != nullptr ? *a.t_base : 0);
@@ -75,7 +77,7 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
     const int yh0 = map_coord(y0 - 1, ny, bc), yh1 = map_coord(y0 + nrows, ny, bc);
     const int lh1 = nrows + 1;
 
-    T nu[NCH][VEC], cc[NCH][VEC], nc[NCH][VEC];
+    T nu[NCH][VEC], cn[NCH][VEC];  // the next input plane's rows, the next output's C
     T hn[2][HMAX][VEC];
 
     auto load_u = [&](T (&d)[NCH][VEC], int zz) {
@@ -134,10 +136,10 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
             else if (bc == ABFT_BC_PERIODIC) row[-1] = d[VEC - 1];
         }
     };
-    // Plane zz (its mapped index mz, or -1 for a plane of constant ghosts) into its buffer.
-    auto buf_of = [&](int zz) { return lds + ((zz % NB + NB) % NB) * plane_elems; };
-    auto put_plane = [&](int zz, const T (&own)[NCH][VEC], const T (&hal)[2][HMAX][VEC]) {
-        T* buf = buf_of(zz);
+    // A plane (the rows loaded for it, constant ghosts for a plane outside the grid) into LDS
+    // buffer b.
+    auto buf_of = [&](int b) { return lds + (b % NB) * plane_elems; };
+    auto put_plane = [&](T* buf, const T (&own)[NCH][VEC], const T (&hal)[2][HMAX][VEC]) {
         if (row_ok) {
             T* row = buf + (r + 1) * stride + VEC;
 #pragma unroll
@@ -170,21 +172,19 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
     };
     unsigned long long nknown = 0ull;
 
-    // prologue: planes z0-1 and z0 into the ring, z0+1 in flight
+    // prologue: plane z0-1 into buffer 0; plane z0 and the constant term of output z0 in flight
     {
         T pu[NCH][VEC], ph[2][HMAX][VEC];
         load_u(pu, map_coord(z0 - 1, nz, bc));
         load_halo(ph, map_coord(z0 - 1, nz, bc));
-        put_plane(z0 - 1, pu, ph);
-        load_u(pu, z0);
-        load_halo(ph, z0);
-        put_plane(z0, pu, ph);
+        put_plane(buf_of(0), pu, ph);
     }
-    load_u(nu, map_coord(z0 + 1, nz, bc));
-    load_halo(hn, map_coord(z0 + 1, nz, bc));
-    load_c(cc, z0);
+    load_u(nu, z0);
+    load_halo(hn, z0);
+    load_c(cn, z0);
 
-    // this lane's neighbour row for the boundary terms (lanes 0..8 of a row), its weights
+    // the boundary terms: lane j < 9 of a row takes, at each step, the row y + ldy of the
+    // plane in LDS, for the output ldz planes before it; its weights
     const int ldz = sl / 3 - 1, ldy = sl % 3 - 1;
     double lwm = 0.0, lwp = 0.0;
     bool lhm = false, lhp = false;
@@ -237,45 +237,43 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
     const bool keep_e = (kProt && xt) || a.E != nullptr;
     using Acc = T;
 
-    for (int z = z0; z < z1; ++z) {
-        if (z > z0) __syncthreads();  // the previous step's reads of plane z-2 are over
-        put_plane(z + 1, nu, hn);
-        if (z + 1 < z1) {
-            load_u(nu, map_coord(z + 2, nz, bc));
-            load_halo(hn, map_coord(z + 2, nz, bc));
-            load_c(nc, z + 1);
-        }
-        __syncthreads();
-
-        const T* rows[3][3];  // [dz + 1][dy + 1]: the input rows around (z, y) in LDS
+    T acc[3][NCH][VEC];  // at step p: the accumulators of outputs p-1, p, p+1
+    const int nsteps = z1 - z0 + 2;
+    for (int st = 0; st < nsteps; ++st) {
+        const int p = z0 - 1 + st;  // the input plane of this step
+        __syncthreads();  // plane p is in its buffer; the reads of the other one are over
+        // plane p+1 into the other buffer, and output p+1 starts from its constant term.  The
+        // loads ahead are not conditional on the step (near the slab's end they repeat its last
+        // plane), so that no register copy has to wait for them.
+        put_plane(buf_of(st + 1), nu, hn);
+        load_u(nu, map_coord(min(p + 2, z1), nz, bc));
+        load_halo(hn, map_coord(min(p + 2, z1), nz, bc));
 #pragma unroll
-        for (int dz = -1; dz <= 1; ++dz)
+        for (int c = 0; c < NCH; ++c)
 #pragma unroll
-            for (int dy = -1; dy <= 1; ++dy)
-                rows[dz + 1][dy + 1] = buf_of(z + dz) + (r + 1 + dy) * stride + VEC;
+            for (int v = 0; v < VEC; ++v) acc[2][c][v] = (Acc)cn[c][v];
+        load_c(cn, min(p + 2, z1 - 1));
+        const T* prow = buf_of(st) + (r + 1) * stride + VEC;  // row y of plane p in LDS
 
-        T o[NCH][VEC];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int x = c * SEGW + sl * VEC;
             if (row_ok && x < nx) {
-                Acc acc[VEC];
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) acc[v] = (Acc)cc[c][v];
-                // taps in the order dz, dy, dx (absent taps contribute nothing, also next to
-                // non-finite values); with every tap present, no per-point selection
+                // each in-plane neighbour once, into the three outputs it is a tap of (tap
+                // (dx, dy, dz) of output p - dz); absent taps contribute nothing, also next to
+                // non-finite values; with every tap present, no per-point selection
                 auto taps = [&](auto every) {
                     constexpr bool kEvery = decltype(every)::value;
 #pragma unroll
-                    for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy) {
+                        const T* rw = prow + dy * stride;
+                        T m[VEC];
+                        V::load(rw + x, m);
+                        const T xl = rw[x - 1], xr = rw[x + VEC];
 #pragma unroll
-                        for (int dy = -1; dy <= 1; ++dy) {
-                            const T* rw = rows[dz + 1][dy + 1];
-                            T m[VEC];
-                            V::load(rw + x, m);
-                            const T xl = rw[x - 1], xr = rw[x + VEC];
+                        for (int dx = -1; dx <= 1; ++dx)
 #pragma unroll
-                            for (int dx = -1; dx <= 1; ++dx) {
+                            for (int dz = -1; dz <= 1; ++dz) {
                                 const int sl_ = box_slot(dx, dy, dz);
                                 const Acc wv = (Acc)wt[sl_];
                                 const bool on = kEvery || has(sl_);
@@ -283,99 +281,121 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
                                 for (int v = 0; v < VEC; ++v) {
                                     const int idx = v + dx;
                                     const T val = idx < 0 ? xl : (idx >= VEC ? xr : m[idx]);
-                                    acc[v] = fma(wv, on ? (Acc)val : Acc(0), acc[v]);
+                                    acc[1 - dz][c][v] =
+                                        fma(wv, on ? (Acc)val : Acc(0), acc[1 - dz][c][v]);
                                 }
                             }
-                        }
+                    }
                 };
                 if (full) taps(std::true_type{});
                 else taps(std::false_type{});
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) o[c][v] = (T)acc[v];
-            } else {
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) o[c][v] = T(0);
             }
         }
 
-        // Fault model of Section 5.1 (as in the star sweep).
-        for (int f = flo; f < fhi; ++f) {
-            const abft_fault F = a.faults[f];
-            if (F.kind == ABFT_FAULT_STORE && F.attempt == a.attempt && F.grid == a.grid &&
-                F.z == z && F.y == y && row_ok) {
-#pragma unroll
-                for (int c = 0; c < NCH; ++c)
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v)
-                        if (c * SEGW + sl * VEC + v == F.x) {
-                            if constexpr (sizeof(T) == 4) {
-                                o[c][v] = __builtin_bit_cast(
-                                    T, __builtin_bit_cast(uint32_t, o[c][v]) ^ (1u << F.bit));
-                            } else {
-                                o[c][v] = __builtin_bit_cast(
-                                    T, __builtin_bit_cast(uint64_t, o[c][v]) ^ (1ull << F.bit));
-                            }
-                        }
-            }
-        }
-
-        if (row_ok) {
-            T* dst = uout + (size_t)z * pstride + (size_t)y * nx;
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                const int x = c * SEGW + sl * VEC;
-                if (x < nx) V::store_nt(dst + x, o[c]);
-            }
-        }
-
-        if constexpr (MODE != MODE_PLAIN) {
-            const double S = row_sum<CS, LPR, NCH, VEC>(o);
-            if (row_ok && sl == 0) tabS[r * a.tz + (z - z0)] = S;
-        }
         if constexpr (kMemChk) {
-            // the input row as read (from the ring) and the output's index-weighted sum, as in
-            // the star sweep
-            T ci[NCH][VEC];
+            // the input row (p, y) as read (from LDS), for the input-side check
+            if (p >= z0 && p < z1) {
+                T ci[NCH][VEC];
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                const int x = c * SEGW + sl * VEC;
-                if (row_ok && x < nx) {
-                    V::load(rows[1][1] + x, ci[c]);
-                } else {
+                for (int c = 0; c < NCH; ++c) {
+                    const int x = c * SEGW + sl * VEC;
+                    if (row_ok && x < nx) {
+                        V::load(prow + x, ci[c]);
+                    } else {
 #pragma unroll
-                    for (int v = 0; v < VEC; ++v) ci[c][v] = T(0);
+                        for (int v = 0; v < VEC; ++v) ci[c][v] = T(0);
+                    }
                 }
-            }
-            const double Si = row_sum<CS, LPR, NCH, VEC>(ci);
-            const double Sw = weighted_row_sum<LPR, NCH, VEC>(o, (double)(sl * VEC + 1));
-            if (row_ok && sl == 0) {
-                tabI[r * a.tz + (z - z0)] = Si;
-                tabW[r * a.tz + (z - z0)] = Sw;
-            }
-        }
-        if constexpr (MODE == MODE_CSUM) {
-            if (a.Wn != nullptr) {  // offline: the weighted sums of the checkpoint to be
-                const double Sw = weighted_row_sum<LPR, NCH, VEC>(o, (double)(sl * VEC + 1));
-                if (row_ok && sl == 0) tabW[r * a.tz + (z - z0)] = Sw;
+                const double Si = row_sum<CS, LPR, NCH, VEC>(ci);
+                if (row_ok && sl == 0) tabI[r * a.tz + (p - z0)] = Si;
             }
         }
         if (keep_e) {
-            // x-boundary terms of the nine input rows around (z, y): a shift dx = -1 reads
-            // G(-1) and drops u(nx-1); dx = +1 reads G(nx) and drops u(0).  Lane j < 9 of
-            // the row takes neighbour row j, and a 16-lane reduction sums them.
+            // x-boundary terms of the input row (p, y + ldy) for output p - ldz: a shift
+            // dx = -1 reads G(-1) and drops u(nx-1); dx = +1 reads G(nx) and drops u(0).  Per
+            // output, a 16-lane reduction sums its three rows of plane p.
             double part = 0.0;
             if (row_ok && sl < 9) {
-                const T* rw = buf_of(z + ldz) + (r + 1 + ldy) * stride + VEC;
+                const T* rw = prow + ldy * stride;
                 if (lhm) part += lwm * ((double)rw[-1] - (double)rw[nx - 1]);
                 if (lhp) part += lwp * ((double)rw[nx] - (double)rw[0]);
             }
-            const double e = row16_sum(part);
-            if (row_ok && sl == 0) tabE[r * a.tz + (z - z0)] = e;
+#pragma unroll
+            for (int k = -1; k <= 1; ++k) {
+                const double e = row16_sum(ldz == k ? part : 0.0);
+                const int zo = p - k;
+                if (zo >= z0 && zo < z1 && row_ok && sl == 0) {
+                    double& te = tabE[r * a.tz + (zo - z0)];
+                    te = k == -1 ? e : te + e;
+                }
+            }
+        }
+
+        // output p-1 is complete
+        const int z = p - 1;
+        if (z >= z0) {
+            T o[NCH][VEC];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const bool ok = row_ok && c * SEGW + sl * VEC < nx;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) o[c][v] = ok ? (T)acc[0][c][v] : T(0);
+            }
+
+            // Fault model of Section 5.1 (as in the star sweep).
+            for (int f = flo; f < fhi; ++f) {
+                const abft_fault F = a.faults[f];
+                if (F.kind == ABFT_FAULT_STORE && F.attempt == a.attempt && F.grid == a.grid &&
+                    F.z == z && F.y == y && row_ok) {
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v)
+                            if (c * SEGW + sl * VEC + v == F.x) {
+                                if constexpr (sizeof(T) == 4) {
+                                    o[c][v] = __builtin_bit_cast(
+                                        T, __builtin_bit_cast(uint32_t, o[c][v]) ^ (1u << F.bit));
+                                } else {
+                                    o[c][v] = __builtin_bit_cast(
+                                        T, __builtin_bit_cast(uint64_t, o[c][v]) ^
+                                               (1ull << F.bit));
+                                }
+                            }
+                }
+            }
+
+            if (row_ok) {
+                T* dst = uout + (size_t)z * pstride + (size_t)y * nx;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const int x = c * SEGW + sl * VEC;
+                    if (x < nx) V::store_nt(dst + x, o[c]);
+                }
+            }
+
+            if constexpr (MODE != MODE_PLAIN) {
+                const double S = row_sum<CS, LPR, NCH, VEC>(o);
+                if (row_ok && sl == 0) tabS[r * a.tz + (z - z0)] = S;
+            }
+            if constexpr (kMemChk) {
+                // the output's index-weighted sum, as in the star sweep
+                const double Sw = weighted_row_sum<LPR, NCH, VEC>(o, (double)(sl * VEC + 1));
+                if (row_ok && sl == 0) tabW[r * a.tz + (z - z0)] = Sw;
+            }
+            if constexpr (MODE == MODE_CSUM) {
+                if (a.Wn != nullptr) {  // offline: the weighted sums of the checkpoint to be
+                    const double Sw = weighted_row_sum<LPR, NCH, VEC>(o, (double)(sl * VEC + 1));
+                    if (row_ok && sl == 0) tabW[r * a.tz + (z - z0)] = Sw;
+                }
+            }
         }
 #pragma unroll
         for (int c = 0; c < NCH; ++c)
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) cc[c][v] = nc[c][v];
+            for (int v = 0; v < VEC; ++v) {
+                acc[0][c][v] = acc[1][c][v];
+                acc[1][c][v] = acc[2][c][v];
+            }
     }
 
     if constexpr (MODE == MODE_PLAIN) {

@@ -1279,7 +1279,7 @@ size_t sweep_lds_bytes(int dtype, int nx, const SweepShape& s, bool input_check)
     const size_t es = dtype == ABFT_F32 ? 4 : 8;
     const size_t ty = (size_t)sweep_rows_per_block(s);
     const size_t pad = (size_t)std::max(s.vec, s.rad);
-    const size_t planes = s.box ? 3 : 2;  // the box sweep keeps a ring of three planes
+    const size_t planes = 2;  // two alternating plane buffers
     // checksum, boundary term[, input, weighted], partial prediction
     const size_t tables = input_check ? 5 : 3;
     return planes * (ty + 2 * s.rad) * (nx + 2 * pad) * es  // plane buffers with halo rows
