@@ -290,7 +290,10 @@ abft_status abft_stencil_inject(abft_ctx* ctx, const abft_fault* f, int32_t n);
 
 /* Times the candidate launch shapes on this context's grid (reads u0's current contents,
  * writes only the scratch buffer) and keeps the fastest; writes the tuning cache if one was
- * named.  Waits for the stream. */
+ * named.  For a batch context it times per-size-class layouts: the timing sweeps alternate
+ * each grid's two buffers as a run does, and the current grids, checksums and weighted sums
+ * are restored afterwards (the other buffer of each grid is overwritten).  Waits for the
+ * stream. */
 abft_status abft_stencil_autotune(abft_ctx* ctx);
 
 /* Frees the library's workspace.  NULL is allowed.  Waits for the context's stream. */

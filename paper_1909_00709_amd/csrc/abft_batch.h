@@ -24,7 +24,11 @@ __device__ __forceinline__ S load_const(const S* src)
 
 // The plain radius-1 variant fits three wavefronts per SIMD with no spill when asked to (168
 // registers instead of 172); the checksum variants would spill, and run slower, at that limit.
-template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int RAD, int BOX>
+// NCHB, NCHC: narrower chunk counts the launch also holds (radius-1 stars only), 0 for none; a
+// grid's descriptor says which of the three its rows take, so that grids of shorter rows share
+// the launch without idle chunks.
+template <typename T, int MODE, int CS, int LPR, int NCH, int VEC, int RAD, int BOX, int NCHB = 0,
+          int NCHC = 0>
 __global__ void __launch_bounds__(kBatchWaves * 64)
     __attribute__((amdgpu_waves_per_eu(MODE == MODE_PLAIN && RAD == 1 && !BOX && VEC > 1 ? 3 : 1)))
     sweep_batch_kernel(const BatchArgs b)
@@ -96,10 +100,27 @@ __global__ void __launch_bounds__(kBatchWaves * 64)
         a.faults = b.faults;
         a.fault_first = b.fault_first;
         a.fault_tmax = b.fault_tmax;
-        if constexpr (BOX)
+        if constexpr (BOX) {
             sweep_box_tile<T, MODE, CS, LPR, NCH, VEC, kBatchWaves>(a, gy, smem_raw);
-        else
-            sweep_tile<T, MODE, CS, LPR, NCH, VEC, 1, kBatchWaves, RAD>(a, gy, smem_raw);
+        } else {
+            auto tile = [&](auto nch) {
+                sweep_tile<T, MODE, CS, LPR, decltype(nch)::value, VEC, 1, kBatchWaves, RAD>(
+                    a, gy, smem_raw);
+            };
+            if constexpr (NCHB > 0) {
+                const int sub = load_const(&d->sub);
+                if constexpr (NCHC > 0) {
+                    if (sub == 2) tile(std::integral_constant<int, (NCHC > 0 ? NCHC : 1)>{});
+                    else if (sub == 1) tile(std::integral_constant<int, NCHB>{});
+                    else tile(std::integral_constant<int, NCH>{});
+                } else {
+                    if (sub == 1) tile(std::integral_constant<int, NCHB>{});
+                    else tile(std::integral_constant<int, NCH>{});
+                }
+            } else {
+                tile(std::integral_constant<int, NCH>{});
+            }
+        }
         if (!b.persistent) break;
         __syncthreads();
         it = __builtin_amdgcn_readfirstlane(sh_next);
@@ -208,6 +229,97 @@ int occupancy_dt(int mode, int csum, const SweepShape& s, size_t lds)
     int batch_occupancy_##NAME(int mode, int csum, const SweepShape& s, size_t lds)            \
     {                                                                                          \
         return occupancy_dt<T, RAD, BOX>(mode, csum, s, lds);                                  \
+    }
+
+// Launches holding several chunk counts (radius-1 stars, 16-byte accesses): 16 or 64 lanes
+// per row, chunk counts (4, 2, 1), (4, 2), (4, 1), (2, 1).
+#define ABFT_BATCH_MULTI(X)                                                                    \
+    X(16, 4, 2, 1)                                                                             \
+    X(16, 4, 2, 0)                                                                             \
+    X(16, 4, 1, 0)                                                                             \
+    X(16, 2, 1, 0)                                                                             \
+    X(64, 4, 2, 1)                                                                             \
+    X(64, 4, 2, 0)                                                                             \
+    X(64, 4, 1, 0)                                                                             \
+    X(64, 2, 1, 0)
+
+template <typename T, int MODE, int CS>
+hipError_t launch_batch_multi_t(const SweepShape& s, const BatchArgs& b, int nblocks, size_t lds,
+                                hipStream_t st)
+{
+    constexpr int VF = 16 / (int)sizeof(T);
+#define ABFT_MULTI_CASE(LPR_, A_, B_, C_)                                                      \
+    if (s.lpr == LPR_ && s.nch == A_ && s.nchb == B_ && s.nchc == C_ && s.vec == VF) {         \
+        auto kern = sweep_batch_kernel<T, MODE, CS, LPR_, A_, VF, 1, 0, B_, C_>;               \
+        static LdsAllowed lds_ok;                                                              \
+        if (hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds, lds_ok))        \
+            return e;                                                                          \
+        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kBatchWaves * 64), lds, st, b);           \
+        return hipGetLastError();                                                              \
+    }
+    ABFT_BATCH_MULTI(ABFT_MULTI_CASE)
+#undef ABFT_MULTI_CASE
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int MODE, int CS>
+int occupancy_multi_t(const SweepShape& s, size_t lds)
+{
+    constexpr int VF = 16 / (int)sizeof(T);
+    int n = 0;
+#define ABFT_MULTI_OCC(LPR_, A_, B_, C_)                                                       \
+    if (s.lpr == LPR_ && s.nch == A_ && s.nchb == B_ && s.nchc == C_ && s.vec == VF) {         \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                      \
+                &n, sweep_batch_kernel<T, MODE, CS, LPR_, A_, VF, 1, 0, B_, C_>,               \
+                kBatchWaves * 64, lds) != hipSuccess)                                          \
+            n = 1;                                                                             \
+        return n > 0 ? n : 1;                                                                  \
+    }
+    ABFT_BATCH_MULTI(ABFT_MULTI_OCC)
+#undef ABFT_MULTI_OCC
+    return 1;
+}
+#undef ABFT_BATCH_MULTI
+
+template <typename T>
+hipError_t launch_batch_multi_dt(int mode, int csum, const SweepShape& s, const BatchArgs& b,
+                                 int nblocks, size_t lds, hipStream_t st)
+{
+    if (mode == MODE_PLAIN) return launch_batch_multi_t<T, MODE_PLAIN, CS_F64>(s, b, nblocks, lds, st);
+    if constexpr (sizeof(T) == 4) {
+        if (csum == CS_F32C) {
+            if (mode == MODE_PROTM)
+                return launch_batch_multi_t<T, MODE_PROTM, CS_F32C>(s, b, nblocks, lds, st);
+            return launch_batch_multi_t<T, MODE_PROT, CS_F32C>(s, b, nblocks, lds, st);
+        }
+    }
+    if (mode == MODE_PROTM) return launch_batch_multi_t<T, MODE_PROTM, CS_F64>(s, b, nblocks, lds, st);
+    return launch_batch_multi_t<T, MODE_PROT, CS_F64>(s, b, nblocks, lds, st);
+}
+
+template <typename T>
+int occupancy_multi_dt(int mode, int csum, const SweepShape& s, size_t lds)
+{
+    if (mode == MODE_PLAIN) return occupancy_multi_t<T, MODE_PLAIN, CS_F64>(s, lds);
+    if constexpr (sizeof(T) == 4) {
+        if (csum == CS_F32C) {
+            if (mode == MODE_PROTM) return occupancy_multi_t<T, MODE_PROTM, CS_F32C>(s, lds);
+            return occupancy_multi_t<T, MODE_PROT, CS_F32C>(s, lds);
+        }
+    }
+    if (mode == MODE_PROTM) return occupancy_multi_t<T, MODE_PROTM, CS_F64>(s, lds);
+    return occupancy_multi_t<T, MODE_PROT, CS_F64>(s, lds);
+}
+
+#define ABFT_BATCH_MULTI_TU(NAME, T)                                                           \
+    hipError_t launch_batch_##NAME(int mode, int csum, const SweepShape& s, const BatchArgs& b, \
+                                   int nblocks, size_t lds, hipStream_t st)                    \
+    {                                                                                          \
+        return launch_batch_multi_dt<T>(mode, csum, s, b, nblocks, lds, st);                   \
+    }                                                                                          \
+    int batch_occupancy_##NAME(int mode, int csum, const SweepShape& s, size_t lds)            \
+    {                                                                                          \
+        return occupancy_multi_dt<T>(mode, csum, s, lds);                                      \
     }
 
 }  // namespace abft

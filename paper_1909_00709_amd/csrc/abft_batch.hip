@@ -13,6 +13,15 @@ bool batch_shape_supported(int dtype, const SweepShape& s)
 {
     const int vf = dtype == ABFT_F32 ? 4 : 2;
     if (s.nw != kBatchWaves || s.pf != 1) return false;
+    if (s.nchb > 0) {
+        // launches of several chunk counts: radius-1 stars, 16-byte accesses, 16 or 64 lanes,
+        // chunk counts (4, 2, 1), (4, 2), (4, 1), (2, 1)
+        if (s.rad != 1 || s.box || s.vec != vf || (s.lpr != 16 && s.lpr != 64)) return false;
+        if (s.nch == 4)
+            return (s.nchb == 2 && (s.nchc == 1 || s.nchc == 0)) || (s.nchb == 1 && s.nchc == 0);
+        return s.nch == 2 && s.nchb == 1 && s.nchc == 0;
+    }
+    if (s.nchc != 0) return false;
     if (s.vec == vf) return (s.lpr == 16 || s.lpr == 64) && (s.nch == 1 || s.nch == 2 || s.nch == 4);
     return s.vec == 1 && s.lpr == 64 && (s.nch == 4 || s.nch == 16);
 }
@@ -29,6 +38,9 @@ hipError_t launch_sweep_batch(int dtype, int mode, int csum, const SweepShape& s
 {
     if (!batch_shape_supported(dtype, s) || nblocks < 1) return hipErrorInvalidValue;
     const bool f32 = dtype == ABFT_F32;
+    if (s.nchb > 0)
+        return f32 ? launch_batch_r1x_f32(mode, csum, s, b, nblocks, lds, st)
+                   : launch_batch_r1x_f64(mode, csum, s, b, nblocks, lds, st);
     if (s.box)
         return f32 ? launch_batch_box_f32(mode, csum, s, b, nblocks, lds, st)
                    : launch_batch_box_f64(mode, csum, s, b, nblocks, lds, st);
@@ -42,6 +54,9 @@ hipError_t launch_sweep_batch(int dtype, int mode, int csum, const SweepShape& s
 int batch_blocks_per_cu(int dtype, int mode, int csum, const SweepShape& s, size_t lds)
 {
     const bool f32 = dtype == ABFT_F32;
+    if (s.nchb > 0)
+        return f32 ? batch_occupancy_r1x_f32(mode, csum, s, lds)
+                   : batch_occupancy_r1x_f64(mode, csum, s, lds);
     if (s.box)
         return f32 ? batch_occupancy_box_f32(mode, csum, s, lds)
                    : batch_occupancy_box_f64(mode, csum, s, lds);

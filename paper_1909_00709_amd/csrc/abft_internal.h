@@ -229,6 +229,8 @@ struct GridDesc {
     const double* cB;
     const double* cA;
     FlagSlot* slot[2];      // flagged rows of sweeps with t & 1 == index
+    int32_t sub;            // chunk count of this grid's rows in its launch: 0 the launch's
+                            // nch, 1 its nchb, 2 its nchc
 };
 
 struct BatchArgs {
@@ -264,6 +266,10 @@ struct SweepShape {
     int32_t nw = 4;  // wavefronts per block: 4 or 8 (each holds 64 / lpr rows)
     int32_t rad = 1; // stencil radius the kernel is built for: 1 or 2
     int32_t box = 0; // 1: the 27-point box kernel (radius 1, prefetch depth 1)
+    // batched radius-1 sweeps: narrower chunk counts one launch also holds (the rows of the
+    // grids whose descriptor has sub 1 or 2), 0 for none
+    int32_t nchb = 0;
+    int32_t nchc = 0;
 };
 
 bool sweep_shape_supported(int dtype, const SweepShape& s);
@@ -293,6 +299,8 @@ ABFT_BATCH_DECL(r2_f32)
 ABFT_BATCH_DECL(r2_f64)
 ABFT_BATCH_DECL(box_f32)
 ABFT_BATCH_DECL(box_f64)
+ABFT_BATCH_DECL(r1x_f32)  // radius-1 launches holding two or three chunk counts
+ABFT_BATCH_DECL(r1x_f64)
 #undef ABFT_BATCH_DECL
 // Offline, before a rollback recompute (guarded by the window's flag count): the checkpoint's
 // rows against their stored checksums, a changed point placed and restored in place.

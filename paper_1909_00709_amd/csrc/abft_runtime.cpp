@@ -105,6 +105,7 @@ struct abft_ctx {
         double* cB;
         double* cA;
         FlagSlot* slot[2];
+        int sub = 0;  // which chunk count of its launch the rows take (GridDesc::sub)
     };
     std::vector<Grid> grids;
     GridDesc* d_grids = nullptr;
@@ -877,6 +878,11 @@ abft_status batch_layout(abft_ctx* c)
             maxnx = std::max(maxnx, G.nx);
             if (shape_width(K.shape) < G.nx || (K.shape.vec > 1 && G.nx % K.shape.vec))
                 return fail(c, ABFT_E_UNSUPPORTED, "batch class shape does not hold its rows");
+            // the fewest chunks of the launch that hold the rows
+            const int cw = K.shape.lpr * K.shape.vec;
+            G.sub = 0;
+            if (K.shape.nchc > 0 && cw * K.shape.nchc >= G.nx) G.sub = 2;
+            else if (K.shape.nchb > 0 && cw * K.shape.nchb >= G.nx) G.sub = 1;
             for (int t = 0; t < G.ntiles; ++t) {
                 const int yb = t % G.nyb, zb = t / G.nyb;
                 const int64_t rows = std::min(ty, G.ny - yb * ty);
@@ -920,6 +926,7 @@ abft_status batch_layout(abft_ctx* c)
         d.cA = G.cA;
         d.slot[0] = G.slot[0];
         d.slot[1] = G.slot[1];
+        d.sub = G.sub;
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->d_order, order.data(), order.size() * sizeof(int2),
@@ -1009,26 +1016,80 @@ abft_status enqueue_batch(abft_ctx* c, int64_t n, const int64_t* tbase, int64_t 
 
 // Per-size-class autotuning.  The grids are grouped by the narrowest shape that holds their
 // rows (classes in order of row length); every run of consecutive classes is timed as one
-// launch for each shape that holds its longest row, slab depth and dispatch form; the split
-// of the classes into runs whose summed launch times are least is kept.  The all-in-one
-// layout (one launch in the widest shape) is one of the splits tried.
+// launch for each shape that holds its longest row (for radius-1 stars also in a launch where
+// each class's grids take the fewest chunks that hold their rows), slab depth and dispatch
+// form; the split of the classes into runs whose summed launch times are least is kept.  The
+// all-in-one layout (one launch in the widest shape) is one of the splits tried.
 abft_status batch_autotune(abft_ctx* c)
 {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     Counters* scnt = nullptr;  // the timing launches count into scratch, log no events
     abft_status s = dalloc(c, &scnt, sizeof(Counters));
     if (s) return s;
+    // The timing sweeps alternate each grid's two buffers as a run does, so that every sweep
+    // reads what the one before it wrote (the same input swept again and again would stay in
+    // the last-level cache and time faster than a run).  The current grids, checksums and
+    // weighted sums are kept in a backup and restored afterwards; both buffers start from them.
+    const int p0 = (int)(c->t & 1);
+    const size_t es = esize(c->dtype);
+    std::vector<size_t> off;
+    size_t total = 0;
+    for (const auto& G : c->grids) {
+        off.push_back(total);
+        total += ((size_t)G.nx * G.ny * G.nz * es + 255) & ~(size_t)255;
+        total += (size_t)G.ny * G.nz * 8 * (G.W[p0] ? 2 : 1);
+        total = (total + 255) & ~(size_t)255;
+    }
+    unsigned char* backup = nullptr;
+    if ((s = dalloc(c, &backup, total))) return s;
+    auto copy_state = [&](bool save) -> bool {
+        for (size_t g = 0; g < c->grids.size(); ++g) {
+            const auto& G = c->grids[g];
+            const size_t nu = (size_t)G.nx * G.ny * G.nz * es, nb = (size_t)G.ny * G.nz * 8;
+            unsigned char* q = backup + off[g];
+            unsigned char* qb = q + ((nu + 255) & ~(size_t)255);
+            struct {
+                void* live;
+                void* other;
+                unsigned char* keep;
+                size_t n;
+            } parts[3] = {{G.u[p0], G.u[p0 ^ 1], q, nu},
+                          {G.B[p0], G.B[p0 ^ 1], qb, nb},
+                          {G.W[p0], G.W[p0 ^ 1], qb + nb, nb}};
+            for (auto& P : parts) {
+                if (!P.live) continue;
+                if (save) {
+                    if (hipMemcpyAsync(P.keep, P.live, P.n, hipMemcpyDeviceToDevice, c->stream) ||
+                        hipMemcpyAsync(P.other, P.live, P.n, hipMemcpyDeviceToDevice, c->stream))
+                        return false;
+                } else if (hipMemcpyAsync(P.live, P.keep, P.n, hipMemcpyDeviceToDevice,
+                                          c->stream)) {
+                    return false;
+                }
+            }
+        }
+        return hipStreamSynchronize(c->stream) == hipSuccess;
+    };
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool saved = false;
     auto cleanup = [&]() {
+        if (saved) (void)copy_state(false);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
-        auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)scnt);
-        if (it != c->allocs.end()) c->allocs.erase(it);
-        (void)hipFree(scnt);
+        for (void* q : {(void*)scnt, (void*)backup}) {
+            auto it = std::find(c->allocs.begin(), c->allocs.end(), q);
+            if (it != c->allocs.end()) c->allocs.erase(it);
+            (void)hipFree(q);
+        }
     };
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         cleanup();
         return fail(c, ABFT_E_HIP, "hipEventCreate");
+    }
+    if (!(saved = copy_state(true))) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(c, ABFT_E_HIP, "autotune state backup");
     }
     // base classes: (16-byte accesses, narrowest shape) per grid, in order of row length
     std::map<std::pair<int, int>, std::vector<int>> by;
@@ -1048,9 +1109,30 @@ abft_status batch_autotune(abft_ctx* c)
         base_vec.push_back(kv.first.first == 0);
     }
     const int nb = (int)base.size();
+    // each run of classes: the fastest configuration of each of its four fastest launch
+    // shapes, fastest first (one entry per shape, so that the whole-sweep timings below see
+    // different shapes, not one shape's slab depths)
     struct Best {
-        float ms = 1e30f, ms2 = 1e30f;  // the fastest and the runner-up
-        abft_ctx::Class k, k2;
+        std::vector<std::pair<float, abft_ctx::Class>> top;
+        float ms() const { return top.empty() ? 1e30f : top[0].first; }
+        void add(float t, const abft_ctx::Class& k)
+        {
+            auto same = [&](const abft_ctx::Class& o) {
+                return o.shape.lpr == k.shape.lpr && o.shape.nch == k.shape.nch &&
+                       o.shape.vec == k.shape.vec && o.shape.nchb == k.shape.nchb &&
+                       o.shape.nchc == k.shape.nchc;
+            };
+            for (auto& e : top)
+                if (same(e.second)) {
+                    if (t < e.first) e = {t, k};
+                    t = -1.f;
+                    break;
+                }
+            if (t >= 0.f) top.push_back({t, k});
+            std::stable_sort(top.begin(), top.end(),
+                             [](const auto& x, const auto& y) { return x.first < y.first; });
+            if (top.size() > 4) top.resize(4);
+        }
     };
     std::vector<std::vector<Best>> best(nb, std::vector<Best>(nb));
     BatchArgs b = batch_args(c, c->t, nullptr, 0);
@@ -1059,6 +1141,14 @@ abft_status batch_autotune(abft_ctx* c)
     b.cnt = scnt;
     b.ev = nullptr;
     b.ev_cap = 0;
+    // one timing launch; every launch swaps the buffers' roles (see above)
+    int flip = p0;
+    auto launch_timed = [&](const abft_ctx::Class& K, bool first) {
+        BatchArgs bb = b;
+        bb.parity = flip;
+        flip ^= 1;
+        return launch_class(c, K, bb, first);
+    };
     for (int i = 0; i < nb; ++i)
         for (int j = i; j < nb; ++j) {
             abft_ctx::Class K;
@@ -1069,7 +1159,31 @@ abft_status batch_autotune(abft_ctx* c)
                 vo = vo && base_vec[q];
                 for (int g : base[q]) wmax = std::max(wmax, c->grids[g].nx);
             }
-            for (SweepShape sh : batch_shapes_for(c->dtype, vo, wmax))
+            std::vector<SweepShape> shapes = batch_shapes_for(c->dtype, vo, wmax);
+            if (c->shape.rad == 1 && !c->shape.box && vo) {
+                // one launch in which each class's grids take the fewest chunks that hold
+                // their rows
+                const size_t n1 = shapes.size();
+                for (size_t q0 = 0; q0 < n1; ++q0) {
+                    SweepShape sh = shapes[q0];
+                    const int cw = sh.lpr * sh.vec;
+                    std::vector<int> need;
+                    for (int q = i; q <= j; ++q) {
+                        int w = 1;
+                        for (int g : base[q]) w = std::max(w, c->grids[g].nx);
+                        int n = 1;
+                        while (cw * n < w) n *= 2;
+                        if (std::find(need.begin(), need.end(), n) == need.end()) need.push_back(n);
+                    }
+                    std::sort(need.rbegin(), need.rend());
+                    if (need.size() < 2 || need.size() > 3 || need[0] != sh.nch) continue;
+                    sh.nchb = need[1];
+                    sh.nchc = need.size() > 2 ? need[2] : 0;
+                    sh.rad = 1;
+                    if (batch_shape_supported(c->dtype, sh)) shapes.push_back(sh);
+                }
+            }
+            for (SweepShape sh : shapes)
                 for (int tz : {2, 4, 8, 16, 32, 1 << 20})
                     for (int p : {1, 0}) {
                         sh.rad = c->shape.rad;
@@ -1081,12 +1195,12 @@ abft_status batch_autotune(abft_ctx* c)
                         if (batch_layout(c)) continue;  // e.g. tiles beyond the LDS
                         const abft_ctx::Class& L = c->classes[0];
                         float ms = 1e30f;
-                        bool ok = launch_class(c, L, b, true) == hipSuccess &&
-                                  launch_class(c, L, b, true) == hipSuccess;
+                        bool ok = launch_timed(L, true) == hipSuccess &&
+                                  launch_timed(L, true) == hipSuccess;
                         for (int grp = 0; ok && grp < 3; ++grp) {
                             ok = hipEventRecord(e0, c->stream) == hipSuccess;
                             for (int r = 0; ok && r < 5; ++r)
-                                ok = launch_class(c, L, b, true) == hipSuccess;
+                                ok = launch_timed(L, true) == hipSuccess;
                             float gms = 0.f;
                             ok = ok && hipEventRecord(e1, c->stream) == hipSuccess &&
                                  hipEventSynchronize(e1) == hipSuccess &&
@@ -1098,16 +1212,7 @@ abft_status batch_autotune(abft_ctx* c)
                             (void)hipStreamSynchronize(c->stream);
                             continue;
                         }
-                        Best& bb = best[i][j];
-                        if (ms < bb.ms) {
-                            bb.ms2 = bb.ms;
-                            bb.k2 = bb.k;
-                            bb.ms = ms;
-                            bb.k = L;
-                        } else if (ms < bb.ms2) {
-                            bb.ms2 = ms;
-                            bb.k2 = L;
-                        }
+                        best[i][j].add(ms, L);
                     }
         }
     // least summed time over the splits into runs of consecutive classes
@@ -1116,8 +1221,8 @@ abft_status batch_autotune(abft_ctx* c)
     f[0] = 0.f;
     for (int j = 0; j < nb; ++j)
         for (int i = 0; i <= j; ++i)
-            if (f[i] + best[i][j].ms < f[j + 1]) {
-                f[j + 1] = f[i] + best[i][j].ms;
+            if (f[i] + best[i][j].ms() < f[j + 1]) {
+                f[j + 1] = f[i] + best[i][j].ms();
                 from[j + 1] = i;
             }
     std::vector<std::pair<int, int>> runs;
@@ -1130,35 +1235,42 @@ abft_status batch_autotune(abft_ctx* c)
     std::reverse(runs.begin(), runs.end());
     // Launch times of one run alone only approximate a whole sweep (the runs' launches follow
     // one another, and configurations within a few percent trade places between timings): the
-    // split found above, the same split with one run in its runner-up configuration, and the
-    // two best one-launch layouts are timed again as whole sweeps, in alternation, and the
+    // split found above, the same split with one run in its runner-up shape, and the one-launch
+    // layouts of the four best shapes are timed again as whole sweeps, in alternation, and the
     // fastest is kept.
     std::vector<std::vector<abft_ctx::Class>> finalists;
     {
         std::vector<abft_ctx::Class> opt;
-        for (auto& r : runs) opt.push_back(best[r.first][r.second].k);
+        for (auto& r : runs) opt.push_back(best[r.first][r.second].top[0].second);
         finalists.push_back(opt);
         for (size_t q = 0; q < runs.size(); ++q) {
             const Best& bb = best[runs[q].first][runs[q].second];
-            if (bb.ms2 >= 1e29f) continue;
+            if (bb.top.size() < 2) continue;
             std::vector<abft_ctx::Class> alt = opt;
-            alt[q] = bb.k2;
+            alt[q] = bb.top[1].second;
             finalists.push_back(alt);
         }
+        // the one-launch layouts: the best of each of the four fastest shapes
         const Best& all = best[0][nb - 1];
-        if (runs.size() > 1 && all.ms < 1e29f) finalists.push_back({all.k});
-        if (all.ms2 < 1e29f) finalists.push_back({all.k2});
+        for (size_t q = runs.size() > 1 ? 0 : 1; q < all.top.size(); ++q)
+            finalists.push_back({all.top[q].second});
     }
     auto time_sweeps = [&](const std::vector<abft_ctx::Class>& layout, int reps) -> float {
         c->classes = layout;
         if (batch_layout(c)) return -1.f;
-        bool ok = true;
-        for (size_t k = 0; ok && k < c->classes.size(); ++k)
-            ok = launch_class(c, c->classes[k], b, k == 0) == hipSuccess;
+        // a sweep's class launches share its parity
+        auto sweep = [&]() {
+            bool ok = true;
+            const int f = flip;
+            for (size_t k = 0; ok && k < c->classes.size(); ++k) {
+                flip = f;
+                ok = launch_timed(c->classes[k], k == 0) == hipSuccess;
+            }
+            return ok;
+        };
+        bool ok = sweep();
         ok = ok && hipEventRecord(e0, c->stream) == hipSuccess;
-        for (int r = 0; ok && r < reps; ++r)
-            for (size_t k = 0; ok && k < c->classes.size(); ++k)
-                ok = launch_class(c, c->classes[k], b, k == 0) == hipSuccess;
+        for (int r = 0; ok && r < reps; ++r) ok = sweep();
         float ms = 0.f;
         ok = ok && hipEventRecord(e1, c->stream) == hipSuccess &&
              hipEventSynchronize(e1) == hipSuccess &&
@@ -1183,12 +1295,12 @@ abft_status batch_autotune(abft_ctx* c)
     c->classes = finalists[pick];
     s = batch_layout(c);
     if (s) return s;
-    // the timing launches cleared the next sweep's flag slots as a sweep would; clear this
-    // sweep's as well
-    for (auto& G : c->grids) {
-        hipError_t e = launch_fill_u32(&G.slot[c->t & 1]->count, 0u, 2, c->stream);
-        if (e != hipSuccess) return hip_fail(c, e, "reset");
-    }
+    // the timing sweeps used both flag slots of every grid: both start empty again
+    for (auto& G : c->grids)
+        for (int q = 0; q < 2; ++q) {
+            hipError_t e = launch_fill_u32(&G.slot[q]->count, 0u, 2, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "reset");
+        }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return ABFT_OK;
 }
@@ -1625,10 +1737,17 @@ abft_status autotune_impl(abft_ctx* c)
     Counters* scnt = nullptr;
     double* sB = nullptr;
     double* sW = nullptr;
+    double* sB2 = nullptr;
+    double* sW2 = nullptr;
+    void* su = nullptr;
     abft_status s;
     const size_t nrows = (size_t)c->nz * c->ny * (c->tile_x ? c->nx / c->tile_x : 1);
+    const bool offline = c->mode == ABFT_MODE_OFFLINE;
     if ((s = dalloc(c, &sslot, sizeof(FlagSlot))) || (s = dalloc(c, &scnt, sizeof(Counters))) ||
-        (s = dalloc(c, &sB, nrows * 8)) || (s = dalloc(c, &sW, nrows * 8)))
+        (s = dalloc(c, &sB, nrows * 8)) || (s = dalloc(c, &sW, nrows * 8)) ||
+        (s = dalloc(c, &sB2, nrows * 8)) || (s = dalloc(c, &sW2, nrows * 8)))
+        return s;
+    if (!offline && (s = dalloc(c, &su, (size_t)c->nx * c->ny * c->nz * esize(c->dtype))))
         return s;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
@@ -1662,34 +1781,46 @@ abft_status autotune_impl(abft_ctx* c)
     float best_ms = 1e30f;
     const int mode = c->mode != ABFT_MODE_ONLINE ? MODE_PLAIN
                      : (c->tile_x ? MODE_TILE : (c->input_check ? MODE_PROTM : MODE_PROT));
+    // The timing launches form one run, each reading what the one before wrote (the same
+    // input swept again and again would stay in the last-level cache and time faster than a
+    // run does): the first reads the current grid, the rest alternate between two scratch
+    // grids (the other buffer and a scratch allocation; in offline mode the window's two
+    // free buffers), with the checksums alternating in the same way.
+    void* const ua = offline ? c->u[buf_of(c, 1)] : c->u[c->cur ^ 1];
+    void* const ub = offline ? c->u[buf_of(c, 2)] : su;
+    int64_t nt = 0;  // timing launches so far
     // one candidate: `groups` timed groups of `reps` launches, the best group's mean; a
     // negative value when the shape does not launch
     auto time_shape = [&](const SweepShape& sh, int groups, int reps) -> float {
         if (apply_shape(c, sh)) return -1.f;
         SweepArgs a = base_args(c);
-        a.uin = c->u[c->cur];
-        a.uout = c->u[c->cur ^ (c->mode == ABFT_MODE_OFFLINE ? 0 : 1)];
-        if (c->mode == ABFT_MODE_OFFLINE) a.uout = c->u[buf_of(c, 1)];
         a.faults = nullptr;
         a.cnt = scnt;
         a.ev = nullptr;
         a.ev_cap = 0;
         a.slot = sslot;
-        a.Bt = c->mode == ABFT_MODE_OFFLINE ? c->B[c->bck] : c->B[c->bcur];
-        a.Bn = sB;
-        if (mode == MODE_PROTM) a.Wn = sW;
         if (mode == MODE_TILE) a.Et = sW;  // the sweep's tile boundary terms (scratch)
         a.t_off = c->t;
+        // the launch after `nt` others (see `nt`)
+        auto sweep = [&]() {
+            const bool odd = nt & 1;
+            a.uin = nt == 0 ? c->u[c->cur] : (odd ? ua : ub);
+            a.uout = odd ? ub : ua;
+            a.Bt = nt == 0 ? (offline ? c->B[c->bck] : c->B[c->bcur]) : (odd ? sB : sB2);
+            a.Bn = odd ? sB2 : sB;
+            if (mode == MODE_PROTM) a.Wn = odd ? sW2 : sW;
+            ++nt;
+            return launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream);
+        };
         for (int w = 0; w < 2; ++w)
-            if (launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream) != hipSuccess) {
+            if (sweep() != hipSuccess) {
                 (void)hipGetLastError();
                 return -1.f;
             }
         float ms = 1e30f;
         for (int g = 0; g < groups; ++g) {
             if (hipEventRecord(e0, c->stream) != hipSuccess) return -1.f;
-            for (int r = 0; r < reps; ++r)
-                (void)launch_sweep(c->dtype, mode, c->csum, c->shape, a, c->stream);
+            for (int r = 0; r < reps; ++r) (void)sweep();
             float gms = 0.f;
             if (hipEventRecord(e1, c->stream) != hipSuccess ||
                 hipEventSynchronize(e1) != hipSuccess ||
@@ -1724,7 +1855,7 @@ abft_status autotune_impl(abft_ctx* c)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     for (void* p : {static_cast<void*>(sslot), static_cast<void*>(scnt), static_cast<void*>(sB),
-                    static_cast<void*>(sW)}) {
+                    static_cast<void*>(sW), static_cast<void*>(sB2), static_cast<void*>(sW2), su}) {
         auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
         if (it != c->allocs.end()) c->allocs.erase(it);
         (void)hipFree(p);
