@@ -252,7 +252,6 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
         for (int c = 0; c < NCH; ++c)
 #pragma unroll
             for (int v = 0; v < VEC; ++v) acc[2][c][v] = (Acc)cn[c][v];
-        load_c(cn, min(p + 2, z1 - 1));
         const T* prow = buf_of(st) + (r + 1) * stride + VEC;  // row y of plane p in LDS
 
 #pragma unroll
@@ -330,6 +329,8 @@ __device__ __forceinline__ void sweep_box_tile(const SweepArgs& a, const int til
                 }
             }
         }
+
+        load_c(cn, min(p + 2, z1 - 1));  // after the gather, so that it holds no registers there
 
         // output p-1 is complete
         const int z = p - 1;
