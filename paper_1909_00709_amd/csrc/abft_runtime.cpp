@@ -938,7 +938,9 @@ abft_status batch_layout(abft_ctx* c)
     return ABFT_OK;
 }
 
-// One class of all grids in the shape that holds the longest row (the layout before tuning).
+// One launch of all grids in the shape that holds the longest row (the layout before tuning);
+// for radius-1 stars each grid's rows take the fewest chunks of that shape that hold them,
+// where the launch form for those chunk counts exists.
 abft_status batch_single_class(abft_ctx* c, int tz, int persistent)
 {
     bool vec_ok = true;
@@ -950,6 +952,22 @@ abft_status batch_single_class(abft_ctx* c, int tz, int persistent)
     K.shape = sh[0];
     K.shape.rad = c->shape.rad;
     K.shape.box = c->shape.box;
+    if (K.shape.rad == 1 && !K.shape.box && vec_ok) {
+        const int cw = K.shape.lpr * K.shape.vec;
+        std::vector<int> need;
+        for (const auto& G : c->grids) {
+            int n = 1;
+            while (cw * n < G.nx) n *= 2;
+            if (std::find(need.begin(), need.end(), n) == need.end()) need.push_back(n);
+        }
+        std::sort(need.rbegin(), need.rend());
+        SweepShape m = K.shape;
+        if (need.size() >= 2 && need.size() <= 3 && need[0] == m.nch) {
+            m.nchb = need[1];
+            m.nchc = need.size() > 2 ? need[2] : 0;
+            if (batch_shape_supported(c->dtype, m)) K.shape = m;
+        }
+    }
     K.tz = tz;
     K.persistent = persistent;
     c->classes.assign(1, K);
